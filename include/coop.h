@@ -1,0 +1,243 @@
+/*
+ * coop.h -- C ABI of libcoop: cooperative kernels for blocking graph
+ * traversal on MI355X (gfx950).
+ *
+ * The programming model is the paper's "cooperative kernels" (Sorensen,
+ * Evrard, Donaldson, "Cooperative Kernels: GPU Multitasking for Blocking
+ * Algorithms", section 3): a kernel is launched asking for up to N
+ * workgroups; the number M of active workgroups may change at resizing
+ * global barriers, where the scheduler can take workgroups back
+ * (offer_kill) for another task and later give them back (request_fork).
+ * The device-side primitives live in coop_device.hpp; this header is the
+ * host side.
+ *
+ * Conventions
+ *  - Every function returns COOP_OK (0) or a negative COOP_E_* code; no
+ *    exception crosses the ABI.
+ *  - Pointers named d_* are device pointers (HBM). They are owned by the
+ *    caller and must stay valid until the launch has completed
+ *    (coop_wait or a stream synchronisation). The library never frees them.
+ *  - Graphs are CSR over uint32: row_ptr[n+1] (row_ptr[0] = 0,
+ *    non-decreasing), col[arcs] (< n), optional w[arcs]; undirected graphs
+ *    store both arcs of every edge. Self loops and duplicates are allowed
+ *    but the traversals treat them like any other arc.
+ *  - `stream` is a hipStream_t (0 = the null stream). Launches are
+ *    asynchronous on that stream. Handles must be finished with coop_wait,
+ *    or passed as NULL, in which case the library reaps them itself.
+ *  - A runtime may be used from several threads; calls on one coop_rt are
+ *    serialised internally.
+ */
+#ifndef COOP_H
+#define COOP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* coop_stream_t;   /* same type as hipStream_t */
+
+typedef struct coop_rt coop_rt;
+typedef struct coop_graph coop_graph;
+typedef struct coop_handle coop_handle;
+
+/* ------------------------------------------------------------ errors */
+enum {
+    COOP_OK = 0,
+    COOP_E_INVALID = -1,   /* bad argument */
+    COOP_E_OOM = -2,       /* device or host allocation failed */
+    COOP_E_HIP = -3,       /* a HIP call failed; coop_last_hip_error has it */
+    COOP_E_TIMEOUT = -4,   /* barrier watchdog fired (non-residency or deadlock) */
+    COOP_E_BUSY = -5,      /* request can never fit (serving) */
+    COOP_E_OVERFLOW = -6,  /* a distance does not fit in int32 */
+    COOP_E_INTERNAL = -7   /* internal capacity or consistency error */
+};
+
+/* Text for an error code (static storage). */
+const char* coop_strerror(int code);
+
+/* ------------------------------------------------------------ runtime */
+
+typedef struct coop_device_info {
+    int device;
+    uint32_t compute_units;        /* CUs (multiProcessorCount) */
+    uint32_t lds_per_cu;           /* bytes of LDS per CU */
+    uint32_t max_lds_per_group;    /* bytes a workgroup may allocate */
+    uint32_t wall_clock_khz;       /* rate of the device wall clock */
+    uint64_t hbm_bytes;            /* global memory size */
+    char arch[64];                 /* gcnArchName, e.g. "gfx950:sramecc+:xnack-" */
+} coop_device_info;
+
+/* Create a runtime on `device` (HIP ordinal). The runtime owns its streams,
+ * scratch buffers and pinned control words. */
+int coop_init(int device, coop_rt** out);
+/* Wait for everything the runtime launched, then free it. */
+int coop_shutdown(coop_rt* rt);
+int coop_device_query(coop_rt* rt, coop_device_info* out);
+/* The HIP error behind the last COOP_E_HIP on this runtime (0 if none). */
+int coop_last_hip_error(coop_rt* rt);
+
+/* ------------------------------------------------------------- graphs */
+
+/* Wrap caller-owned device CSR arrays (no copy). d_w may be NULL (no
+ * weights; SSSP then fails with COOP_E_INVALID). The runtime reads row_ptr
+ * once (device to host copy) to size its work queues. */
+int coop_graph_wrap(coop_rt* rt, const uint32_t* d_row_ptr, const uint32_t* d_col,
+                    const uint32_t* d_w, uint32_t n, uint64_t arcs, coop_graph** out);
+int coop_graph_release(coop_graph* g);
+
+/* ----------------------------------------------------------- launches */
+
+enum { COOP_MODE_PLAIN = 0, COOP_MODE_COOP = 1 };
+
+enum {
+    COOP_F_PARK_KILLED = 1u,      /* killed workgroups queue again as joiners (test mode) */
+    COOP_F_RANDOM_SCHEDULE = 2u,  /* seeded device-side kill/fork schedule */
+    COOP_F_HOST_SCHEDULE = 4u     /* barrier reads the host-written target (coop_set_target) */
+};
+
+typedef struct coop_launch_opts {
+    uint32_t mode;            /* COOP_MODE_PLAIN (fixed M = grid, all resident) or COOP_MODE_COOP */
+    uint32_t num_groups;      /* N requested; 0 = one per compute unit x residency */
+    uint32_t group_size;      /* threads per workgroup: multiple of 64, <= 1024; 0 = 1024 */
+    uint32_t lds_bytes;       /* LDS per workgroup; 0 = 96 KiB (one workgroup per CU) */
+    uint32_t flags;           /* COOP_F_* */
+    uint32_t heavy_threshold; /* degree above which a vertex is split into strips; 0 = 128 */
+    uint32_t strip;           /* arcs per strip; 0 = 4096 */
+    uint32_t startup_wait_ns; /* how long workgroup 0 waits for the grid to register; 0 = 20 us */
+    uint64_t sched_seed;      /* COOP_F_RANDOM_SCHEDULE: seed */
+    double sched_p;           /* COOP_F_RANDOM_SCHEDULE: P(target changes) per barrier */
+    uint64_t watchdog_ns;     /* spin bound of every barrier wait; 0 = 10 s */
+} coop_launch_opts;
+
+/* Fill `o` with the defaults (plain mode). */
+void coop_launch_opts_default(coop_launch_opts* o);
+
+typedef struct coop_stats {
+    int32_t error;            /* COOP_OK or the kernel's COOP_E_* */
+    uint32_t barriers;        /* global barriers executed */
+    uint32_t kills;           /* workgroups claimed by the scheduler */
+    uint32_t forks;           /* workgroups admitted at barriers */
+    uint32_t resizes;         /* barriers at which M changed */
+    uint32_t min_groups;      /* smallest M after a barrier */
+    uint32_t max_groups;      /* largest M after a barrier */
+    uint32_t final_groups;    /* M at the last barrier */
+    uint32_t grid;            /* workgroups launched (N) */
+    uint32_t levels;          /* BFS levels / SSSP or colouring rounds, over all sources */
+    double kernel_ms;         /* persistent kernel time (HIP events) */
+    double device_ms;         /* first barrier to end (device wall clock) */
+} coop_stats;
+
+/* BFS (the cooperative graph-traversal kernel of the paper's programming
+ * section): level of every vertex from each source, one source after
+ * another inside one persistent launch. d_roots holds nroots source
+ * vertices (device memory). d_level receives, for source r, n levels at
+ * d_level + r * out_stride (out_stride = 0: every source overwrites the same
+ * n entries). Unreached vertices get 0xFFFFFFFF. */
+int coop_bfs(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_t nroots,
+             uint32_t* d_level, uint64_t out_stride, const coop_launch_opts* opts,
+             coop_stream_t stream, coop_handle** out);
+
+/* SSSP by frontier Bellman-Ford (relaxations with atomicMin; a vertex whose
+ * distance dropped is queued once for the next round). Distances int32;
+ * unreached INT32_MAX; a distance >= INT32_MAX fails with COOP_E_OVERFLOW.
+ * Weights are uint32 and must be present in the graph. */
+int coop_sssp(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_t nroots,
+              int32_t* d_dist, uint64_t out_stride, const coop_launch_opts* opts,
+              coop_stream_t stream, coop_handle** out);
+
+/* Greedy colouring in priority order (Jones-Plassmann rounds over the
+ * priority DAG): vertex v gets the smallest colour unused by its
+ * higher-priority neighbours, priority key (h(v), v) with h(v) output v of
+ * SplitMix64 seeded with prio_seed, higher first. d_colour: n uint32. */
+int coop_color(coop_rt* rt, const coop_graph* g, uint64_t prio_seed, uint32_t* d_colour,
+               const coop_launch_opts* opts, coop_stream_t stream, coop_handle** out);
+
+/* Greedy maximal independent set in the same priority order: v is in the set
+ * iff no higher-priority neighbour is. d_in_set: n bytes (0/1). */
+int coop_mis(coop_rt* rt, const coop_graph* g, uint64_t prio_seed, uint8_t* d_in_set,
+             const coop_launch_opts* opts, coop_stream_t stream, coop_handle** out);
+
+/* Generic launch by kernel id with a parameter block (immutable, copied). */
+enum { COOP_KERNEL_BFS = 1, COOP_KERNEL_SSSP = 2, COOP_KERNEL_COLOR = 3, COOP_KERNEL_MIS = 4,
+       COOP_KERNEL_BARRIER = 5 };
+typedef struct coop_params {
+    const coop_graph* graph;
+    const uint32_t* d_roots;
+    uint32_t nroots;
+    uint64_t out_stride;
+    uint64_t prio_seed;
+    uint32_t barrier_iters;   /* COOP_KERNEL_BARRIER: barriers to run */
+    void* d_out;              /* levels / distances / colours / set flags */
+} coop_params;
+int coop_launch(coop_rt* rt, int kernel_id, const coop_params* params, const coop_launch_opts* opts,
+                coop_stream_t stream, coop_handle** out);
+
+/* Wait for a launch, fill `stats` (nullable), free the handle. Returns the
+ * kernel's error code (COOP_OK, COOP_E_TIMEOUT, COOP_E_OVERFLOW, ...). */
+int coop_wait(coop_handle* h, coop_stats* stats);
+
+/* ---------------------------------------------------------- scheduler */
+
+/* Number of workgroups launched for this handle (N). */
+uint32_t coop_handle_groups(const coop_handle* h);
+
+/* Scheduler target for a COOP_F_HOST_SCHEDULE launch: at its next resizing
+ * barrier the kernel keeps min(max(1, target), N) workgroups (the paper's
+ * `query`): surplus workgroups leave (their CUs become free), and waiting
+ * joiners are admitted while M < target. Non-blocking host store. */
+int coop_set_target(coop_handle* h, uint32_t target);
+
+/* Give workgroups back: launch `count` joiner workgroups for this handle on
+ * the runtime's joiner stream (they register and are admitted at the next
+ * barrier, as forks). Usually preceded by coop_set_target(h, N). */
+int coop_fork_groups(coop_handle* h, uint32_t count);
+
+/* ----------------------------------------------------------- co-tasks */
+
+typedef struct coop_cotask_cfg {
+    uint32_t groups;          /* workgroups the co-task needs (one per CU) */
+    uint32_t lds_bytes;       /* LDS per co-task workgroup; 0 = 96 KiB */
+    uint64_t busy_ns;         /* how long each workgroup holds its CU */
+    uint64_t period_ns;       /* injector: one co-task per period */
+    uint32_t max_tasks;       /* injector: stop after this many (0 = until stopped) */
+} coop_cotask_cfg;
+
+typedef struct coop_cotask_stats {
+    uint32_t count;           /* co-tasks completed */
+    double latency_p50_ms;    /* request -> co-task end (host clock) */
+    double latency_p99_ms;
+    double latency_max_ms;
+    double gather_p50_ms;     /* request -> all co-task workgroups running */
+    double gather_p99_ms;
+    double gather_max_ms;
+    double busy_mean_ms;      /* co-task run time on the device */
+} coop_cotask_stats;
+
+/* Run one co-task now on `stream` and wait for it (blocking). latency_ms /
+ * gather_ms (nullable) get request->end and request->all-running times. */
+int coop_cotask_run(coop_rt* rt, const coop_cotask_cfg* cfg, coop_stream_t stream,
+                    double* latency_ms, double* gather_ms);
+
+/* Start a host thread that, every period, asks the cooperative launch `h`
+ * for cfg->groups workgroups (target = N - groups), runs the co-task on the
+ * runtime's co-task stream, then restores the target and forks the
+ * workgroups back. h may be NULL (co-tasks only). One injector per runtime. */
+int coop_injector_start(coop_rt* rt, coop_handle* h, const coop_cotask_cfg* cfg);
+/* Stop the injector thread and return its statistics. */
+int coop_injector_stop(coop_rt* rt, coop_cotask_stats* out);
+
+/* ------------------------------------------------------ measurements */
+
+/* Global-barrier latency: a persistent launch that does `iters` barriers
+ * and nothing else. ns_per_barrier from the device wall clock. */
+int coop_barrier_bench(coop_rt* rt, const coop_launch_opts* opts, uint32_t iters,
+                       coop_stream_t stream, double* ns_per_barrier, coop_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COOP_H */

@@ -1,0 +1,408 @@
+"""Python binding of libcoop (include/coop.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of ``libcoop.so``. There is no
+fallback: if the library is missing, loading raises ``CoopLibraryMissing``.
+Device buffers are torch tensors on the GPU (``data_ptr()``), streams are
+``torch.cuda.Stream`` objects or raw ``hipStream_t`` integers.
+
+The functions keep the C names (``coop_init``, ``coop_bfs``, ...). A small
+``Runtime`` class bundles a runtime with tensor allocation for convenience.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+from . import build as _build
+
+COOP_OK = 0
+COOP_E_INVALID = -1
+COOP_E_OOM = -2
+COOP_E_HIP = -3
+COOP_E_TIMEOUT = -4
+COOP_E_BUSY = -5
+COOP_E_OVERFLOW = -6
+COOP_E_INTERNAL = -7
+
+COOP_MODE_PLAIN = 0
+COOP_MODE_COOP = 1
+COOP_F_PARK_KILLED = 1
+COOP_F_RANDOM_SCHEDULE = 2
+COOP_F_HOST_SCHEDULE = 4
+
+COOP_KERNEL_BFS = 1
+COOP_KERNEL_SSSP = 2
+COOP_KERNEL_COLOR = 3
+COOP_KERNEL_MIS = 4
+COOP_KERNEL_BARRIER = 5
+
+UNREACHED_LEVEL = 0xFFFFFFFF
+UNREACHED_DIST = 0x7FFFFFFF
+
+# every symbol include/coop.h declares (checked by the ABI test)
+EXPORTS = [
+    "coop_strerror", "coop_launch_opts_default", "coop_init", "coop_shutdown", "coop_device_query",
+    "coop_last_hip_error", "coop_graph_wrap", "coop_graph_release", "coop_bfs", "coop_sssp",
+    "coop_color", "coop_mis", "coop_launch", "coop_wait", "coop_handle_groups", "coop_set_target",
+    "coop_fork_groups", "coop_cotask_run", "coop_injector_start", "coop_injector_stop",
+    "coop_barrier_bench",
+]
+
+
+class CoopLibraryMissing(RuntimeError):
+    pass
+
+
+class CoopError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = _lib.coop_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{where}: {msg} ({code})")
+
+
+class coop_launch_opts(ctypes.Structure):
+    _fields_ = [
+        ("mode", ctypes.c_uint32), ("num_groups", ctypes.c_uint32), ("group_size", ctypes.c_uint32),
+        ("lds_bytes", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("heavy_threshold", ctypes.c_uint32),
+        ("strip", ctypes.c_uint32), ("startup_wait_ns", ctypes.c_uint32), ("sched_seed", ctypes.c_uint64),
+        ("sched_p", ctypes.c_double), ("watchdog_ns", ctypes.c_uint64),
+    ]
+
+
+class coop_stats(ctypes.Structure):
+    _fields_ = [
+        ("error", ctypes.c_int32), ("barriers", ctypes.c_uint32), ("kills", ctypes.c_uint32),
+        ("forks", ctypes.c_uint32), ("resizes", ctypes.c_uint32), ("min_groups", ctypes.c_uint32),
+        ("max_groups", ctypes.c_uint32), ("final_groups", ctypes.c_uint32), ("grid", ctypes.c_uint32),
+        ("levels", ctypes.c_uint32), ("kernel_ms", ctypes.c_double), ("device_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class coop_device_info(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int), ("compute_units", ctypes.c_uint32), ("lds_per_cu", ctypes.c_uint32),
+        ("max_lds_per_group", ctypes.c_uint32), ("wall_clock_khz", ctypes.c_uint32),
+        ("hbm_bytes", ctypes.c_uint64), ("arch", ctypes.c_char * 64),
+    ]
+
+
+class coop_params(ctypes.Structure):
+    _fields_ = [
+        ("graph", ctypes.c_void_p), ("d_roots", ctypes.c_void_p), ("nroots", ctypes.c_uint32),
+        ("out_stride", ctypes.c_uint64), ("prio_seed", ctypes.c_uint64), ("barrier_iters", ctypes.c_uint32),
+        ("d_out", ctypes.c_void_p),
+    ]
+
+
+class coop_cotask_cfg(ctypes.Structure):
+    _fields_ = [
+        ("groups", ctypes.c_uint32), ("lds_bytes", ctypes.c_uint32), ("busy_ns", ctypes.c_uint64),
+        ("period_ns", ctypes.c_uint64), ("max_tasks", ctypes.c_uint32),
+    ]
+
+
+class coop_cotask_stats(ctypes.Structure):
+    _fields_ = [
+        ("count", ctypes.c_uint32), ("latency_p50_ms", ctypes.c_double), ("latency_p99_ms", ctypes.c_double),
+        ("latency_max_ms", ctypes.c_double), ("gather_p50_ms", ctypes.c_double),
+        ("gather_p99_ms", ctypes.c_double), ("gather_max_ms", ctypes.c_double),
+        ("busy_mean_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+VP = ctypes.c_void_p
+VPP = ctypes.POINTER(ctypes.c_void_p)
+
+
+def library_path() -> str:
+    return _build.COOP_SO
+
+
+def load_library():
+    """Load libcoop.so (build it first with __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise CoopLibraryMissing(f"{path} not found: build the HIP library first")
+    lib = ctypes.CDLL(path)
+    i32, u32, u64 = ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64
+    sig = {
+        "coop_strerror": (ctypes.c_char_p, [i32]),
+        "coop_launch_opts_default": (None, [ctypes.POINTER(coop_launch_opts)]),
+        "coop_init": (i32, [i32, VPP]),
+        "coop_shutdown": (i32, [VP]),
+        "coop_device_query": (i32, [VP, ctypes.POINTER(coop_device_info)]),
+        "coop_last_hip_error": (i32, [VP]),
+        "coop_graph_wrap": (i32, [VP, VP, VP, VP, u32, u64, VPP]),
+        "coop_graph_release": (i32, [VP]),
+        "coop_bfs": (i32, [VP, VP, VP, u32, VP, u64, ctypes.POINTER(coop_launch_opts), VP, VPP]),
+        "coop_sssp": (i32, [VP, VP, VP, u32, VP, u64, ctypes.POINTER(coop_launch_opts), VP, VPP]),
+        "coop_color": (i32, [VP, VP, u64, VP, ctypes.POINTER(coop_launch_opts), VP, VPP]),
+        "coop_mis": (i32, [VP, VP, u64, VP, ctypes.POINTER(coop_launch_opts), VP, VPP]),
+        "coop_launch": (i32, [VP, i32, ctypes.POINTER(coop_params), ctypes.POINTER(coop_launch_opts), VP, VPP]),
+        "coop_wait": (i32, [VP, ctypes.POINTER(coop_stats)]),
+        "coop_handle_groups": (u32, [VP]),
+        "coop_set_target": (i32, [VP, u32]),
+        "coop_fork_groups": (i32, [VP, u32]),
+        "coop_cotask_run": (i32, [VP, ctypes.POINTER(coop_cotask_cfg), VP,
+                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+        "coop_injector_start": (i32, [VP, VP, ctypes.POINTER(coop_cotask_cfg)]),
+        "coop_injector_stop": (i32, [VP, ctypes.POINTER(coop_cotask_stats)]),
+        "coop_barrier_bench": (i32, [VP, ctypes.POINTER(coop_launch_opts), u32, VP,
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(coop_stats)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, where: str) -> int:
+    if rc != COOP_OK:
+        raise CoopError(rc, where)
+    return rc
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(s) -> Optional[int]:
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def make_opts(mode: int = COOP_MODE_PLAIN, **kw) -> coop_launch_opts:
+    o = coop_launch_opts()
+    load_library().coop_launch_opts_default(ctypes.byref(o))
+    o.mode = mode
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+# ----------------------------------------------------------- C-named calls
+
+def coop_strerror(code: int) -> str:
+    return load_library().coop_strerror(code).decode()
+
+
+def coop_init(device: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(load_library().coop_init(device, ctypes.byref(h)), "coop_init")
+    return h.value
+
+
+def coop_shutdown(rt: int) -> None:
+    _check(load_library().coop_shutdown(rt), "coop_shutdown")
+
+
+def coop_device_query(rt: int) -> dict:
+    info = coop_device_info()
+    _check(load_library().coop_device_query(rt, ctypes.byref(info)), "coop_device_query")
+    d = {k: getattr(info, k) for k, _ in info._fields_}
+    d["arch"] = info.arch.decode()
+    return d
+
+
+def coop_graph_wrap(rt: int, row_ptr, col, w, n: int, arcs: int) -> int:
+    g = ctypes.c_void_p()
+    _check(load_library().coop_graph_wrap(rt, _ptr(row_ptr), _ptr(col), _ptr(w), n, arcs, ctypes.byref(g)),
+           "coop_graph_wrap")
+    return g.value
+
+
+def coop_graph_release(g: int) -> None:
+    _check(load_library().coop_graph_release(g), "coop_graph_release")
+
+
+def _handle_out(keep: bool):
+    return ctypes.c_void_p() if keep else None
+
+
+def coop_bfs(rt, g, roots, nroots, level, out_stride=0, opts=None, stream=None, keep=True):
+    h = _handle_out(keep)
+    rc = load_library().coop_bfs(rt, g, _ptr(roots), nroots, _ptr(level), out_stride,
+                                 ctypes.byref(opts) if opts is not None else None, _stream(stream),
+                                 ctypes.byref(h) if keep else None)
+    _check(rc, "coop_bfs")
+    return h.value if keep else None
+
+
+def coop_sssp(rt, g, roots, nroots, dist, out_stride=0, opts=None, stream=None, keep=True):
+    h = _handle_out(keep)
+    rc = load_library().coop_sssp(rt, g, _ptr(roots), nroots, _ptr(dist), out_stride,
+                                  ctypes.byref(opts) if opts is not None else None, _stream(stream),
+                                  ctypes.byref(h) if keep else None)
+    _check(rc, "coop_sssp")
+    return h.value if keep else None
+
+
+def coop_color(rt, g, prio_seed, colour, opts=None, stream=None, keep=True):
+    h = _handle_out(keep)
+    rc = load_library().coop_color(rt, g, prio_seed & (2**64 - 1), _ptr(colour),
+                                   ctypes.byref(opts) if opts is not None else None, _stream(stream),
+                                   ctypes.byref(h) if keep else None)
+    _check(rc, "coop_color")
+    return h.value if keep else None
+
+
+def coop_mis(rt, g, prio_seed, in_set, opts=None, stream=None, keep=True):
+    h = _handle_out(keep)
+    rc = load_library().coop_mis(rt, g, prio_seed & (2**64 - 1), _ptr(in_set),
+                                 ctypes.byref(opts) if opts is not None else None, _stream(stream),
+                                 ctypes.byref(h) if keep else None)
+    _check(rc, "coop_mis")
+    return h.value if keep else None
+
+
+def coop_launch(rt, kernel_id, params: coop_params, opts=None, stream=None, keep=True):
+    h = _handle_out(keep)
+    rc = load_library().coop_launch(rt, kernel_id, ctypes.byref(params),
+                                    ctypes.byref(opts) if opts is not None else None, _stream(stream),
+                                    ctypes.byref(h) if keep else None)
+    _check(rc, "coop_launch")
+    return h.value if keep else None
+
+
+def coop_wait(h: int) -> tuple[int, dict]:
+    """Returns (rc, stats). rc is the kernel's own code; it is not raised."""
+    st = coop_stats()
+    rc = load_library().coop_wait(h, ctypes.byref(st))
+    return rc, st.as_dict()
+
+
+def coop_handle_groups(h: int) -> int:
+    return int(load_library().coop_handle_groups(h))
+
+
+def coop_set_target(h: int, target: int) -> None:
+    _check(load_library().coop_set_target(h, target), "coop_set_target")
+
+
+def coop_fork_groups(h: int, count: int) -> None:
+    _check(load_library().coop_fork_groups(h, count), "coop_fork_groups")
+
+
+def coop_cotask_run(rt, groups, busy_ns, lds_bytes=0, stream=None) -> tuple[float, float]:
+    cfg = coop_cotask_cfg(groups=groups, lds_bytes=lds_bytes, busy_ns=busy_ns, period_ns=0, max_tasks=0)
+    lat, gat = ctypes.c_double(), ctypes.c_double()
+    _check(load_library().coop_cotask_run(rt, ctypes.byref(cfg), _stream(stream), ctypes.byref(lat),
+                                          ctypes.byref(gat)), "coop_cotask_run")
+    return lat.value, gat.value
+
+
+def coop_injector_start(rt, h, groups, busy_ns, period_ns, max_tasks=0, lds_bytes=0) -> None:
+    cfg = coop_cotask_cfg(groups=groups, lds_bytes=lds_bytes, busy_ns=busy_ns, period_ns=period_ns,
+                          max_tasks=max_tasks)
+    _check(load_library().coop_injector_start(rt, h, ctypes.byref(cfg)), "coop_injector_start")
+
+
+def coop_injector_stop(rt) -> tuple[int, dict]:
+    st = coop_cotask_stats()
+    rc = load_library().coop_injector_stop(rt, ctypes.byref(st))
+    return rc, st.as_dict()
+
+
+def coop_barrier_bench(rt, iters, opts=None, stream=None) -> tuple[float, dict]:
+    ns = ctypes.c_double()
+    st = coop_stats()
+    _check(load_library().coop_barrier_bench(rt, ctypes.byref(opts) if opts is not None else None, iters,
+                                             _stream(stream), ctypes.byref(ns), ctypes.byref(st)),
+           "coop_barrier_bench")
+    return ns.value, st.as_dict()
+
+
+# ------------------------------------------------------------- convenience
+
+class DeviceGraph:
+    """A graph resident in HBM (torch tensors) wrapped for libcoop."""
+
+    def __init__(self, rt: "Runtime", g, device="cuda"):
+        import torch
+        self.rt = rt
+        self.n = g.n
+        self.arcs = g.arcs
+        self.row_ptr = torch.from_numpy(g.row_ptr.view("int32")).to(device)
+        self.col = torch.from_numpy(g.col.view("int32")).to(device) if g.arcs else \
+            torch.zeros(1, dtype=torch.int32, device=device)
+        self.w = torch.from_numpy(g.w.view("int32")).to(device) if g.w is not None and g.arcs else None
+        self.handle = coop_graph_wrap(rt.rt, self.row_ptr, self.col, self.w, g.n, g.arcs)
+
+    def release(self):
+        if self.handle:
+            coop_graph_release(self.handle)
+            self.handle = None
+
+
+class Runtime:
+    def __init__(self, device: int = 0):
+        self.rt = coop_init(device)
+        self.info = coop_device_query(self.rt)
+
+    def close(self):
+        if self.rt:
+            coop_shutdown(self.rt)
+            self.rt = None
+
+    def graph(self, g) -> DeviceGraph:
+        return DeviceGraph(self, g)
+
+    def _roots(self, roots):
+        import numpy as np
+        import torch
+        r = np.ascontiguousarray(np.asarray(roots, dtype=np.uint32).reshape(-1))
+        return torch.from_numpy(r.view("int32")).cuda()
+
+    def bfs(self, dg: DeviceGraph, roots, opts=None, stream=None, out=None):
+        import torch
+        rt = self._roots(roots)
+        k = rt.numel()
+        if out is None:
+            out = torch.empty(k * dg.n, dtype=torch.int32, device="cuda")
+        h = coop_bfs(self.rt, dg.handle, rt, k, out, dg.n if k > 1 else 0, opts, stream)
+        rc, st = coop_wait(h)
+        return rc, out.view(k, dg.n) if k > 1 else out, st
+
+    def sssp(self, dg: DeviceGraph, roots, opts=None, stream=None, out=None):
+        import torch
+        rt = self._roots(roots)
+        k = rt.numel()
+        if out is None:
+            out = torch.empty(k * dg.n, dtype=torch.int32, device="cuda")
+        h = coop_sssp(self.rt, dg.handle, rt, k, out, dg.n if k > 1 else 0, opts, stream)
+        rc, st = coop_wait(h)
+        return rc, out.view(k, dg.n) if k > 1 else out, st
+
+    def color(self, dg: DeviceGraph, prio_seed: int, opts=None, stream=None):
+        import torch
+        out = torch.empty(dg.n, dtype=torch.int32, device="cuda")
+        h = coop_color(self.rt, dg.handle, prio_seed, out, opts, stream)
+        rc, st = coop_wait(h)
+        return rc, out, st
+
+    def mis(self, dg: DeviceGraph, prio_seed: int, opts=None, stream=None):
+        import torch
+        out = torch.empty(dg.n, dtype=torch.uint8, device="cuda")
+        h = coop_mis(self.rt, dg.handle, prio_seed, out, opts, stream)
+        rc, st = coop_wait(h)
+        return rc, out, st

@@ -1,0 +1,240 @@
+"""GPU parity: every HIP path against the CPU oracle, element by element.
+
+All results are integers with a unique correct value, so the bar is bit
+equality, under plain launches, cooperative launches, and cooperative
+launches under seeded kill/fork schedules (any schedule must give the
+never-resizing schedule's result)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.conftest import gpu_available
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rt():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    from paper_1707_01989_amd import coop
+    r = coop.Runtime(0)
+    say(f"device: {r.info}")
+    yield r
+    r.close()
+
+
+@pytest.fixture(scope="module")
+def coop_mod():
+    from paper_1707_01989_amd import coop
+    return coop
+
+
+def as_u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def modes(coop):
+    return {
+        "plain": coop.make_opts(coop.COOP_MODE_PLAIN),
+        "coop": coop.make_opts(coop.COOP_MODE_COOP),
+        "coop_host": coop.make_opts(coop.COOP_MODE_COOP, flags=coop.COOP_F_HOST_SCHEDULE),
+    }
+
+
+# ------------------------------------------------------------------ BFS
+
+@pytest.mark.parametrize("mode", ["plain", "coop", "coop_host"])
+def test_bfs_er4096(rt, coop_mod, gg, mode):
+    g = gg.er(4096, 8, 1)
+    say(f"bfs er4096 mode={mode}")
+    dg = rt.graph(g)
+    rc, lv, st = rt.bfs(dg, [0], modes(coop_mod)[mode])
+    assert rc == 0, coop_mod.coop_strerror(rc)
+    assert np.array_equal(as_u32(lv), oracle.bfs(g, 0))
+    assert st["kills"] == 0
+    dg.release()
+
+
+@pytest.mark.parametrize("name", ["path", "star_leaf", "disjoint", "isolated", "cycle", "grid", "tree"])
+def test_bfs_small_graphs(rt, coop_mod, gg, name):
+    g, src = {
+        "path": (gg.path(300), 7),
+        "star_leaf": (gg.star(200), 5),
+        "disjoint": (gg.disjoint_union(gg.cycle(50), gg.path(40)), 60),
+        "isolated": (gg.disjoint_union(gg.empty(3), gg.path(5)), 1),
+        "cycle": (gg.cycle(1001), 0),
+        "grid": (gg.grid(17, 23), 40),
+        "tree": (gg.binary_tree(2047), 0),
+    }[name]
+    say(f"bfs small {name}")
+    dg = rt.graph(g)
+    exp = oracle.bfs(g, src)
+    for mode, o in modes(coop_mod).items():
+        rc, lv, _ = rt.bfs(dg, [src], o)
+        assert rc == 0, (mode, coop_mod.coop_strerror(rc))
+        assert np.array_equal(as_u32(lv), exp), mode
+    dg.release()
+
+
+@pytest.mark.parametrize("th,strip", [(128, 4096), (16, 64), (4, 8)])
+def test_bfs_rmat_heavy_strips(rt, coop_mod, gg, th, strip):
+    g = gg.rmat(14, 16, seed=3)
+    src = int(gg.sources(g, 1, 1)[0])
+    say(f"bfs rmat14 heavy_th={th} strip={strip}")
+    dg = rt.graph(g)
+    exp = oracle.bfs(g, src)
+    for mode in ("plain", "coop"):
+        o = modes(coop_mod)[mode]
+        o.heavy_threshold = th
+        o.strip = strip
+        rc, lv, st = rt.bfs(dg, [src], o)
+        assert rc == 0, coop_mod.coop_strerror(rc)
+        assert np.array_equal(as_u32(lv), exp), mode
+    dg.release()
+
+
+def test_bfs_multi_root(rt, coop_mod, gg):
+    g = gg.rmat(13, 16, seed=5)
+    roots = gg.sources(g, 2, 6)
+    say(f"bfs multi-root rmat13 roots={roots.tolist()}")
+    dg = rt.graph(g)
+    for mode in ("plain", "coop"):
+        rc, lv, st = rt.bfs(dg, roots, modes(coop_mod)[mode])
+        assert rc == 0
+        got = lv.cpu().numpy().view(np.uint32)
+        for i, r in enumerate(roots):
+            assert np.array_equal(got[i], oracle.bfs(g, int(r))), (mode, i)
+    dg.release()
+
+
+def test_bfs_small_groups(rt, coop_mod, gg):
+    """Few and narrow workgroups: many claims per workgroup, ragged tails."""
+    g = gg.er(20000, 6, 9)
+    say("bfs er20000 narrow launches")
+    dg = rt.graph(g)
+    exp = oracle.bfs(g, 3)
+    for mode in ("plain", "coop"):
+        for ng, gs in ((1, 64), (3, 128), (7, 256), (40, 1024)):
+            o = modes(coop_mod)[mode]
+            o.num_groups = ng
+            o.group_size = gs
+            rc, lv, st = rt.bfs(dg, [3], o)
+            assert rc == 0, (mode, ng, gs, coop_mod.coop_strerror(rc))
+            assert np.array_equal(as_u32(lv), exp), (mode, ng, gs)
+    dg.release()
+
+
+# ----------------------------------------------------------------- SSSP
+
+@pytest.mark.parametrize("name", ["grid64", "er5000", "rmat12"])
+def test_sssp(rt, coop_mod, gg, name):
+    g = {"grid64": lambda: gg.add_weights(gg.grid(64, 64), 2, 1, 1000),
+         "er5000": lambda: gg.add_weights(gg.er(5000, 6, 4), 4, 1, 1000),
+         "rmat12": lambda: gg.add_weights(gg.rmat(12, 16, seed=4), 4, 1, 255)}[name]()
+    src = int(gg.sources(g, 6, 1)[0])
+    say(f"sssp {name} src={src}")
+    dg = rt.graph(g)
+    exp = oracle.sssp(g, src)
+    for mode, o in modes(coop_mod).items():
+        o.heavy_threshold = 32
+        o.strip = 128
+        rc, d, st = rt.sssp(dg, [src], o)
+        assert rc == 0, (mode, coop_mod.coop_strerror(rc))
+        assert np.array_equal(d.cpu().numpy(), exp), mode
+    dg.release()
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_sssp_random_schedule_park(rt, coop_mod, gg, seed):
+    """Seeded kill/fork schedule (target redrawn at a quarter of the
+    barriers); killed workgroups queue again as joiners."""
+    g = gg.add_weights(gg.grid(96, 96), 2, 1, 1000)
+    say(f"sssp grid96 random schedule seed={seed}")
+    dg = rt.graph(g)
+    exp = oracle.sssp(g, 0)
+    o = coop_mod.make_opts(coop_mod.COOP_MODE_COOP,
+                           flags=coop_mod.COOP_F_RANDOM_SCHEDULE | coop_mod.COOP_F_PARK_KILLED,
+                           sched_seed=seed, sched_p=0.25, num_groups=32, group_size=256)
+    rc, d, st = rt.sssp(dg, [0], o)
+    assert rc == 0, coop_mod.coop_strerror(rc)
+    assert np.array_equal(d.cpu().numpy(), exp)
+    assert st["kills"] > 0 and st["forks"] > 0 and st["resizes"] > 0
+    say(f"  rounds={st['levels']} kills={st['kills']} forks={st['forks']} M in [{st['min_groups']},{st['max_groups']}]")
+    dg.release()
+
+
+def test_bfs_random_schedule_with_joiner_grid(rt, coop_mod, gg):
+    """Killed workgroups really exit; a separately launched joiner grid
+    supplies the forks."""
+    g = gg.grid(128, 128)
+    say("bfs grid128 random schedule with joiner grid")
+    dg = rt.graph(g)
+    exp = oracle.bfs(g, 0)
+    import torch
+    roots = rt._roots([0])
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    o = coop_mod.make_opts(coop_mod.COOP_MODE_COOP, flags=coop_mod.COOP_F_RANDOM_SCHEDULE,
+                           sched_seed=11, sched_p=0.3, num_groups=24, group_size=256)
+    h = coop_mod.coop_bfs(rt.rt, dg.handle, roots, 1, out, 0, o)
+    coop_mod.coop_fork_groups(h, 600)
+    rc, st = coop_mod.coop_wait(h)
+    assert rc == 0, coop_mod.coop_strerror(rc)
+    assert np.array_equal(as_u32(out), exp)
+    say(f"  kills={st['kills']} forks={st['forks']}")
+    assert st["kills"] > 0
+    dg.release()
+
+
+# ------------------------------------------------------ colouring / MIS
+
+@pytest.mark.parametrize("name", ["er", "rmat", "complete", "empty"])
+def test_color_and_mis(rt, coop_mod, gg, name):
+    g = {"er": lambda: gg.er(6000, 16, 8), "rmat": lambda: gg.rmat(12, 8, seed=2),
+         "complete": lambda: gg.complete(70), "empty": lambda: gg.empty(100)}[name]()
+    say(f"color/mis {name}")
+    dg = rt.graph(g)
+    for seed in (0, 12345):
+        ec = oracle.color(g, seed)
+        em = oracle.mis(g, seed)
+        for mode in ("plain", "coop"):
+            o = modes(coop_mod)[mode]
+            rc, c, _ = rt.color(dg, seed, o)
+            assert rc == 0
+            assert np.array_equal(as_u32(c), ec), (mode, seed)
+            rc, m, _ = rt.mis(dg, seed, o)
+            assert rc == 0
+            assert np.array_equal(m.cpu().numpy(), em), (mode, seed)
+    dg.release()
+
+
+def test_color_random_schedule(rt, coop_mod, gg):
+    g = gg.er(20000, 12, 21)
+    say("color er20000 random schedule")
+    dg = rt.graph(g)
+    exp = oracle.color(g, 77)
+    for seed in range(3):
+        o = coop_mod.make_opts(coop_mod.COOP_MODE_COOP,
+                               flags=coop_mod.COOP_F_RANDOM_SCHEDULE | coop_mod.COOP_F_PARK_KILLED,
+                               sched_seed=seed, sched_p=0.5, num_groups=16, group_size=256)
+        rc, c, st = rt.color(dg, 77, o)
+        assert rc == 0
+        assert np.array_equal(as_u32(c), exp), seed
+    dg.release()
+
+
+# ---------------------------------------------------------- barrier
+
+@pytest.mark.parametrize("mode", ["plain", "coop", "coop_host"])
+def test_barrier_bench(rt, coop_mod, mode):
+    say(f"barrier bench {mode}")
+    ns, st = coop_mod.coop_barrier_bench(rt.rt, 2000, modes(coop_mod)[mode])
+    say(f"  {ns:.0f} ns/barrier, grid={st['grid']} M={st['final_groups']}")
+    assert st["barriers"] >= 2000 and ns > 0
