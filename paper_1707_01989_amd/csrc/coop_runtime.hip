@@ -589,12 +589,13 @@ int coop_launch(coop_rt* rt, int kernel_id, const coop_params* p, const coop_lau
 int coop_wait(coop_handle* h, coop_stats* stats) {
     if (!h) return COOP_E_INVALID;
     coop_rt* rt = h->rt;
-    // detach from the injector first
+    hipError_t e = hipEventSynchronize(h->ev_end);
+    // the kernel is finished: detach it from the injector (which may still
+    // be forking joiners for it), then wait for those joiner grids
     if (rt->inj_handle.load() == h) {
         rt->inj_handle.store(nullptr);
         while (rt->inj_busy.load()) std::this_thread::yield();
     }
-    hipError_t e = hipEventSynchronize(h->ev_end);
     if (e == hipSuccess && h->joined) e = hipEventSynchronize(h->ev_join);
     Ctx c;
     Work w;
