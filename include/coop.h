@@ -95,7 +95,8 @@ enum { COOP_MODE_PLAIN = 0, COOP_MODE_COOP = 1 };
 enum {
     COOP_F_PARK_KILLED = 1u,      /* killed workgroups queue again as joiners (test mode) */
     COOP_F_RANDOM_SCHEDULE = 2u,  /* seeded device-side kill/fork schedule */
-    COOP_F_HOST_SCHEDULE = 4u     /* barrier reads the host-written target (coop_set_target) */
+    COOP_F_HOST_SCHEDULE = 4u,    /* barrier reads the host-written target (coop_set_target) */
+    COOP_F_TOP_DOWN_ONLY = 8u     /* BFS: never switch to bottom-up levels */
 };
 
 typedef struct coop_launch_opts {
@@ -110,6 +111,15 @@ typedef struct coop_launch_opts {
     uint64_t sched_seed;      /* COOP_F_RANDOM_SCHEDULE: seed */
     double sched_p;           /* COOP_F_RANDOM_SCHEDULE: P(target changes) per barrier */
     uint64_t watchdog_ns;     /* spin bound of every barrier wait; 0 = 10 s */
+    uint64_t* d_trace;        /* optional device buffer: per barrier two words, the device
+                                 wall clock when the master step began and (low 48 bits)
+                                 when it published, with the published flags in the top
+                                 16 bits; NULL = no trace */
+    uint32_t trace_cap;       /* barriers d_trace (and d_wgtrace) can hold */
+    uint32_t reserved0;
+    uint64_t* d_wgtrace;      /* optional device buffer: per barrier e and logical workgroup id,
+                                 four device wall-clock stamps at [(e * N + id) * 4 + k]: work
+                                 start, work done, barrier arrival, release seen; NULL = off */
 } coop_launch_opts;
 
 /* Fill `o` with the defaults (plain mode). */
@@ -128,11 +138,22 @@ typedef struct coop_stats {
     uint32_t levels;          /* BFS levels / SSSP or colouring rounds, over all sources */
     double kernel_ms;         /* persistent kernel time (HIP events) */
     double device_ms;         /* first barrier to end (device wall clock) */
+    uint64_t arcs;            /* arcs examined (top-down walks + bottom-up probes) */
+    uint64_t rows;            /* vertex row ranges (row_ptr pairs) read */
+    uint64_t found;           /* vertices reached (BFS) / queued (SSSP, colouring) */
+    uint64_t bitmap_words;    /* BFS frontier/visited bitmap words streamed */
+    uint32_t td_levels;       /* BFS levels run top-down */
+    uint32_t bu_levels;       /* BFS levels run bottom-up */
+    uint32_t heavy_phases;    /* extra phases that walked heavy-vertex strips */
+    uint32_t reserved;
 } coop_stats;
 
 /* BFS (the cooperative graph-traversal kernel of the paper's programming
  * section): level of every vertex from each source, one source after
- * another inside one persistent launch. d_roots holds nroots source
+ * another inside one persistent launch. Levels alternate between top-down
+ * (expand the frontier) and bottom-up (unvisited vertices look for a parent
+ * in the frontier) by the edge-count rule of Beamer et al. (SC 2012) unless
+ * COOP_F_TOP_DOWN_ONLY is set; the result is the same either way. d_roots holds nroots source
  * vertices (device memory). d_level receives, for source r, n levels at
  * d_level + r * out_stride (out_stride = 0: every source overwrites the same
  * n entries). Unreached vertices get 0xFFFFFFFF. */

@@ -17,18 +17,21 @@
 //    workgroups that are running, whatever the hardware made resident.
 //  * The barrier is a counter in HBM: each workgroup's thread 0 adds 1 with
 //    agent-scope release; the last arrival (count == M) runs the critical
-//    section ("master step") while everybody else is parked, then publishes
-//    one 64-bit release word {epoch, M', flags} with agent-scope release.
+//    section ("master step") with all of its threads while everybody else is
+//    parked, then publishes one 64-bit release word {epoch, M', flags}.
 //  * In the master step: per-level bookkeeping (a callback), fork = admit up
-//    to k in [0, N-M] waiting joiners as ids [M, M+k-1], query = read the
-//    scheduler target T (host-written word in pinned memory, or a seeded
-//    device-side schedule), and kill = the top W = min(max(0, M+k-T), M+k-1)
-//    ids leave. Workgroup 0 is never killed.
+//    to k in [0, N-M] waiting joiners as ids [M, M+k-1] (the master
+//    workgroup's threads admit them in parallel), query = read the scheduler
+//    target T (host-written word in pinned memory, or a seeded device-side
+//    schedule), and kill = the top W = min(max(0, M+k-T), M+k-1) ids leave.
+//    Workgroup 0 is never killed.
 //  * Waiters read (epoch, M') as one word. An alive member is needed by the
 //    next barrier, so it can never miss an epoch; a waiter that sees the
 //    epoch advance by more than one was therefore killed at the epoch it
 //    missed. (Reading the count separately would let a slow killed
 //    workgroup pick up a later epoch's count and continue with a stale id.)
+//  * Launch constants travel as kernel arguments (Cfg), so the master step
+//    touches only a few lines of HBM state, loaded in one batch.
 //  * Every spin is bounded by a wall-clock watchdog; expiry sets an error
 //    and an abort flag that every waiter honours, so the grid always drains.
 #pragma once
@@ -41,17 +44,17 @@ namespace coop {
 constexpr uint32_t kMaxThreads = 1024;
 constexpr uint32_t kMaxWaves = kMaxThreads / 64;
 constexpr uint32_t kJoinCap = 8192;          // joiner admission ring
+constexpr uint32_t kMaxGroups = 2048;        // launch limit N
 
 // release-word flags
 constexpr uint32_t kFlagDone = 1u;          // kernel finished: everybody leaves
 constexpr uint32_t kFlagAbort = 2u;         // watchdog fired or error: leave
 constexpr uint32_t kFlagUser0 = 16u;        // algorithm-specific bits start here
 
-// ctx->mode bits
+// Cfg::mode bits
 constexpr uint32_t kModeCoop = 1u;          // cooperative (resizable) launch
 constexpr uint32_t kModePark = 2u;          // killed workgroups re-queue as joiners
 constexpr uint32_t kModeRandomSched = 4u;   // device-side seeded kill/fork schedule
-constexpr uint32_t kModeTrace = 8u;         // record per-barrier timestamps
 
 // error codes written to ctx->error (match COOP_E_* of coop.h)
 constexpr int32_t kErrTimeout = -4;
@@ -62,9 +65,30 @@ constexpr int32_t kErrInternal = -7;
 struct alignas(64) HostCtl {
     uint32_t target;          // scheduler target T (query), 1..N
     uint32_t pad0[15];
-    uint32_t exited;          // workgroups released to the scheduler (device writes)
-    uint32_t pad1[15];
 };
+
+// Launch constants (kernel argument; immutable like the paper's kernel
+// parameters).
+struct Cfg {
+    uint32_t N;               // launch limit (max active workgroups)
+    uint32_t mode;            // kMode* bits
+    uint32_t sched_p16;       // random schedule: P(target changes) * 65536
+    uint32_t trace_cap;       // barriers the trace buffer holds
+    uint64_t sched_seed;
+    uint64_t watchdog_ticks;  // wall-clock ticks before a spin gives up
+    HostCtl* host;            // host-written target, or null
+    uint64_t* trace;          // optional: 2 words per barrier (master start, publish|flags)
+    uint32_t epoch0_wait;     // ticks ticket 0 waits for the grid to register
+    uint32_t wgtrace_cap;     // barriers the per-workgroup trace holds
+    uint64_t* wgtrace;        // optional: per barrier and logical id, 4 timestamps
+};
+
+// Per-workgroup phase trace points (debugging and tuning only).
+enum WgTracePoint : uint32_t { kTrStart = 0, kTrWorkDone = 1, kTrArrive = 2, kTrReleased = 3 };
+__device__ __forceinline__ void wg_trace(const Cfg cfg, uint32_t epoch, uint32_t id, uint32_t point) {
+    if (cfg.wgtrace && epoch < cfg.wgtrace_cap && threadIdx.x == 0)
+        cfg.wgtrace[((size_t)epoch * cfg.N + id) * 4 + point] = wall_clock64();
+}
 
 struct alignas(256) Ctx {
     // ---- line: barrier arrival counter (one atomic per workgroup per barrier)
@@ -73,24 +97,17 @@ struct alignas(256) Ctx {
     // ---- line: release word {epoch:32 (lo) | M:16 | flags:16 (hi)}
     uint64_t release;
     uint64_t _pr[31];
-    // ---- line: registration / joiner queue
+    // ---- line: registration
     uint32_t ticket;          // start-up tickets
     uint32_t join_tail;       // next joiner slot
-    uint32_t join_head;       // first slot not yet admitted (master only)
-    uint32_t _pj[61];
-    // ---- line: configuration (written by the init kernel, read-only after)
-    uint32_t N;               // launch limit (max active workgroups)
-    uint32_t mode;
-    uint32_t sched_p16;       // random schedule: P(change) * 65536
-    uint32_t wg_size;
-    uint64_t sched_seed;
-    uint64_t watchdog_ticks;  // wall-clock ticks before a spin gives up
-    HostCtl* host;            // nullable
-    uint32_t T_dev;           // device-side target (random schedule)
-    uint32_t epoch0_wait;     // ticks ticket 0 waits for the first joiners
-    uint32_t _pc[52];
-    // ---- line: results / statistics (master only, plus error by anyone)
+    uint32_t _pj[62];
+    // ---- line: error and the host target as read by workgroup 0
     int32_t error;
+    uint32_t T_seen;
+    uint32_t _pe[62];
+    // ---- line: master-only scheduler state and statistics
+    uint32_t join_head;       // first slot not yet admitted
+    uint32_t T_dev;           // device-side target (random schedule)
     uint32_t barriers;
     uint32_t kills;
     uint32_t forks;
@@ -98,19 +115,20 @@ struct alignas(256) Ctx {
     uint32_t min_M;
     uint32_t max_M;
     uint32_t final_M;
+    uint32_t _pm0;
     uint64_t t_start;
     uint64_t t_end;
-    uint32_t _ps[52];
+    uint32_t _pm[50];
     // ---- joiner admission ring: {slot:32 (lo) | epoch_lo:16 | id:16 (hi)}
     uint64_t join_entry[kJoinCap];
 };
 
 // ------------------------------------------------------------- atomics
 
-__device__ __forceinline__ uint32_t ld_acquire(const uint32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ uint32_t ld_relaxed(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t ld_relaxed_i(const int32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint64_t ld_relaxed64(const uint64_t* p) {
@@ -125,14 +143,14 @@ __device__ __forceinline__ void st_release64(uint64_t* p, uint64_t v) {
 __device__ __forceinline__ uint32_t add_relaxed(uint32_t* p, uint32_t v) {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ uint64_t add_relaxed64(uint64_t* p, uint64_t v) {
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Fire-and-forget add (the result is unused, so no round trip is waited for).
+__device__ __forceinline__ void add_nr64(uint64_t* p, uint64_t v) {
+    (void)__hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint32_t ld_system(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 __device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
-__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 
 __device__ __forceinline__ uint64_t now_ticks() { return wall_clock64(); }
 
@@ -162,33 +180,21 @@ struct Member {
     uint32_t alive;     // 1 while this workgroup is an active member
 };
 
+// Workgroup-shared state of the barrier.
+struct BarrierLds {
+    Member member;
+    uint32_t killed;        // this workgroup left because the scheduler claimed it
+    uint32_t is_master;     // this workgroup runs the master step
+    uint32_t flags;         // master step result (broadcast inside the master)
+    uint32_t head, kmax, T;
+    uint32_t valid[kMaxGroups / 32];   // admission: ring slots whose joiner was still waiting
+};
+
 // Raise the abort flag so every spinning workgroup leaves.
 __device__ inline void raise_error(Ctx* c, int32_t err) {
     atomicCAS(&c->error, 0, err);
     __hip_atomic_fetch_or(&c->release, (uint64_t)kFlagAbort << 48, __ATOMIC_RELEASE,
                           __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// The scheduler target this barrier sees (the paper's `query`): either the
-// host-written word or a seeded device-side random schedule.
-__device__ inline uint32_t query_target(Ctx* c, uint32_t epoch, uint32_t host_T) {
-    const uint32_t N = c->N;
-    uint32_t T;
-    if (c->mode & kModeRandomSched) {
-        uint64_t h = splitmix64(c->sched_seed + (uint64_t)epoch * 0x9E3779B97F4A7C15ull);
-        T = c->T_dev;
-        if ((uint32_t)(h & 0xFFFFu) < c->sched_p16) {
-            T = 1u + (uint32_t)((h >> 16) % N);
-            c->T_dev = T;
-        }
-    } else if (c->host) {
-        T = host_T;
-    } else {
-        T = N;
-    }
-    if (T < 1u) T = 1u;
-    if (T > N) T = N;
-    return T;
 }
 
 // Joiner admission entries: {slot:32 (lo) | epoch_lo:16 | id:16 (hi)}.
@@ -199,45 +205,13 @@ __device__ inline uint32_t query_target(Ctx* c, uint32_t epoch, uint32_t host_T)
 __device__ __forceinline__ uint64_t withdrawn_entry(uint32_t slot) {
     return (uint64_t)slot | (0xFFFFFFFFull << 32);
 }
-
-// Master step, part 2: fork (admit joiners) and kill (query). Returns M'.
-// Runs while every other member is parked in the barrier.
-__device__ inline uint32_t resize_at_barrier(Ctx* c, uint32_t M, uint32_t new_epoch,
-                                             uint32_t host_T) {
-    const uint32_t N = c->N;
-    const uint32_t T = query_target(c, new_epoch, host_T);
-    // fork: k in [0, N - M], limited by registered joiners and the target
-    uint32_t head = c->join_head;
-    const uint32_t tail = ld_relaxed(&c->join_tail);
-    const uint32_t want = T > M ? T - M : 0u;
-    const uint32_t room = N - M;
-    uint32_t k = 0;
-    while (head != tail && k < room && k < want) {
-        const uint32_t slot = head++;
-        const uint64_t e = (uint64_t)slot | ((uint64_t)(new_epoch & 0xFFFFu) << 32) |
-                           ((uint64_t)(M + k) << 48);
-        const uint64_t prev = __hip_atomic_exchange(&c->join_entry[slot % kJoinCap], e,
-                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == withdrawn_entry(slot)) continue;   // that joiner already left
-        ++k;
-    }
-    c->join_head = head;
-    const uint32_t M2 = M + k;
-    // query/kill: the top W ids leave; workgroup 0 always stays
-    uint32_t W = M2 > T ? M2 - T : 0u;
-    if (W > M2 - 1) W = M2 - 1;
-    const uint32_t Mn = M2 - W;
-    if (k) c->forks += k;
-    if (W) c->kills += W;
-    if (Mn != M) c->resizes += 1;
-    if (Mn < c->min_M) c->min_M = Mn;
-    if (Mn > c->max_M) c->max_M = Mn;
-    return Mn;
+__device__ __forceinline__ uint64_t admit_entry(uint32_t slot, uint32_t epoch, uint32_t id) {
+    return (uint64_t)slot | ((uint64_t)(epoch & 0xFFFFu) << 32) | ((uint64_t)id << 48);
 }
 
 // Wait for the release word to move past `epoch` (or abort/done). Returns
 // the word. Bounded by the watchdog.
-__device__ inline uint64_t wait_release(Ctx* c, uint32_t epoch) {
+__device__ inline uint64_t wait_release(Ctx* c, const Cfg cfg, uint32_t epoch) {
     const uint64_t t0 = now_ticks();
     uint32_t spins = 0;
     for (;;) {
@@ -246,9 +220,8 @@ __device__ inline uint64_t wait_release(Ctx* c, uint32_t epoch) {
         if (++spins > 32) {
             __builtin_amdgcn_s_sleep(1);
             if ((spins & 255) == 0) {
-                if (__hip_atomic_load(&c->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                    return r | ((uint64_t)kFlagAbort << 48);
-                if (now_ticks() - t0 > c->watchdog_ticks) {
+                if (ld_relaxed_i(&c->error)) return r | ((uint64_t)kFlagAbort << 48);
+                if (now_ticks() - t0 > cfg.watchdog_ticks) {
                     raise_error(c, kErrTimeout);
                     return ld_relaxed64(&c->release) | ((uint64_t)kFlagAbort << 48);
                 }
@@ -257,33 +230,31 @@ __device__ inline uint64_t wait_release(Ctx* c, uint32_t epoch) {
     }
 }
 
-// Registration (thread 0 only). In a plain launch the workgroup id is the
-// block id and M is the grid size. In a cooperative launch ticket 0 becomes
-// logical 0 (M starts at 1); everybody else -- late-dispatched workgroups,
-// workgroups of a joiner grid, killed workgroups re-queued in park mode --
-// waits in the joiner queue until admitted at a barrier, until the kernel is
-// done, or until it gives its compute unit back because the scheduler target
-// leaves no room (host-driven schedule only) or the watchdog expires.
-__device__ inline Member join_queue(Ctx* c) {
+// Joiner queue (thread 0 only): wait until admitted at a barrier, until
+// the kernel is done, or until giving the compute unit back because the
+// scheduler target leaves no room (host-driven schedule only) or the
+// watchdog expires.
+__device__ inline Member join_queue(Ctx* c, const Cfg cfg) {
     Member m{};
     m.alive = 0;
     const uint32_t slot = add_relaxed(&c->join_tail, 1u);
     uint64_t* ent = &c->join_entry[slot % kJoinCap];
     const uint64_t t0 = now_ticks();
     for (uint32_t it = 0;; ++it) {
-        uint64_t e = __hip_atomic_load(ent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t e = __hip_atomic_load(ent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         uint64_t r = ld_relaxed64(&c->release);
         if ((uint32_t)e == slot && (e >> 32) != 0xFFFFFFFFull) {
-            // admitted at epoch (e >> 32) & 0xFFFF as id (e >> 48): wait until
-            // that epoch's release is visible, then start after the fork point
+            // admitted at epoch (e >> 32) & 0xFFFF: wait until that epoch's
+            // release is visible, then read the final id (the master may
+            // renumber before it publishes) and start after the fork point
             const uint32_t aep = (uint32_t)(e >> 32) & 0xFFFFu;
-            while ((rel_epoch(r) & 0xFFFFu) != aep &&
-                   !(rel_flags(r) & (kFlagAbort | kFlagDone))) {
+            while ((rel_epoch(r) & 0xFFFFu) != aep && !(rel_flags(r) & (kFlagAbort | kFlagDone))) {
                 __builtin_amdgcn_s_sleep(1);
                 r = ld_relaxed64(&c->release);
             }
             fence_acquire();
-            m.id = (uint32_t)(e >> 48);
+            const uint64_t f = __hip_atomic_load(ent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            m.id = (uint32_t)(f >> 48);
             m.M = rel_M(r);
             m.epoch = rel_epoch(r);
             m.flags = rel_flags(r);
@@ -291,16 +262,15 @@ __device__ inline Member join_queue(Ctx* c) {
             return m;
         }
         bool leave = (rel_flags(r) & (kFlagAbort | kFlagDone)) != 0;
-        if (!leave && c->host && !(c->mode & kModePark) && (it & 15) == 15) {
+        if (!leave && cfg.host && !(cfg.mode & kModePark) && (it & 15) == 15) {
             // no room under the current target: give the compute unit back
-            leave = ld_system(&c->host->target) <= rel_M(r);
+            leave = ld_system(&cfg.host->target) <= rel_M(r);
         }
-        if (!leave && now_ticks() - t0 > c->watchdog_ticks) leave = true;
+        if (!leave && now_ticks() - t0 > cfg.watchdog_ticks) leave = true;
         if (leave) {
             uint64_t expected = e;
-            if (__hip_atomic_compare_exchange_strong(ent, &expected, withdrawn_entry(slot),
-                                                     __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT))
+            if (__hip_atomic_compare_exchange_strong(ent, &expected, withdrawn_entry(slot), __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
                 return m;            // withdrawn: the master will skip this slot
             continue;                // the master admitted us meanwhile: re-read
         }
@@ -308,13 +278,16 @@ __device__ inline Member join_queue(Ctx* c) {
     }
 }
 
-__device__ inline Member register_member(Ctx* c, bool plain, bool joiner_grid) {
+// Registration (thread 0 only). In a plain launch the workgroup id is the
+// block id and M is the grid size. In a cooperative launch ticket 0 becomes
+// logical 0 (M starts at 1); everybody else -- late-dispatched workgroups,
+// workgroups of a joiner grid, killed workgroups re-queued in park mode --
+// waits in the joiner queue.
+__device__ inline Member register_member(Ctx* c, const Cfg cfg, bool plain, bool joiner_grid) {
     Member m{};
     if (plain) {
         m.id = blockIdx.x;
         m.M = gridDim.x;
-        m.epoch = 0;
-        m.flags = 0;
         m.alive = 1;
         return m;
     }
@@ -323,74 +296,185 @@ __device__ inline Member register_member(Ctx* c, bool plain, bool joiner_grid) {
         if (t == 0) {
             m.id = 0;
             m.M = 1;
-            m.epoch = 0;
-            m.flags = 0;
             m.alive = 1;
             return m;
         }
     }
-    return join_queue(c);
-}
-
-// The (resizing) global barrier. Called by every thread of every active
-// workgroup. `master_fn(M, new_epoch)` runs in thread 0 of the last
-// arrival while all other members wait; it does the per-level bookkeeping
-// and returns the flags to publish (kFlagDone ends the kernel). In a
-// cooperative launch the barrier then admits joiners and applies the
-// scheduler's target. `sh` is a workgroup-shared slot used to broadcast the
-// new membership; `killed` tells the caller whether this workgroup left
-// because the scheduler claimed it (as opposed to the kernel ending).
-template <bool Coop, class MasterFn>
-__device__ inline void barrier(Ctx* c, Member& m, Member* sh, uint32_t* killed, MasterFn&& master_fn) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t host_T = 0;
-        if (Coop && c->host) host_T = ld_system(&c->host->target);   // prefetch the query
-        const uint32_t old = __hip_atomic_fetch_add(&c->arrive, 1u, __ATOMIC_ACQ_REL,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-        Member n = m;
-        uint32_t k = 0;
-        if (old + 1 == m.M) {
-            // master step: everybody else is parked in the barrier
-            __hip_atomic_store(&c->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t ne = m.epoch + 1;
-            uint32_t flags = master_fn(m.M, ne);
-            if (__hip_atomic_load(&c->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                flags |= kFlagAbort;
-            uint32_t Mn = m.M;
-            if (Coop && !(flags & (kFlagDone | kFlagAbort))) Mn = resize_at_barrier(c, m.M, ne, host_T);
-            c->barriers += 1;
-            if (flags & kFlagDone) { c->final_M = m.M; c->t_end = now_ticks(); }
-            st_release64(&c->release, make_release(ne, Mn, flags));
-            n.epoch = ne;
-            n.M = Mn;
-            n.flags = flags;
-        } else {
-            const uint64_t r = wait_release(c, m.epoch);
-            fence_acquire();
-            const uint32_t e = rel_epoch(r);
-            n.flags = rel_flags(r);
-            n.M = rel_M(r);
-            n.epoch = e;
-            // an alive member cannot miss an epoch: a gap means we were killed
-            if (Coop && e != m.epoch + 1) k = 1;
-        }
-        if (Coop && n.id >= n.M) k = 1;
-        if (n.flags & (kFlagDone | kFlagAbort)) k = 0;
-        n.alive = (!k && !(n.flags & (kFlagDone | kFlagAbort))) ? 1u : 0u;
-        *sh = n;
-        *killed = k;
-    }
-    __syncthreads();
-    m = *sh;
+    return join_queue(c, cfg);
 }
 
 // Start-up: in a cooperative launch ticket 0 waits briefly for the rest of
 // the grid to register, so the first barrier can admit them together.
-__device__ inline void startup_wait(Ctx* c) {
+__device__ inline void startup_wait(Ctx* c, const Cfg cfg) {
     const uint64_t t0 = now_ticks();
-    while (ld_relaxed(&c->join_tail) + 1 < gridDim.x && now_ticks() - t0 < c->epoch0_wait)
+    while (ld_relaxed(&c->join_tail) + 1 < gridDim.x && now_ticks() - t0 < cfg.epoch0_wait)
         __builtin_amdgcn_s_sleep(2);
+}
+
+// Scheduler part of the master step, run by every thread of the master
+// workgroup: fork (admit waiting joiners, in parallel), query (the target)
+// and kill (the top ids). Thread 0 then publishes the release word.
+template <bool Coop>
+__device__ inline void master_schedule(Ctx* c, const Cfg cfg, Member& m, BarrierLds& b, uint32_t flags,
+                                       uint64_t t_in) {
+    const uint32_t ne = m.epoch + 1;
+    // one batch of independent loads
+    uint32_t T_dev = 0, nb = 0, kills = 0, forks = 0, resizes = 0, min_M = 0, max_M = 0;
+    if (threadIdx.x == 0) {
+        const int32_t err = ld_relaxed_i(&c->error);
+        const uint32_t tail = Coop ? ld_relaxed(&c->join_tail) : 0u;
+        const uint32_t T_seen = (Coop && cfg.host) ? ld_relaxed(&c->T_seen) : 0u;
+        const uint32_t join_head = c->join_head;
+        T_dev = c->T_dev;
+        nb = c->barriers;
+        kills = c->kills;
+        forks = c->forks;
+        resizes = c->resizes;
+        min_M = c->min_M;
+        max_M = c->max_M;
+        if (err) flags |= kFlagAbort;
+        const bool live = Coop && !(flags & (kFlagDone | kFlagAbort));
+        uint32_t T = cfg.N;
+        if (live) {
+            if (cfg.mode & kModeRandomSched) {
+                const uint64_t h = splitmix64(cfg.sched_seed + (uint64_t)ne * 0x9E3779B97F4A7C15ull);
+                if ((uint32_t)(h & 0xFFFFu) < cfg.sched_p16) T_dev = 1u + (uint32_t)((h >> 16) % cfg.N);
+                T = T_dev;
+            } else if (cfg.host) {
+                T = T_seen;
+            }
+            if (T < 1u) T = 1u;
+            if (T > cfg.N) T = cfg.N;
+        }
+        const uint32_t ready = tail - join_head;
+        const uint32_t room = cfg.N - m.M;
+        const uint32_t want = T > m.M ? T - m.M : 0u;
+        uint32_t kmax = live ? ready : 0u;
+        kmax = kmax < room ? kmax : room;
+        kmax = kmax < want ? kmax : want;
+        b.head = join_head;
+        b.kmax = kmax;
+        b.T = T;
+        b.flags = flags;
+    }
+    uint32_t admitted = 0;
+    if (Coop) {
+        __syncthreads();
+        const uint32_t kmax = b.kmax, head = b.head;
+        if (kmax) {
+            const uint32_t nwords = (kmax + 31) / 32;
+            for (uint32_t w = threadIdx.x; w < nwords; w += blockDim.x) b.valid[w] = 0;
+            __syncthreads();
+            // fork: admit ring slots head .. head+kmax-1 as ids M .. M+kmax-1
+            for (uint32_t j = threadIdx.x; j < kmax; j += blockDim.x) {
+                const uint32_t slot = head + j;
+                const uint64_t prev = __hip_atomic_exchange(&c->join_entry[slot % kJoinCap],
+                                                            admit_entry(slot, ne, m.M + j), __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
+                if (prev != withdrawn_entry(slot)) atomicOr(&b.valid[j / 32], 1u << (j % 32));
+            }
+            __syncthreads();
+            // withdrawn slots leave holes: renumber the admitted ones densely
+            // (a joiner reads its final id after the release is published)
+            for (uint32_t j = threadIdx.x; j < kmax; j += blockDim.x) {
+                const uint32_t wj = j / 32, bj = j % 32;
+                if (!((b.valid[wj] >> bj) & 1u)) continue;
+                uint32_t rank = __popc(b.valid[wj] & ((1u << bj) - 1u));
+                for (uint32_t q = 0; q < wj; ++q) rank += __popc(b.valid[q]);
+                if (rank != j) {
+                    const uint32_t slot = head + j;
+                    __hip_atomic_store(&c->join_entry[slot % kJoinCap], admit_entry(slot, ne, m.M + rank),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            for (uint32_t q = 0; q < nwords; ++q) admitted += __popc(b.valid[q]);
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) {
+        flags = b.flags;
+        uint32_t Mn = m.M;
+        if (Coop && !(flags & (kFlagDone | kFlagAbort))) {
+            const uint32_t M2 = m.M + admitted;
+            uint32_t W = M2 > b.T ? M2 - b.T : 0u;
+            if (W > M2 - 1) W = M2 - 1;
+            Mn = M2 - W;
+            if (b.kmax) c->join_head = b.head + b.kmax;
+            if (cfg.mode & kModeRandomSched) c->T_dev = T_dev;
+            if (admitted) c->forks = forks + admitted;
+            if (W) c->kills = kills + W;
+            if (Mn != m.M) c->resizes = resizes + 1;
+            if (Mn < min_M) c->min_M = Mn;
+            if (Mn > max_M) c->max_M = Mn;
+        }
+        c->barriers = nb + 1;
+        if (nb == 0) c->t_start = t_in;
+        if (flags & kFlagDone) {
+            c->final_M = m.M;
+            c->t_end = now_ticks();
+        }
+        if (cfg.trace && nb < cfg.trace_cap) {
+            cfg.trace[2 * nb] = t_in;
+            cfg.trace[2 * nb + 1] = (now_ticks() & 0xFFFFFFFFFFFFull) | ((uint64_t)(flags & 0xFFFFu) << 48);
+        }
+        st_release64(&c->release, make_release(ne, Mn, flags));
+        Member n = m;
+        n.epoch = ne;
+        n.M = Mn;
+        n.flags = flags;
+        const bool over = (flags & (kFlagDone | kFlagAbort)) != 0;
+        n.alive = (over || (Coop && n.id >= Mn)) ? 0u : 1u;
+        b.member = n;
+        b.killed = (!over && Coop && n.id >= Mn) ? 1u : 0u;
+    }
+}
+
+// The (resizing) global barrier. Called by every thread of every active
+// workgroup. The last workgroup to arrive runs the master step with all of
+// its threads: `master_fn(M, new_epoch)` does the per-level bookkeeping
+// (it may use __syncthreads and must return the same flags in every
+// thread); kFlagDone ends the kernel. In a cooperative launch the master
+// then admits joiners and applies the scheduler target. Only workgroup 0
+// reads the host-written target (one PCIe read per barrier), before it
+// arrives.
+template <bool Coop, class MasterFn>
+__device__ inline void barrier(Ctx* c, const Cfg cfg, Member& m, BarrierLds& b, MasterFn&& master_fn) {
+    __syncthreads();
+    wg_trace(cfg, m.epoch, m.id, kTrArrive);
+    if (threadIdx.x == 0) {
+        if (Coop && cfg.host && m.id == 0)
+            __hip_atomic_store(&c->T_seen, ld_system(&cfg.host->target), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t old = __hip_atomic_fetch_add(&c->arrive, 1u, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        b.is_master = (old + 1 == m.M) ? 1u : 0u;
+        if (b.is_master) __hip_atomic_store(&c->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (b.is_master) {
+        // master step: everybody else is parked in the barrier
+        const uint64_t t_in = now_ticks();
+        const uint32_t flags = master_fn(m.M, m.epoch + 1);
+        master_schedule<Coop>(c, cfg, m, b, flags, t_in);
+    } else if (threadIdx.x == 0) {
+        const uint64_t r = wait_release(c, cfg, m.epoch);
+        fence_acquire();
+        Member n = m;
+        const uint32_t e = rel_epoch(r);
+        n.flags = rel_flags(r);
+        n.M = rel_M(r);
+        n.epoch = e;
+        // an alive member cannot miss an epoch: a gap means it was killed
+        uint32_t k = (Coop && e != m.epoch + 1) ? 1u : 0u;
+        if (Coop && n.id >= n.M) k = 1;
+        if (n.flags & (kFlagDone | kFlagAbort)) k = 0;
+        n.alive = (!k && !(n.flags & (kFlagDone | kFlagAbort))) ? 1u : 0u;
+        b.member = n;
+        b.killed = k;
+    }
+    __syncthreads();
+    wg_trace(cfg, m.epoch, m.id, kTrReleased);
+    m = b.member;
 }
 
 }  // namespace coop

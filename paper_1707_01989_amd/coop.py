@@ -30,6 +30,7 @@ COOP_MODE_COOP = 1
 COOP_F_PARK_KILLED = 1
 COOP_F_RANDOM_SCHEDULE = 2
 COOP_F_HOST_SCHEDULE = 4
+COOP_F_TOP_DOWN_ONLY = 8
 
 COOP_KERNEL_BFS = 1
 COOP_KERNEL_SSSP = 2
@@ -67,6 +68,8 @@ class coop_launch_opts(ctypes.Structure):
         ("lds_bytes", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("heavy_threshold", ctypes.c_uint32),
         ("strip", ctypes.c_uint32), ("startup_wait_ns", ctypes.c_uint32), ("sched_seed", ctypes.c_uint64),
         ("sched_p", ctypes.c_double), ("watchdog_ns", ctypes.c_uint64),
+        ("d_trace", ctypes.c_void_p), ("trace_cap", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
+        ("d_wgtrace", ctypes.c_void_p),
     ]
 
 
@@ -76,6 +79,9 @@ class coop_stats(ctypes.Structure):
         ("forks", ctypes.c_uint32), ("resizes", ctypes.c_uint32), ("min_groups", ctypes.c_uint32),
         ("max_groups", ctypes.c_uint32), ("final_groups", ctypes.c_uint32), ("grid", ctypes.c_uint32),
         ("levels", ctypes.c_uint32), ("kernel_ms", ctypes.c_double), ("device_ms", ctypes.c_double),
+        ("arcs", ctypes.c_uint64), ("rows", ctypes.c_uint64), ("found", ctypes.c_uint64),
+        ("bitmap_words", ctypes.c_uint64), ("td_levels", ctypes.c_uint32), ("bu_levels", ctypes.c_uint32),
+        ("heavy_phases", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:

@@ -9,27 +9,92 @@
 
 namespace coop {
 
+// Transmit block: the per-level state the master step maintains, which a
+// joining workgroup takes over from workgroup 0. Loaded and stored as a
+// whole by the master (one batch of loads).
+struct Xfer {
+    uint32_t level;            // level (BFS) / round (SSSP, colouring) of the interval
+    uint32_t root;             // index of the current source
+    uint32_t round;            // rounds over all sources (SSSP queue tags)
+    uint32_t in_size;          // input queue length (queue engine) / heavy strips (HEAVY)
+    uint32_t nf_prev;          // BFS: vertices in the previous frontier
+    uint32_t lvl_found;        // BFS: found in the current level before a HEAVY phase
+    uint32_t lvl_mf_lo;        // BFS: their degree sum (64-bit, split)
+    uint32_t lvl_mf_hi;
+    uint32_t m_visited_lo;     // BFS: sum of degrees of visited vertices (current source)
+    uint32_t m_visited_hi;
+    uint32_t levels_total;     // statistics: levels/rounds over all sources
+    uint32_t td_levels;        // BFS levels run top-down
+    uint32_t bu_levels;        // BFS levels run bottom-up
+    uint32_t heavy_phases;     // HEAVY phases
+    uint32_t pad[2];
+};
+
+__host__ __device__ inline uint64_t join64(uint32_t lo, uint32_t hi) { return ((uint64_t)hi << 32) | lo; }
+
+// Register copy of the transmit block for the master step: four 16-byte
+// loads issued together, four stores at the end (a struct copy would be
+// staged through private memory by the compiler).
+struct XferR {
+    uint4 a, b, c, d;
+    __device__ uint32_t& level() { return a.x; }
+    __device__ uint32_t& root() { return a.y; }
+    __device__ uint32_t& round() { return a.z; }
+    __device__ uint32_t& in_size() { return a.w; }
+    __device__ uint32_t& nf_prev() { return b.x; }
+    __device__ uint32_t& lvl_found() { return b.y; }
+    __device__ uint32_t& lvl_mf_lo() { return b.z; }
+    __device__ uint32_t& lvl_mf_hi() { return b.w; }
+    __device__ uint32_t& m_visited_lo() { return c.x; }
+    __device__ uint32_t& m_visited_hi() { return c.y; }
+    __device__ uint32_t& levels_total() { return c.z; }
+    __device__ uint32_t& td_levels() { return c.w; }
+    __device__ uint32_t& bu_levels() { return d.x; }
+    __device__ uint32_t& heavy_phases() { return d.y; }
+};
+
 // Per-launch work counters and the transmit block, on separate cache lines.
 struct alignas(256) Work {
-    uint64_t claim;            // input frontier claims: {size:32 (hi) | next:32 (lo)}
-    uint64_t _p0[31];
-    uint32_t out_tail;         // output frontier length
+    uint32_t out_tail;         // output queue length (queue engine)
     uint32_t _p1[63];
     uint32_t heavy_tail;       // heavy strips queued this level
     uint32_t _p2[63];
-    uint64_t hclaim;           // heavy strip claims: {count (hi) | next (lo)}
-    uint64_t _p3[31];
-    // transmit block: state a joining workgroup takes over from workgroup 0
-    uint32_t xfer_level;       // level (BFS) / round (SSSP, colouring) of the interval
-    uint32_t xfer_root;        // index of the current source
-    uint32_t xfer_round;       // rounds over all sources (SSSP queue tags)
-    uint32_t levels_total;     // statistics: levels/rounds over all sources
-    uint32_t _p4[60];
+    Xfer x;
+    uint32_t _p4[64 - sizeof(Xfer) / 4];
+
+    __device__ XferR load_x() const {
+        const uint4* p = reinterpret_cast<const uint4*>(&x);
+        return XferR{p[0], p[1], p[2], p[3]};
+    }
+    __device__ void store_x(const XferR& r) {
+        uint4* p = reinterpret_cast<uint4*>(&x);
+        p[0] = r.a;
+        p[1] = r.b;
+        p[2] = r.c;
+        p[3] = r.d;
+    }
+};
+static_assert(sizeof(Xfer) == 64, "transmit block is four 16-byte words");
+
+// Per-workgroup accumulator slot (one 64-byte line per logical id) of
+// uint64 fields, updated with fire-and-forget atomic adds: no shared
+// counter on the hot path. The master step reads and clears the per-level
+// fields; the cumulative ones are summed by the host after the launch.
+constexpr uint32_t kSlotWords = 16;     // 8 uint64 fields
+enum SlotField : uint32_t {
+    kSlotFound = 0,       // per level: vertices reached / queued
+    kSlotMf = 1,          // per level: sum of their degrees (BFS direction rule)
+    kSlotArcs = 2,        // cumulative: arcs examined
+    kSlotRows = 3,        // cumulative: row ranges read
+    kSlotBitmap = 4,      // cumulative: bitmap words streamed
+    kSlotFoundAll = 5,    // cumulative: vertices reached / queued
 };
 
 struct TraversalArgs {
+    Cfg cfg;
     Ctx* ctx;
     Work* work;
+    uint32_t* slots;           // N x kSlotWords per-workgroup accumulators (zeroed at init)
     const uint32_t* row_ptr;
     const uint32_t* col;
     const uint32_t* w;         // arc weights (SSSP) or null
@@ -38,21 +103,28 @@ struct TraversalArgs {
     uint32_t strip;            // arcs per heavy strip
     uint32_t heavy_cap;        // capacity of `heavy` in strips
     uint4* heavy;              // strips {payload, first arc, length, vertex}
-    uint32_t* frontier[2];     // n entries each
+    uint32_t* frontier[2];     // queue engine: n entries each
     const uint32_t* roots;     // sources, processed one after another
     uint32_t nroots;
     uint32_t out_stride;       // elements between consecutive roots' outputs (0: shared)
+    uint32_t N;                // launch limit (slots)
 };
 
 struct BfsArgs {
     TraversalArgs t;
-    uint32_t* bitmap;          // ceil(n/32) words, visited set
+    uint32_t* vis;             // visited bitmap, ceil(n/32) words (+ padding to 64-word blocks)
+    uint32_t* fb[3];           // rotating frontier bitmaps: current / next / being cleared
+    const uint32_t* deg0;      // vertices without arcs (never expanded, skipped bottom-up)
     uint32_t* level_out;       // nroots * out_stride (or n) levels
+    uint32_t words;            // bitmap words, multiple of 64
+    uint32_t direction_opt;    // 0: top-down only; 1: switch to bottom-up on large frontiers
+    uint32_t alpha, beta;      // switching parameters (Beamer et al.)
+    uint64_t total_arcs;
 };
 
 struct SsspArgs {
     TraversalArgs t;
-    uint32_t* stamp;           // n words: round tag of the last queueing
+    uint64_t* state;           // n words {distance:32 (hi) | round tag of the last queueing:32 (lo)}
     int32_t* dist_out;         // nroots * out_stride (or n) distances
 };
 
@@ -74,16 +146,17 @@ struct CotaskArgs {
 };
 
 struct BarrierBenchArgs {
+    Cfg cfg;
     Ctx* ctx;
     Work* work;
     uint32_t iters;
 };
 
 // Launchers (defined in coop_kernels.hip). Each returns a hipError_t.
-hipError_t launch_init_ctx(Ctx* c, Work* w, uint32_t N, uint32_t mode, uint32_t wg_size,
-                           uint64_t sched_seed, uint32_t sched_p16, uint64_t watchdog_ticks,
-                           uint32_t epoch0_wait, HostCtl* host, hipStream_t s);
+hipError_t launch_init_ctx(Ctx* c, Work* w, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s);
+// Bitmap of vertices without arcs (words: multiple of 64, padding bits set).
+hipError_t launch_deg0_bitmap(const uint32_t* row_ptr, uint32_t n, uint32_t* bits, uint32_t words, hipStream_t s);
 hipError_t launch_bfs(const BfsArgs& a, bool coop, bool joiner_grid, uint32_t grid, uint32_t block,
                       uint32_t lds_bytes, hipStream_t s);
 hipError_t launch_sssp(const SsspArgs& a, bool coop, bool joiner_grid, uint32_t grid, uint32_t block,

@@ -61,6 +61,8 @@ struct coop_graph {
     uint32_t n;
     uint64_t arcs;
     uint32_t max_deg;
+    uint32_t* deg0 = nullptr;                            // device bitmap: vertices without arcs
+    uint32_t words = 0;                                  // bitmap words (multiple of 64)
     std::vector<uint32_t> deg;                           // host copy of the degrees
     std::map<std::pair<uint32_t, uint32_t>, uint64_t> strips;   // (threshold, strip) -> capacity
 
@@ -80,6 +82,8 @@ struct coop_handle {
     coop_rt* rt = nullptr;
     int kind = 0;
     bool coop = false;
+    coop::Cfg cfg{};
+    uint32_t* slots = nullptr;           // per-workgroup statistics (device)
     uint32_t grid = 0, block = 0, lds = 0;
     Ctx* ctx = nullptr;
     Work* work = nullptr;
@@ -209,7 +213,6 @@ struct Sizing {
     uint64_t watchdog_ticks;
     uint32_t startup_ticks, sched_p16;
     bool coop;
-    HostCtl* host_needed;
 };
 
 int size_launch(coop_rt* rt, const coop_launch_opts* o, Sizing* s) {
@@ -246,7 +249,6 @@ int size_launch(coop_rt* rt, const coop_launch_opts* o, Sizing* s) {
     if (s->watchdog_ticks == 0) s->watchdog_ticks = 1;
     const uint64_t su = o->startup_wait_ns ? o->startup_wait_ns : kDefaultStartupNs;
     s->startup_ticks = (uint32_t)std::min<uint64_t>(0xFFFFFFFFu, su * (uint64_t)rt->wall_khz / 1000000ull);
-    s->host_needed = nullptr;
     return COOP_OK;
 }
 
@@ -276,9 +278,19 @@ int begin_launch(coop_rt* rt, const coop_launch_opts* o, const Sizing& sz, int k
     for (hipEvent_t* e : {&h->ev_init, &h->ev_start, &h->ev_end, &h->ev_join}) {
         if (hipEventCreate(e) != hipSuccess) { handle_free(h); return hip_fail(rt, hipErrorOutOfMemory); }
     }
-    hipError_t e = coop::launch_init_ctx(h->ctx, h->work, sz.grid, sz.mode, sz.block,
-                                         o ? o->sched_seed : 0, sz.sched_p16, sz.watchdog_ticks,
-                                         sz.startup_ticks, host, stream);
+    coop::Cfg& cfg = h->cfg;
+    cfg.N = sz.grid;
+    cfg.mode = sz.mode;
+    cfg.sched_p16 = sz.sched_p16;
+    cfg.sched_seed = o ? o->sched_seed : 0;
+    cfg.watchdog_ticks = sz.watchdog_ticks;
+    cfg.host = host;
+    cfg.trace = o ? o->d_trace : nullptr;
+    cfg.trace_cap = (o && o->d_trace) ? o->trace_cap : 0u;
+    cfg.epoch0_wait = sz.startup_ticks;
+    cfg.wgtrace = o ? o->d_wgtrace : nullptr;
+    cfg.wgtrace_cap = (o && o->d_wgtrace) ? o->trace_cap : 0u;
+    hipError_t e = coop::launch_init_ctx(h->ctx, h->work, stream);
     if (e != hipSuccess) { handle_free(h); return hip_fail(rt, e); }
     *hout = h;
     return COOP_OK;
@@ -309,13 +321,16 @@ hipError_t relaunch(coop_handle* h, bool joiner, uint32_t grid, hipStream_t s) {
 }
 
 int fill_traversal(coop_handle* h, const coop_graph* g, const uint32_t* roots, uint32_t nroots,
-                   uint64_t out_stride, const coop_launch_opts* o, coop::TraversalArgs* t, bool heavy) {
+                   uint64_t out_stride, const coop_launch_opts* o, coop::TraversalArgs* t, bool heavy,
+                   bool queues) {
+    t->cfg = h->cfg;
     t->ctx = h->ctx;
     t->work = h->work;
     t->row_ptr = g->row_ptr;
     t->col = g->col;
     t->w = g->w;
     t->n = g->n;
+    t->N = h->grid;
     t->heavy_th = (o && o->heavy_threshold) ? o->heavy_threshold : kDefaultHeavy;
     t->strip = (o && o->strip) ? o->strip : kDefaultStrip;
     t->roots = roots;
@@ -329,10 +344,19 @@ int fill_traversal(coop_handle* h, const coop_graph* g, const uint32_t* roots, u
         t->heavy = static_cast<uint4*>(scratch(h, hs * sizeof(uint4)));
         if (!t->heavy) return COOP_E_OOM;
     }
-    for (int i = 0; i < 2; ++i) {
-        t->frontier[i] = static_cast<uint32_t*>(scratch(h, (size_t)g->n * 4 + 4));
-        if (!t->frontier[i]) return COOP_E_OOM;
+    t->frontier[0] = t->frontier[1] = nullptr;
+    if (queues) {
+        for (int i = 0; i < 2; ++i) {
+            t->frontier[i] = static_cast<uint32_t*>(scratch(h, (size_t)g->n * 4 + 4));
+            if (!t->frontier[i]) return COOP_E_OOM;
+        }
     }
+    const size_t slot_words = (size_t)h->grid * coop::kSlotWords;
+    t->slots = static_cast<uint32_t*>(scratch(h, slot_words * 4));
+    if (!t->slots) return COOP_E_OOM;
+    h->slots = t->slots;
+    hipError_t e = coop::launch_fill_u32(t->slots, slot_words, 0u, h->stream);
+    if (e != hipSuccess) return hip_fail(h->rt, e);
     return COOP_OK;
 }
 
@@ -453,6 +477,7 @@ int coop_graph_wrap(coop_rt* rt, const uint32_t* d_row_ptr, const uint32_t* d_co
     g->arcs = arcs;
     g->deg.resize(n);
     g->max_deg = 0;
+    g->words = (uint32_t)((((uint64_t)n + 31) / 32 + 63) / 64 * 64);
     for (uint32_t v = 0; v < n; ++v) {
         if (rp[v + 1] < rp[v]) { delete g; return COOP_E_INVALID; }
         g->deg[v] = rp[v + 1] - rp[v];
@@ -464,6 +489,10 @@ int coop_graph_wrap(coop_rt* rt, const uint32_t* d_row_ptr, const uint32_t* d_co
 
 int coop_graph_release(coop_graph* g) {
     if (!g) return COOP_E_INVALID;
+    if (g->deg0) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(g->deg0);
+    }
     delete g;
     return COOP_OK;
 }
@@ -480,10 +509,31 @@ int coop_bfs(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_t
     coop_handle* h = nullptr;
     if ((rc = begin_launch(rt, opts, sz, COOP_KERNEL_BFS, s, &h))) return rc;
     coop::BfsArgs& a = h->bfs;
-    if ((rc = fill_traversal(h, g, d_roots, nroots, out_stride, opts, &a.t, true))) { handle_free(h); return rc; }
-    a.bitmap = static_cast<uint32_t*>(scratch(h, ((size_t)g->n + 31) / 32 * 4));
+    if ((rc = fill_traversal(h, g, d_roots, nroots, out_stride, opts, &a.t, true, false))) {
+        handle_free(h);
+        return rc;
+    }
+    coop_graph* gm = const_cast<coop_graph*>(g);
+    if (!gm->deg0) {
+        hipError_t e = hipMalloc(&gm->deg0, (size_t)gm->words * 4);
+        if (e == hipSuccess) e = coop::launch_deg0_bitmap(g->row_ptr, g->n, gm->deg0, gm->words, s);
+        if (e != hipSuccess) {
+            if (gm->deg0) (void)hipFree(gm->deg0);
+            gm->deg0 = nullptr;
+            handle_free(h);
+            return hip_fail(rt, e);
+        }
+    }
+    a.words = g->words;
+    a.vis = static_cast<uint32_t*>(scratch(h, (size_t)a.words * 4));
+    for (int i = 0; i < 3; ++i) a.fb[i] = static_cast<uint32_t*>(scratch(h, (size_t)a.words * 4));
+    a.deg0 = gm->deg0;
     a.level_out = d_level;
-    if (!a.bitmap) { handle_free(h); return COOP_E_OOM; }
+    a.direction_opt = (opts && (opts->flags & COOP_F_TOP_DOWN_ONLY)) ? 0u : 1u;
+    a.alpha = 14;
+    a.beta = 24;
+    a.total_arcs = g->arcs;
+    if (!a.vis || !a.fb[0] || !a.fb[1] || !a.fb[2]) { handle_free(h); return COOP_E_OOM; }
     (void)hipEventRecord(h->ev_init, s);
     (void)hipEventRecord(h->ev_start, s);
     return finish_launch(rt, h, relaunch(h, false, h->grid, s), out);
@@ -502,12 +552,13 @@ int coop_sssp(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_
     coop_handle* h = nullptr;
     if ((rc = begin_launch(rt, opts, sz, COOP_KERNEL_SSSP, s, &h))) return rc;
     coop::SsspArgs& a = h->sssp;
-    if ((rc = fill_traversal(h, g, d_roots, nroots, out_stride, opts, &a.t, true))) { handle_free(h); return rc; }
-    a.stamp = static_cast<uint32_t*>(scratch(h, (size_t)g->n * 4));
+    if ((rc = fill_traversal(h, g, d_roots, nroots, out_stride, opts, &a.t, true, true))) {
+        handle_free(h);
+        return rc;
+    }
+    a.state = static_cast<uint64_t*>(scratch(h, (size_t)g->n * 8));
     a.dist_out = d_dist;
-    if (!a.stamp) { handle_free(h); return COOP_E_OOM; }
-    hipError_t e = coop::launch_fill_u32(a.stamp, g->n, 0u, s);
-    if (e != hipSuccess) { handle_free(h); return hip_fail(rt, e); }
+    if (!a.state) { handle_free(h); return COOP_E_OOM; }
     (void)hipEventRecord(h->ev_init, s);
     (void)hipEventRecord(h->ev_start, s);
     return finish_launch(rt, h, relaunch(h, false, h->grid, s), out);
@@ -527,7 +578,7 @@ static int color_or_mis(coop_rt* rt, const coop_graph* g, uint64_t seed, uint32_
     coop::ColorArgs& a = h->color;
     static const uint32_t dummy_root = 0;
     (void)dummy_root;
-    if ((rc = fill_traversal(h, g, nullptr, 1, 0, opts, &a.t, false))) { handle_free(h); return rc; }
+    if ((rc = fill_traversal(h, g, nullptr, 1, 0, opts, &a.t, false, true))) { handle_free(h); return rc; }
     a.prio_seed = seed;
     a.pending = static_cast<uint32_t*>(scratch(h, (size_t)g->n * 4));
     a.colour_out = colour;
@@ -575,6 +626,7 @@ int coop_launch(coop_rt* rt, int kernel_id, const coop_params* p, const coop_lau
             hipStream_t s = reinterpret_cast<hipStream_t>(stream);
             coop_handle* h = nullptr;
             if ((rc = begin_launch(rt, opts, sz, COOP_KERNEL_BARRIER, s, &h))) return rc;
+            h->bb.cfg = h->cfg;
             h->bb.ctx = h->ctx;
             h->bb.work = h->work;
             h->bb.iters = p->barrier_iters;
@@ -599,8 +651,18 @@ int coop_wait(coop_handle* h, coop_stats* stats) {
     if (e == hipSuccess && h->joined) e = hipEventSynchronize(h->ev_join);
     Ctx c;
     Work w;
+    std::vector<uint64_t> slots(h->slots ? (size_t)h->grid * coop::kSlotWords / 2 : 0);
     if (e == hipSuccess) e = hipMemcpy(&c, h->ctx, offsetof(Ctx, join_entry), hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(&w, h->work, sizeof(Work), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && h->slots)
+        e = hipMemcpy(slots.data(), h->slots, slots.size() * 8, hipMemcpyDeviceToHost);
+    uint64_t arcs = 0, rows = 0, words = 0, found = 0;
+    for (size_t i = 0; i + 8 <= slots.size(); i += 8) {
+        arcs += slots[i + coop::kSlotArcs];
+        rows += slots[i + coop::kSlotRows];
+        words += slots[i + coop::kSlotBitmap];
+        found += slots[i + coop::kSlotFoundAll];
+    }
     float ms = 0.f;
     if (e == hipSuccess) (void)hipEventElapsedTime(&ms, h->ev_start, h->ev_end);
     int rc = COOP_OK;
@@ -615,14 +677,23 @@ int coop_wait(coop_handle* h, coop_stats* stats) {
             stats->forks = c.forks;
             stats->resizes = c.resizes;
             stats->min_groups = c.min_M == 0xFFFFFFFFu ? (h->coop ? 1u : h->grid) : c.min_M;
+            if (c.min_M == 0xFFFFFFFFu && h->coop && c.max_M == 0) stats->min_groups = 1;
             stats->max_groups = c.max_M ? c.max_M : (h->coop ? 1u : h->grid);
             stats->final_groups = c.final_M;
             stats->grid = h->grid;
-            stats->levels = w.levels_total;
+            stats->levels = w.x.levels_total;
             stats->kernel_ms = ms;
             stats->device_ms = (c.t_end > c.t_start && c.t_start)
                                    ? (double)(c.t_end - c.t_start) / (double)rt->wall_khz
                                    : 0.0;
+            stats->arcs = arcs;
+            stats->rows = rows;
+            stats->found = found;
+            stats->bitmap_words = words;
+            stats->td_levels = w.x.td_levels;
+            stats->bu_levels = w.x.bu_levels;
+            stats->heavy_phases = w.x.heavy_phases;
+            stats->reserved = 0;
         }
     }
     std::lock_guard<std::recursive_mutex> lk(rt->mu);

@@ -46,12 +46,13 @@ def modes(coop):
         "plain": coop.make_opts(coop.COOP_MODE_PLAIN),
         "coop": coop.make_opts(coop.COOP_MODE_COOP),
         "coop_host": coop.make_opts(coop.COOP_MODE_COOP, flags=coop.COOP_F_HOST_SCHEDULE),
+        "coop_topdown": coop.make_opts(coop.COOP_MODE_COOP, flags=coop.COOP_F_TOP_DOWN_ONLY),
     }
 
 
 # ------------------------------------------------------------------ BFS
 
-@pytest.mark.parametrize("mode", ["plain", "coop", "coop_host"])
+@pytest.mark.parametrize("mode", ["plain", "coop", "coop_host", "coop_topdown"])
 def test_bfs_er4096(rt, coop_mod, gg, mode):
     g = gg.er(4096, 8, 1)
     say(f"bfs er4096 mode={mode}")
@@ -91,13 +92,14 @@ def test_bfs_rmat_heavy_strips(rt, coop_mod, gg, th, strip):
     say(f"bfs rmat14 heavy_th={th} strip={strip}")
     dg = rt.graph(g)
     exp = oracle.bfs(g, src)
-    for mode in ("plain", "coop"):
+    for mode in ("plain", "coop", "coop_topdown"):
         o = modes(coop_mod)[mode]
         o.heavy_threshold = th
         o.strip = strip
         rc, lv, st = rt.bfs(dg, [src], o)
         assert rc == 0, coop_mod.coop_strerror(rc)
         assert np.array_equal(as_u32(lv), exp), mode
+        say(f"  {mode}: td={st['td_levels']} bu={st['bu_levels']} heavy={st['heavy_phases']} arcs={st['arcs']}")
     dg.release()
 
 
@@ -106,7 +108,7 @@ def test_bfs_multi_root(rt, coop_mod, gg):
     roots = gg.sources(g, 2, 6)
     say(f"bfs multi-root rmat13 roots={roots.tolist()}")
     dg = rt.graph(g)
-    for mode in ("plain", "coop"):
+    for mode in ("plain", "coop", "coop_topdown"):
         rc, lv, st = rt.bfs(dg, roots, modes(coop_mod)[mode])
         assert rc == 0
         got = lv.cpu().numpy().view(np.uint32)
@@ -121,7 +123,7 @@ def test_bfs_small_groups(rt, coop_mod, gg):
     say("bfs er20000 narrow launches")
     dg = rt.graph(g)
     exp = oracle.bfs(g, 3)
-    for mode in ("plain", "coop"):
+    for mode in ("plain", "coop", "coop_topdown"):
         for ng, gs in ((1, 64), (3, 128), (7, 256), (40, 1024)):
             o = modes(coop_mod)[mode]
             o.num_groups = ng
@@ -152,6 +154,29 @@ def test_sssp(rt, coop_mod, gg, name):
     dg.release()
 
 
+def test_sssp_multi_root(rt, coop_mod, gg):
+    g = gg.add_weights(gg.rmat(12, 16, seed=9), 3, 1, 255)
+    roots = gg.sources(g, 4, 5)
+    say(f"sssp multi-root rmat12 roots={roots.tolist()}")
+    dg = rt.graph(g)
+    for mode in ("plain", "coop"):
+        rc, d, st = rt.sssp(dg, roots, modes(coop_mod)[mode])
+        assert rc == 0, coop_mod.coop_strerror(rc)
+        got = d.cpu().numpy()
+        for i, r in enumerate(roots):
+            assert np.array_equal(got[i], oracle.sssp(g, int(r))), (mode, i)
+    dg.release()
+
+
+def test_sssp_overflow_reported(rt, coop_mod, gg):
+    g = gg.constant_weights(gg.path(6), 1_000_000_000)
+    say("sssp overflow path")
+    dg = rt.graph(g)
+    rc, d, st = rt.sssp(dg, [0], modes(coop_mod)["coop"])
+    assert rc == coop_mod.COOP_E_OVERFLOW
+    dg.release()
+
+
 @pytest.mark.parametrize("seed", range(8))
 def test_sssp_random_schedule_park(rt, coop_mod, gg, seed):
     """Seeded kill/fork schedule (target redrawn at a quarter of the
@@ -168,6 +193,25 @@ def test_sssp_random_schedule_park(rt, coop_mod, gg, seed):
     assert np.array_equal(d.cpu().numpy(), exp)
     assert st["kills"] > 0 and st["forks"] > 0 and st["resizes"] > 0
     say(f"  rounds={st['levels']} kills={st['kills']} forks={st['forks']} M in [{st['min_groups']},{st['max_groups']}]")
+    dg.release()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_bfs_rmat_random_schedule(rt, coop_mod, gg, seed):
+    """Direction-optimizing BFS under seeded kill/fork schedules (parked)."""
+    g = gg.rmat(15, 16, seed=7)
+    src = int(gg.sources(g, 5, 1)[0])
+    say(f"bfs rmat15 random schedule seed={seed}")
+    dg = rt.graph(g)
+    exp = oracle.bfs(g, src)
+    o = coop_mod.make_opts(coop_mod.COOP_MODE_COOP,
+                           flags=coop_mod.COOP_F_RANDOM_SCHEDULE | coop_mod.COOP_F_PARK_KILLED,
+                           sched_seed=100 + seed, sched_p=0.6, num_groups=64, group_size=256,
+                           heavy_threshold=32, strip=256)
+    rc, lv, st = rt.bfs(dg, [src], o)
+    assert rc == 0, coop_mod.coop_strerror(rc)
+    assert np.array_equal(as_u32(lv), exp)
+    say(f"  td={st['td_levels']} bu={st['bu_levels']} kills={st['kills']} forks={st['forks']}")
     dg.release()
 
 
