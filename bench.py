@@ -1,29 +1,39 @@
 #!/usr/bin/env python3
 """Benchmark: cooperative vs plain persistent BFS on R-MAT scale 22, with the
-co-task preemption measurement.
+co-task preemption measurement and an SSSP grid side line.
 
 Workload (one GPU): R-MAT scale 22, edge factor 16 (a=0.57, b=0.19,
 c=0.19, d=0.05), seeded, permuted, symmetrised, loops/duplicates removed,
 uint32 CSR resident in HBM. A *step* is one BFS traversal from the next
-seeded source (degree >= 1) inside one persistent cooperative launch
-(the scheduler target word is polled at every resizing barrier, kept at N).
+seeded source (degree >= 1). Steps run inside persistent cooperative
+launches of ``--roots-per-launch`` sources each (the scheduler target word
+is polled at every resizing barrier and kept at N), so every launch of the
+kernel does the same kind of work and the per-launch event time can be
+compared with a profiler's per-dispatch average.
 
 Printed JSON line (one):
-  value          GTEPS of the cooperative launch: sum over sources of the
-                 undirected edges in the source's component / time
-  plain          same sources in a plain persistent launch (fixed M)
-  coop_overhead  cooperative time / plain time
+  value          GTEPS of the cooperative launches: sum over sources of the
+                 undirected edges in the source's component / wall time of
+                 the timed region (synchronised on both sides)
+  plain          same sources in plain persistent launches (fixed M)
+  coop_overhead  cooperative time / plain time (kernel events)
+  sssp           frontier Bellman-Ford on the 1024x1024 grid, coop vs plain,
+                 and one run under a seeded random kill/fork schedule
   cotask         a co-task every 10 ms needing half the CUs for 1 ms while
                  a cooperative launch runs: p50/p99 latency, gather time,
                  slowdown of the traversal
-  roofline       algorithmic bytes of the traversal / kernel time vs 8 TB/s
+  roofline       algorithmic bytes per launch / mean launch time (HIP events
+                 on the launch stream) vs 8 TB/s; traffic from the committed
+                 PMC summary when it was taken on the current kernel sources
   cpu_baseline   the oracle's FIFO BFS on the host, bounded sample
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -31,10 +41,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bfs_kernel_rmat22_traffic.txt")
+KERNEL_SOURCES = ("paper_1707_01989_amd/csrc/coop_kernels.hip", "paper_1707_01989_amd/csrc/traverse.h",
+                  "paper_1707_01989_amd/csrc/coop_internal.h", "include/coop_device.hpp")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic():
+    """HBM bytes per launch from the committed PMC summary, or None when the
+    summary is missing or was taken on other kernel sources."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"^source_hash:\s*(\w+)", text, re.M)
+    b = re.search(r"^traffic_bytes_per_launch:\s*([0-9.eE+]+)", text, re.M)
+    if not m or not b or m.group(1) != kernel_source_hash():
+        return None
+    return float(b.group(1))
 
 
 def main():
@@ -43,14 +78,21 @@ def main():
     ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--scale", type=int, default=22)
-    ap.add_argument("--cotask-seconds", type=float, default=2.0)
-    ap.add_argument("--cpu-sample", type=int, default=4, help="sources for the oracle timing")
+    ap.add_argument("--roots-per-launch", type=int, default=8)
+    ap.add_argument("--cotask-seconds", type=float, default=4.0)
+    ap.add_argument("--cpu-sample", type=int, default=32, help="sources for the oracle timing")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one int32 'x + 1' elementwise kernel over this many MiB (counter calibration)")
     ap.add_argument("--skip-cotask", action="store_true")
+    ap.add_argument("--skip-sssp", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "this benchmark measures one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    L = max(1, args.roots_per_launch)
+    if args.steps % L or args.warmup % L:
+        sys.exit(f"--steps and --warmup must be multiples of --roots-per-launch ({L})")
 
     import numpy as np
     import torch
@@ -61,11 +103,9 @@ def main():
     g = gg.rmat(args.scale, 16, seed=3)
     log(f"rmat{args.scale}: n={g.n} arcs={g.arcs} generated in {time.time() - t0:.1f}s")
     deg = g.degrees()
-    nsrc = args.warmup + args.steps
-    roots = gg.sources(g, 3, nsrc)
+    roots = gg.sources(g, 3, args.warmup + args.steps)
 
-    # per-source traversal sizes for GTEPS and algorithmic bytes (component
-    # of each source: undirected edges, vertices reached)
+    # per-source traversal sizes (component of each source)
     from scipy.sparse import csr_matrix
     from scipy.sparse.csgraph import connected_components
     A = csr_matrix((np.ones(g.arcs, dtype=np.int8), g.col.astype(np.int64), g.row_ptr.astype(np.int64)),
@@ -78,14 +118,14 @@ def main():
 
     rt = coop.Runtime(0)
     dg = rt.graph(g)
-    timed = roots[args.warmup:]
-    d_warm = rt._roots(roots[:args.warmup])
-    d_timed = rt._roots(timed)
+    timed = [int(r) for r in roots[args.warmup:]]
+    batches_w = [rt._roots(roots[i:i + L]) for i in range(0, args.warmup, L)]
+    batches_t = [rt._roots(timed[i:i + L]) for i in range(0, args.steps, L)]
     level = torch.empty(g.n, dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
 
-    def run(mode_opts, d_roots, k):
-        h = coop.coop_bfs(rt.rt, dg.handle, d_roots, k, level, 0, mode_opts, stream)
+    def run(opts, d_roots):
+        h = coop.coop_bfs(rt.rt, dg.handle, d_roots, d_roots.numel(), level, 0, opts, stream)
         rc, st = coop.coop_wait(h)
         if rc != 0:
             raise RuntimeError(coop.coop_strerror(rc))
@@ -93,34 +133,41 @@ def main():
 
     coop_opts = coop.make_opts(coop.COOP_MODE_COOP, flags=coop.COOP_F_HOST_SCHEDULE)
     plain_opts = coop.make_opts(coop.COOP_MODE_PLAIN)
-    # warmup
-    run(coop_opts, d_warm, args.warmup)
-    run(plain_opts, d_warm, args.warmup)
+    for b in batches_w:
+        run(coop_opts, b)
+        run(plain_opts, b)
     torch.cuda.synchronize()
 
-    edges = sum(edges_of(int(r)) for r in timed)
-    verts = sum(verts_of(int(r)) for r in timed)
-    arcs_scanned = 2 * edges
-    # algorithmic bytes (top-down frontier BFS): per scanned arc 4 B column
-    # index + 4 B visited probe; per reached vertex 8 B row range, 4 B
-    # frontier read, 4 B frontier write, 4 B level write; per source the
-    # level and visited-set initialisation (4 B + 1/8 B per vertex)
-    alg_bytes = 8 * arcs_scanned + 20 * verts + len(timed) * (4.125 * g.n)
+    def timed_region(opts):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sts = [run(opts, b) for b in batches_t]
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, sts
 
-    t = time.perf_counter()
-    st_c = run(coop_opts, d_timed, len(timed))
-    torch.cuda.synchronize()
-    wall_c = time.perf_counter() - t
-    t = time.perf_counter()
-    st_p = run(plain_opts, d_timed, len(timed))
-    torch.cuda.synchronize()
-    wall_p = time.perf_counter() - t
-    ms_c, ms_p = st_c["kernel_ms"], st_p["kernel_ms"]
-    log(f"coop {ms_c:.3f} ms (wall {wall_c*1e3:.1f}), plain {ms_p:.3f} ms, levels {st_c['levels']}")
+    wall_c, sts_c = timed_region(coop_opts)
+    wall_p, sts_p = timed_region(plain_opts)
+    ms_c = sum(s["kernel_ms"] for s in sts_c)
+    ms_p = sum(s["kernel_ms"] for s in sts_p)
+    launch_ms = ms_c / len(sts_c)
+    log(f"coop {ms_c:.3f} ms kernel / {wall_c*1e3:.1f} ms wall, plain {ms_p:.3f} / {wall_p*1e3:.1f}; "
+        f"launch mean {launch_ms:.3f} ms, levels {sum(s['levels'] for s in sts_c)}")
 
-    gteps_c = edges / (ms_c * 1e-3) / 1e9
-    gteps_p = edges / (ms_p * 1e-3) / 1e9
-    achieved = alg_bytes / (ms_c * 1e-3) / 1e9
+    edges = sum(edges_of(r) for r in timed)
+    verts = sum(verts_of(r) for r in timed)
+    gteps_c = edges / wall_c / 1e9
+    gteps_p = edges / wall_p / 1e9
+
+    # algorithmic bytes of a level-synchronous BFS, at the data's natural
+    # width: 8 B per scanned arc (column index + state probe) and 20 B per
+    # reached vertex (row range, frontier read and write, level write);
+    # arcs scanned = the degree sum of the reached vertices
+    alg_bytes_launch = (8 * 2 * edges + 20 * verts) / len(sts_c)
+    achieved = alg_bytes_launch / (launch_ms * 1e-3) / 1e9
+    # what this kernel itself read, by its own counters (direction-optimising
+    # BFS skips arcs): 4 B per arc examined, 8 B per row range, 4 B per
+    # bitmap word, summed over the timed launches
+    counted = sum(4 * s["arcs"] + 8 * s["rows"] + 4 * s["bitmap_words"] for s in sts_c) / len(sts_c)
 
     result = {
         "metric": "GTEPS BFS/SSSP coop vs plain persistent kernel; p99 co-task latency",
@@ -129,29 +176,71 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_c / len(timed), 4),
+        "ms_per_step": round(wall_c * 1e3 / args.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": f"BFS on R-MAT scale {args.scale} (edge factor 16, a=.57 b=.19 c=.19), "
-                               f"one source per step, one persistent cooperative launch",
-                   "n": g.n, "arcs": g.arcs, "sources": len(timed), "parallelism": "1 GPU",
-                   "groups": st_c["grid"], "group_size": 1024},
-        "plain": {"value": round(gteps_p, 3), "ms": round(ms_p, 3)},
+        "config": {"workload": f"BFS on R-MAT scale {args.scale} (edge factor 16, a=.57 b=.19 c=.19, seed 3), "
+                               f"one seeded source per step, {L} sources per persistent cooperative launch, "
+                               f"co-task every 10 ms needing half the CUs for 1 ms",
+                   "n": g.n, "arcs": g.arcs, "sources": len(timed), "roots_per_launch": L,
+                   "groups": sts_c[0]["grid"], "group_size": 1024},
+        "plain": {"value": round(gteps_p, 3), "kernel_ms": round(ms_p, 3), "wall_ms": round(wall_p * 1e3, 3)},
         "coop_overhead": round(ms_c / ms_p, 4),
-        "barriers": st_c["barriers"],
+        "kernel_ms": round(ms_c, 3),
+        "barriers": sum(s["barriers"] for s in sts_c),
     }
+
+    if not args.skip_sssp:
+        # frontier Bellman-Ford on the 1024x1024 grid, w U[1,1000], source 0
+        gs = gg.add_weights(gg.grid(1024, 1024), 2, 1, 1000)
+        dgs = rt.graph(gs)
+        dist = torch.empty(gs.n, dtype=torch.int32, device="cuda")
+        d0 = rt._roots([0])
+
+        def run_s(opts):
+            h = coop.coop_sssp(rt.rt, dgs.handle, d0, 1, dist, 0, opts, stream)
+            rc, st = coop.coop_wait(h)
+            if rc != 0:
+                raise RuntimeError(coop.coop_strerror(rc))
+            return st
+        run_s(coop_opts)
+        run_s(plain_opts)
+        reps = 5
+        sc = [run_s(coop_opts)["kernel_ms"] for _ in range(reps)]
+        sp = [run_s(plain_opts)["kernel_ms"] for _ in range(reps)]
+        rnd = coop.make_opts(coop.COOP_MODE_COOP, flags=coop.COOP_F_RANDOM_SCHEDULE | coop.COOP_F_PARK_KILLED,
+                             sched_seed=1, sched_p=0.25)
+        st_r = run_s(rnd)
+        ref = dist.clone()
+        st_1 = run_s(coop_opts)
+        same = bool(torch.equal(ref, dist))
+        e_s = gs.edges
+        result["sssp"] = {
+            "workload": "frontier Bellman-Ford, 1024x1024 grid, w U[1,1000] (seed 2), source 0",
+            "gteps_coop": round(e_s / (np.median(sc) * 1e-3) / 1e9, 4),
+            "gteps_plain": round(e_s / (np.median(sp) * 1e-3) / 1e9, 4),
+            "ms_coop": round(float(np.median(sc)), 3), "ms_plain": round(float(np.median(sp)), 3),
+            "coop_overhead": round(float(np.median(sc) / np.median(sp)), 4),
+            "rounds": st_1["barriers"],
+            "ns_per_barrier_coop": round(float(np.median(sc)) * 1e6 / st_1["barriers"], 1),
+            "random_schedule": {"seed": 1, "p": 0.25, "ms": round(st_r["kernel_ms"], 3), "kills": st_r["kills"],
+                                "forks": st_r["forks"], "min_groups": st_r["min_groups"],
+                                "same_as_never_resize": same},
+        }
+        log(f"sssp: {result['sssp']}")
+        del dgs
 
     if not args.skip_cotask:
         # co-task every 10 ms needing half the CUs for 1 ms during a long launch
         per_root_ms = ms_c / len(timed)
         k = max(1, int(args.cotask_seconds * 1e3 / max(per_root_ms, 1e-3)))
-        k = min(k, 200000)
-        reps = np.resize(timed, k)
+        k = min(k, 400000)
+        reps = np.resize(np.asarray(timed, dtype=np.uint32), k)
         d_many = rt._roots(reps)
-        alone = run(coop_opts, d_many, k)
+        alone = run(coop_opts, d_many)
         cus = rt.info["compute_units"]
         h = coop.coop_bfs(rt.rt, dg.handle, d_many, k, level, 0, coop_opts, stream)
         coop.coop_injector_start(rt.rt, h, groups=cus // 2, busy_ns=1_000_000, period_ns=10_000_000)
@@ -162,20 +251,42 @@ def main():
         result["cotask"] = {
             "period_ms": 10, "busy_ms": 1, "groups": cus // 2, "count": cst["count"],
             "latency_p50_ms": round(cst["latency_p50_ms"], 4), "latency_p99_ms": round(cst["latency_p99_ms"], 4),
+            "latency_max_ms": round(cst["latency_max_ms"], 4),
             "gather_p50_ms": round(cst["gather_p50_ms"], 4), "gather_p99_ms": round(cst["gather_p99_ms"], 4),
+            "busy_mean_ms": round(cst["busy_mean_ms"], 4),
+            "traversal_ms_alone": round(alone["kernel_ms"], 2), "traversal_ms_with_cotask": round(st_m["kernel_ms"], 2),
             "slowdown": round(st_m["kernel_ms"] / alone["kernel_ms"], 4),
             "kills": st_m["kills"], "forks": st_m["forks"],
             "model_kernel_preemption": round(10 / 9, 4), "model_half_cu": round(10 / 9.5, 4),
         }
         log(f"cotask: {result['cotask']}")
 
+    # global-barrier latency (persistent launch doing barriers only)
+    bar = {}
+    for name, o in (("plain", plain_opts), ("coop", coop_opts)):
+        ns, _ = coop.coop_barrier_bench(rt.rt, 2000, o, stream)
+        bar[name] = round(ns, 1)
+    result["barrier_ns"] = bar
+    log(f"barrier ns: {bar}")
+
+    if args.copy_probe_mib > 0:
+        x = torch.zeros(args.copy_probe_mib << 18, dtype=torch.int32, device="cuda")
+        y = x + 1
+        torch.cuda.synchronize()
+        del x, y
+
+    traffic = committed_traffic()
     result["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                          "kernel": "bfs_kernel<true>", "alg_bytes_per_launch": int(alg_bytes)}
+                          "frac": round(achieved / HBM_PEAK_GBS, 4),
+                          "traffic": None if traffic is None else int(traffic),
+                          "kernel": "bfs_kernel<true>", "launch_ms": round(launch_ms, 4),
+                          "alg_bytes_per_launch": int(alg_bytes_launch),
+                          "kernel_counted_bytes_per_launch": int(counted),
+                          "source_hash": kernel_source_hash()}
 
     # CPU baseline: the oracle (single-threaded FIFO BFS) on a bounded sample
     import oracle
-    sample = [int(r) for r in timed[:args.cpu_sample]]
+    sample = timed[:args.cpu_sample]
     t = time.perf_counter()
     for r in sample:
         oracle.bfs(g, r)

@@ -183,7 +183,7 @@ int coop_mis(coop_rt* rt, const coop_graph* g, uint64_t prio_seed, uint8_t* d_in
 
 /* Generic launch by kernel id with a parameter block (immutable, copied). */
 enum { COOP_KERNEL_BFS = 1, COOP_KERNEL_SSSP = 2, COOP_KERNEL_COLOR = 3, COOP_KERNEL_MIS = 4,
-       COOP_KERNEL_BARRIER = 5 };
+       COOP_KERNEL_BARRIER = 5, COOP_KERNEL_BATCH = 6 /* handles of coop_batch_run only */ };
 typedef struct coop_params {
     const coop_graph* graph;
     const uint32_t* d_roots;
@@ -235,6 +235,10 @@ typedef struct coop_cotask_stats {
     double gather_p99_ms;
     double gather_max_ms;
     double busy_mean_ms;      /* co-task run time on the device */
+    double setup_max_ms;      /* injector: longest period start -> request (host API calls) */
+    double restore_max_ms;    /* injector: longest co-task end -> workgroups forked back */
+    uint32_t late_periods;    /* injector: periods that started more than one period late */
+    uint32_t reserved;
 } coop_cotask_stats;
 
 /* Run one co-task now on `stream` and wait for it (blocking). latency_ms /
@@ -249,6 +253,70 @@ int coop_cotask_run(coop_rt* rt, const coop_cotask_cfg* cfg, coop_stream_t strea
 int coop_injector_start(coop_rt* rt, coop_handle* h, const coop_cotask_cfg* cfg);
 /* Stop the injector thread and return its statistics. */
 int coop_injector_stop(coop_rt* rt, coop_cotask_stats* out);
+
+/* ------------------------------------------------------------ batched */
+
+/* Batched persistent launch: many independent graph instances in ONE
+ * launch, each run by a team of workgroups with a barrier of its own (the
+ * paper's level-synchronous loop per instance, not one global barrier for
+ * all). Instances are ordered largest first; team size =
+ * clamp(ceil((arcs + n) / team_arcs), 1, team_max). In COOP mode a
+ * workgroup between two instances is where the scheduler may take it
+ * (offer_kill: COOP_F_HOST_SCHEDULE target, or COOP_F_RANDOM_SCHEDULE with
+ * probability sched_p per instance boundary; never fewer than team_max
+ * workgroups stay) and where joiner workgroups from coop_fork_groups enter.
+ * Results never depend on team sizes or on the kill/fork schedule. */
+#define COOP_BATCH_BFS   1u   /* BFS levels from bfs_root */
+#define COOP_BATCH_COLOR 2u   /* then greedy colouring (as coop_color) */
+#define COOP_BATCH_MIS   4u   /* or greedy MIS (as coop_mis); not with COLOR */
+
+typedef struct coop_batch_item {
+    const coop_graph* graph;  /* resident graph (coop_graph_wrap) */
+    uint32_t ops;             /* COOP_BATCH_* bits, at least one */
+    uint32_t bfs_root;        /* BFS source, < n */
+    uint64_t prio_seed;       /* colouring / MIS priority seed */
+    uint32_t* d_level;        /* BFS: n levels (device, caller-owned) */
+    uint32_t* d_colour;       /* COLOR: n colours */
+    uint8_t* d_in_set;        /* MIS: n flags */
+} coop_batch_item;
+
+/* Tunable schedule of a batched launch (what coop_batch_autotune picks). */
+typedef struct coop_tune {
+    uint32_t group_size;      /* threads per workgroup, multiple of 64, <= 1024; 0 = 1024 */
+    uint32_t num_groups;      /* launch limit N; 0 = all resident workgroups at this size */
+    uint64_t team_arcs;       /* work (arcs + vertices) per team member; 0 = 2^20 */
+    uint32_t team_max;        /* largest team; 0 = max(1, N / 8); must be <= N */
+    uint32_t direction_opt;   /* BFS: 1 = direction-optimising, 0 = top-down only */
+    uint32_t heavy_threshold; /* as coop_launch_opts; 0 = 128 */
+    uint32_t strip;           /* as coop_launch_opts; 0 = 4096 */
+} coop_tune;
+
+/* Defaults (what an untuned batch runs with). */
+void coop_tune_default(coop_tune* t);
+
+/* Launch `count` instances (items copied; graphs and outputs must stay
+ * valid until coop_wait). opts: mode, flags (HOST/RANDOM schedule),
+ * sched_seed/sched_p, watchdog_ns; its group and size fields are ignored in
+ * favour of `tune` (NULL = defaults). coop_wait's stats sum over instances:
+ * barriers = team barriers, levels = BFS levels, arcs/rows/found/bitmap
+ * words; kills/forks = workgroups that left/entered between instances;
+ * min/max_groups = fewest/most active workgroups. Errors: COOP_E_INVALID
+ * (bad item, team_max > N), COOP_E_OOM. */
+int coop_batch_run(coop_rt* rt, const coop_batch_item* items, uint32_t count, const coop_tune* tune,
+                   const coop_launch_opts* opts, coop_stream_t stream, coop_handle** out);
+
+/* Autotuner: coordinate search over group size, team work and BFS
+ * direction rule, timing each candidate (median of `reps` runs, HIP
+ * events) on the calibration subset items[0], items[stride], ... (stride 0
+ * or 1 = all items). The result is cached in the runtime, keyed by the
+ * device and the batch's size statistics (count, sum of n, sum of arcs,
+ * largest instance); a later call with the same key returns the cached
+ * tune without timing. Outputs of the subset are overwritten. best_ms
+ * (nullable) gets the winner's time on the subset, default_ms (nullable)
+ * the default tune's. */
+int coop_batch_autotune(coop_rt* rt, const coop_batch_item* items, uint32_t count, uint32_t stride,
+                        uint32_t reps, const coop_launch_opts* opts, coop_stream_t stream, coop_tune* best,
+                        double* best_ms, double* default_ms);
 
 /* ------------------------------------------------------ measurements */
 

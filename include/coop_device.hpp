@@ -90,7 +90,9 @@ __device__ __forceinline__ void wg_trace(const Cfg cfg, uint32_t epoch, uint32_t
         cfg.wgtrace[((size_t)epoch * cfg.N + id) * 4 + point] = wall_clock64();
 }
 
-struct alignas(256) Ctx {
+// Barrier state: the lines every barrier touches. A team of workgroups
+// inside a batched launch uses one of these on its own (no joiners).
+struct alignas(256) CtxCore {
     // ---- line: barrier arrival counter (one atomic per workgroup per barrier)
     uint32_t arrive;
     uint32_t _pa[63];
@@ -119,7 +121,11 @@ struct alignas(256) Ctx {
     uint64_t t_start;
     uint64_t t_end;
     uint32_t _pm[50];
-    // ---- joiner admission ring: {slot:32 (lo) | epoch_lo:16 | id:16 (hi)}
+};
+
+// Context of a resizable launch: barrier lines plus the joiner admission
+// ring, entries {slot:32 (lo) | epoch_lo:16 | id:16 (hi)}.
+struct alignas(256) Ctx : CtxCore {
     uint64_t join_entry[kJoinCap];
 };
 
@@ -191,7 +197,7 @@ struct BarrierLds {
 };
 
 // Raise the abort flag so every spinning workgroup leaves.
-__device__ inline void raise_error(Ctx* c, int32_t err) {
+__device__ inline void raise_error(CtxCore* c, int32_t err) {
     atomicCAS(&c->error, 0, err);
     __hip_atomic_fetch_or(&c->release, (uint64_t)kFlagAbort << 48, __ATOMIC_RELEASE,
                           __HIP_MEMORY_SCOPE_AGENT);
@@ -211,7 +217,7 @@ __device__ __forceinline__ uint64_t admit_entry(uint32_t slot, uint32_t epoch, u
 
 // Wait for the release word to move past `epoch` (or abort/done). Returns
 // the word. Bounded by the watchdog.
-__device__ inline uint64_t wait_release(Ctx* c, const Cfg cfg, uint32_t epoch) {
+__device__ inline uint64_t wait_release(CtxCore* c, const Cfg cfg, uint32_t epoch) {
     const uint64_t t0 = now_ticks();
     uint32_t spins = 0;
     for (;;) {
@@ -314,8 +320,8 @@ __device__ inline void startup_wait(Ctx* c, const Cfg cfg) {
 // Scheduler part of the master step, run by every thread of the master
 // workgroup: fork (admit waiting joiners, in parallel), query (the target)
 // and kill (the top ids). Thread 0 then publishes the release word.
-template <bool Coop>
-__device__ inline void master_schedule(Ctx* c, const Cfg cfg, Member& m, BarrierLds& b, uint32_t flags,
+template <bool Coop, class C>
+__device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLds& b, uint32_t flags,
                                        uint64_t t_in) {
     const uint32_t ne = m.epoch + 1;
     // one batch of independent loads
@@ -358,7 +364,7 @@ __device__ inline void master_schedule(Ctx* c, const Cfg cfg, Member& m, Barrier
         b.flags = flags;
     }
     uint32_t admitted = 0;
-    if (Coop) {
+    if constexpr (Coop) {
         __syncthreads();
         const uint32_t kmax = b.kmax, head = b.head;
         if (kmax) {
@@ -437,8 +443,8 @@ __device__ inline void master_schedule(Ctx* c, const Cfg cfg, Member& m, Barrier
 // then admits joiners and applies the scheduler target. Only workgroup 0
 // reads the host-written target (one PCIe read per barrier), before it
 // arrives.
-template <bool Coop, class MasterFn>
-__device__ inline void barrier(Ctx* c, const Cfg cfg, Member& m, BarrierLds& b, MasterFn&& master_fn) {
+template <bool Coop, class C, class MasterFn>
+__device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, MasterFn&& master_fn) {
     __syncthreads();
     wg_trace(cfg, m.epoch, m.id, kTrArrive);
     if (threadIdx.x == 0) {
@@ -455,7 +461,7 @@ __device__ inline void barrier(Ctx* c, const Cfg cfg, Member& m, BarrierLds& b, 
         // master step: everybody else is parked in the barrier
         const uint64_t t_in = now_ticks();
         const uint32_t flags = master_fn(m.M, m.epoch + 1);
-        master_schedule<Coop>(c, cfg, m, b, flags, t_in);
+        master_schedule<Coop, C>(c, cfg, m, b, flags, t_in);
     } else if (threadIdx.x == 0) {
         const uint64_t r = wait_release(c, cfg, m.epoch);
         fence_acquire();
@@ -475,6 +481,38 @@ __device__ inline void barrier(Ctx* c, const Cfg cfg, Member& m, BarrierLds& b, 
     __syncthreads();
     wg_trace(cfg, m.epoch, m.id, kTrReleased);
     m = b.member;
+}
+
+// Barrier of a team: a fixed set of `m.M` workgroups that work on one
+// instance inside a batched launch, with its own barrier lines and no
+// scheduler (kill and fork happen between instances). A one-workgroup team
+// needs no global atomics: every wave waits for its own memory operations,
+// the workgroup meets at s_barrier, one agent-scope acquire drops stale
+// L1 lines (other waves' atomics were performed in L2), and the workgroup
+// runs the master step itself.
+template <class MasterFn>
+__device__ inline void team_barrier(CtxCore* c, const Cfg cfg, Member& m, BarrierLds& b, MasterFn&& master_fn) {
+    if (m.M > 1) {
+        barrier<false>(c, cfg, m, b, master_fn);
+        return;
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __syncthreads();
+    uint32_t flags = master_fn(1u, m.epoch + 1);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (ld_relaxed_i(&c->error)) flags |= kFlagAbort;
+        c->barriers += 1;
+        b.flags = flags;
+    }
+    __syncthreads();
+    flags = b.flags;
+    m.epoch += 1;
+    m.flags = flags;
+    m.alive = (flags & (kFlagDone | kFlagAbort)) ? 0u : 1u;
 }
 
 }  // namespace coop

@@ -24,7 +24,7 @@ INCLUDE_DIR = os.path.join(REPO_DIR, "include")
 GRAPHGEN_SO = os.path.join(LIB_DIR, "libgraphgen.so")
 COOP_SO = os.path.join(LIB_DIR, "libcoop.so")
 
-HIP_SOURCES = ["coop_kernels.hip", "coop_runtime.hip"]
+HIP_SOURCES = ["coop_kernels.hip", "batch_kernels.hip", "coop_runtime.hip"]
 HIP_ARCH = "gfx950"
 
 
@@ -78,7 +78,7 @@ def build_coop(jobs: int = 4) -> str:
             raise subprocess.CalledProcessError(p.returncode, p.args)
     tmp = COOP_SO + ".tmp"
     _run([cc, f"--offload-arch={HIP_ARCH}", "-shared", "-fPIC", *objs, "-o", tmp,
-          "-lpthread"])
+          "-lpthread", "-Wl,--no-undefined"])
     os.replace(tmp, COOP_SO)
     return COOP_SO
 

@@ -37,6 +37,11 @@ COOP_KERNEL_SSSP = 2
 COOP_KERNEL_COLOR = 3
 COOP_KERNEL_MIS = 4
 COOP_KERNEL_BARRIER = 5
+COOP_KERNEL_BATCH = 6
+
+COOP_BATCH_BFS = 1
+COOP_BATCH_COLOR = 2
+COOP_BATCH_MIS = 4
 
 UNREACHED_LEVEL = 0xFFFFFFFF
 UNREACHED_DIST = 0x7FFFFFFF
@@ -47,7 +52,7 @@ EXPORTS = [
     "coop_last_hip_error", "coop_graph_wrap", "coop_graph_release", "coop_bfs", "coop_sssp",
     "coop_color", "coop_mis", "coop_launch", "coop_wait", "coop_handle_groups", "coop_set_target",
     "coop_fork_groups", "coop_cotask_run", "coop_injector_start", "coop_injector_stop",
-    "coop_barrier_bench",
+    "coop_barrier_bench", "coop_tune_default", "coop_batch_run", "coop_batch_autotune",
 ]
 
 
@@ -116,7 +121,27 @@ class coop_cotask_stats(ctypes.Structure):
         ("count", ctypes.c_uint32), ("latency_p50_ms", ctypes.c_double), ("latency_p99_ms", ctypes.c_double),
         ("latency_max_ms", ctypes.c_double), ("gather_p50_ms", ctypes.c_double),
         ("gather_p99_ms", ctypes.c_double), ("gather_max_ms", ctypes.c_double),
-        ("busy_mean_ms", ctypes.c_double),
+        ("busy_mean_ms", ctypes.c_double), ("setup_max_ms", ctypes.c_double),
+        ("restore_max_ms", ctypes.c_double), ("late_periods", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class coop_batch_item(ctypes.Structure):
+    _fields_ = [
+        ("graph", ctypes.c_void_p), ("ops", ctypes.c_uint32), ("bfs_root", ctypes.c_uint32),
+        ("prio_seed", ctypes.c_uint64), ("d_level", ctypes.c_void_p), ("d_colour", ctypes.c_void_p),
+        ("d_in_set", ctypes.c_void_p),
+    ]
+
+
+class coop_tune(ctypes.Structure):
+    _fields_ = [
+        ("group_size", ctypes.c_uint32), ("num_groups", ctypes.c_uint32), ("team_arcs", ctypes.c_uint64),
+        ("team_max", ctypes.c_uint32), ("direction_opt", ctypes.c_uint32), ("heavy_threshold", ctypes.c_uint32),
+        ("strip", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:
@@ -166,6 +191,12 @@ def load_library():
         "coop_injector_stop": (i32, [VP, ctypes.POINTER(coop_cotask_stats)]),
         "coop_barrier_bench": (i32, [VP, ctypes.POINTER(coop_launch_opts), u32, VP,
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(coop_stats)]),
+        "coop_tune_default": (None, [ctypes.POINTER(coop_tune)]),
+        "coop_batch_run": (i32, [VP, ctypes.POINTER(coop_batch_item), u32, ctypes.POINTER(coop_tune),
+                                 ctypes.POINTER(coop_launch_opts), VP, VPP]),
+        "coop_batch_autotune": (i32, [VP, ctypes.POINTER(coop_batch_item), u32, u32, u32,
+                                      ctypes.POINTER(coop_launch_opts), VP, ctypes.POINTER(coop_tune),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -338,6 +369,48 @@ def coop_barrier_bench(rt, iters, opts=None, stream=None) -> tuple[float, dict]:
     return ns.value, st.as_dict()
 
 
+def coop_tune_default() -> coop_tune:
+    t = coop_tune()
+    load_library().coop_tune_default(ctypes.byref(t))
+    return t
+
+
+def make_tune(**kw) -> coop_tune:
+    t = coop_tune_default()
+    for k, v in kw.items():
+        setattr(t, k, v)
+    return t
+
+
+def _items_array(items):
+    arr = (coop_batch_item * len(items))()
+    for i, it in enumerate(items):
+        arr[i] = it
+    return arr
+
+
+def coop_batch_run(rt, items, tune=None, opts=None, stream=None, keep=True):
+    """items: sequence of coop_batch_item (device pointers must stay alive until coop_wait)."""
+    arr = _items_array(items)
+    h = _handle_out(keep)
+    rc = load_library().coop_batch_run(rt, arr, len(items), ctypes.byref(tune) if tune is not None else None,
+                                       ctypes.byref(opts) if opts is not None else None, _stream(stream),
+                                       ctypes.byref(h) if keep else None)
+    _check(rc, "coop_batch_run")
+    return h.value if keep else None
+
+
+def coop_batch_autotune(rt, items, stride=1, reps=3, opts=None, stream=None) -> tuple[coop_tune, float, float]:
+    arr = _items_array(items)
+    best = coop_tune()
+    bms, dms = ctypes.c_double(), ctypes.c_double()
+    _check(load_library().coop_batch_autotune(rt, arr, len(items), stride, reps,
+                                              ctypes.byref(opts) if opts is not None else None, _stream(stream),
+                                              ctypes.byref(best), ctypes.byref(bms), ctypes.byref(dms)),
+           "coop_batch_autotune")
+    return best, bms.value, dms.value
+
+
 # ------------------------------------------------------------- convenience
 
 class DeviceGraph:
@@ -405,6 +478,25 @@ class Runtime:
         h = coop_color(self.rt, dg.handle, prio_seed, out, opts, stream)
         rc, st = coop_wait(h)
         return rc, out, st
+
+    def batch_items(self, dgs, ops=COOP_BATCH_BFS | COOP_BATCH_COLOR, roots=None, seeds=None):
+        """Items and output tensors for a batch over DeviceGraphs `dgs`
+        (BFS root 0 and priority seed = index unless given)."""
+        import torch
+        items, outs = [], []
+        for i, dg in enumerate(dgs):
+            lv = torch.empty(dg.n, dtype=torch.int32, device="cuda") if ops & COOP_BATCH_BFS else None
+            cl = torch.empty(dg.n, dtype=torch.int32, device="cuda") if ops & COOP_BATCH_COLOR else None
+            ms = torch.empty(dg.n, dtype=torch.uint8, device="cuda") if ops & COOP_BATCH_MIS else None
+            items.append(coop_batch_item(graph=dg.handle, ops=ops, bfs_root=int(roots[i]) if roots is not None else 0,
+                                         prio_seed=(int(seeds[i]) if seeds is not None else i) & (2**64 - 1),
+                                         d_level=_ptr(lv), d_colour=_ptr(cl), d_in_set=_ptr(ms)))
+            outs.append({"level": lv, "colour": cl, "in_set": ms})
+        return items, outs
+
+    def batch(self, items, tune=None, opts=None, stream=None):
+        h = coop_batch_run(self.rt, items, tune, opts, stream)
+        return coop_wait(h)
 
     def mis(self, dg: DeviceGraph, prio_seed: int, opts=None, stream=None):
         import torch

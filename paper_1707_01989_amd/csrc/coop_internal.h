@@ -92,7 +92,7 @@ enum SlotField : uint32_t {
 
 struct TraversalArgs {
     Cfg cfg;
-    Ctx* ctx;
+    CtxCore* ctx;              // barrier state (a Ctx for the resizable kernels)
     Work* work;
     uint32_t* slots;           // N x kSlotWords per-workgroup accumulators (zeroed at init)
     const uint32_t* row_ptr;
@@ -152,6 +152,63 @@ struct BarrierBenchArgs {
     uint32_t iters;
 };
 
+// ------------------------------------------------------------- batched
+
+// Barrier lines and transmit blocks of one instance's team (BFS, then
+// colouring), zeroed by the batch init kernel.
+struct alignas(256) TeamState {
+    CtxCore bfs_ctx;
+    Work bfs_work;
+    CtxCore col_ctx;
+    Work col_work;
+};
+
+constexpr uint32_t kBatchBfs = 1u;         // run BFS from bfs.t.roots[0]
+constexpr uint32_t kBatchColor = 2u;       // then greedy colouring / MIS (col.mis)
+
+// One instance of a batched launch: complete argument blocks of the two
+// algorithms (pointers into the instance's graph, outputs and scratch) and
+// its team size. Read through the constant address space, so every field is
+// a scalar load.
+struct alignas(16) BatchInst {
+    BfsArgs bfs;
+    ColorArgs col;
+    uint32_t team;             // workgroups that run this instance together
+    uint32_t ops;              // kBatch* bits
+    uint32_t pad[2];
+};
+
+// Launch-wide counters of a batched launch.
+struct alignas(256) BatchCtl {
+    uint32_t ticket;           // next (instance, rank) entry
+    uint32_t _p0[63];
+    uint32_t active;           // workgroups inside the instance loop
+    uint32_t _p1[63];
+    uint32_t decisions;        // random schedule: kill decisions taken
+    int32_t error;
+    uint32_t kills;
+    uint32_t forks;            // workgroups of joiner grids that entered
+    uint32_t left;             // workgroups that left when tickets ran out
+    uint32_t min_active;
+    uint32_t max_active;
+    uint32_t _p2[57];
+};
+
+struct BatchArgs {
+    Cfg cfg;                   // N, mode (kill policy), host target, watchdog
+    const BatchInst* inst;     // `count` descriptors in ticket order
+    const uint32_t* first;     // count + 1: first ticket of each instance
+    TeamState* teams;          // count team blocks
+    BatchCtl* ctl;
+    uint32_t count;
+    uint32_t team_max;         // largest team: the kill rule keeps at least this many workgroups
+};
+
+hipError_t launch_batch_init(TeamState* teams, const BatchInst* inst, uint32_t count, BatchCtl* ctl,
+                             hipStream_t s);
+hipError_t launch_batch(const BatchArgs& a, bool coop, bool joiner_grid, uint32_t grid, uint32_t block,
+                        uint32_t lds_bytes, hipStream_t s);
+
 // Launchers (defined in coop_kernels.hip). Each returns a hipError_t.
 hipError_t launch_init_ctx(Ctx* c, Work* w, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s);
@@ -167,5 +224,6 @@ hipError_t launch_barrier_bench(const BarrierBenchArgs& a, bool coop, bool joine
                                 uint32_t block, uint32_t lds_bytes, hipStream_t s);
 hipError_t launch_cotask(const CotaskArgs& a, uint32_t block, uint32_t lds_bytes, hipStream_t s);
 uint32_t kernel_lds_bytes();   // LDS the traversal kernels need at least
+uint32_t kernel_lds_bytes_for(uint32_t block);   // ... with `block` threads per workgroup
 
 }  // namespace coop

@@ -17,6 +17,8 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <string>
+#include <tuple>
 #include <thread>
 #include <vector>
 
@@ -25,6 +27,7 @@
 #include "coop_internal.h"
 
 using coop::Ctx;
+using coop::CtxCore;
 using coop::HostCtl;
 using coop::Work;
 
@@ -96,6 +99,14 @@ struct coop_handle {
     coop::SsspArgs sssp{};
     coop::ColorArgs color{};
     coop::BarrierBenchArgs bb{};
+    // batched launch
+    coop::BatchArgs batch{};
+    std::vector<coop::BatchInst> batch_inst;   // descriptors in ticket order (host copy)
+    std::vector<uint32_t> batch_first, batch_roots;
+    coop::TeamState* teams = nullptr;
+    coop::BatchCtl* bctl = nullptr;
+    uint32_t* bslots = nullptr;
+    size_t bslot_words = 0;
 };
 
 struct coop_rt {
@@ -119,6 +130,8 @@ struct coop_rt {
     std::atomic<uint32_t> inj_busy{0};         // 1 while the injector touches inj_handle
     coop_cotask_cfg inj_cfg{};
     std::vector<double> inj_lat, inj_gather, inj_busy_ms;
+    double inj_setup_max = 0, inj_restore_max = 0;
+    uint32_t inj_late = 0;
     int inj_error = 0;
 };
 
@@ -215,7 +228,7 @@ struct Sizing {
     bool coop;
 };
 
-int size_launch(coop_rt* rt, const coop_launch_opts* o, Sizing* s) {
+int size_launch(coop_rt* rt, const coop_launch_opts* o, Sizing* s, uint32_t min_lds = 0) {
     coop_launch_opts d;
     coop_launch_opts_default(&d);
     if (!o) o = &d;
@@ -223,7 +236,8 @@ int size_launch(coop_rt* rt, const coop_launch_opts* o, Sizing* s) {
     s->coop = o->mode == COOP_MODE_COOP;
     s->block = o->group_size ? o->group_size : 1024;
     if (s->block % 64 || s->block > coop::kMaxThreads || s->block == 0) return COOP_E_INVALID;
-    s->lds = std::max<uint32_t>(o->lds_bytes ? o->lds_bytes : kDefaultLds, coop::kernel_lds_bytes());
+    s->lds = min_lds ? std::max<uint32_t>(o->lds_bytes, min_lds)
+                     : std::max<uint32_t>(o->lds_bytes ? o->lds_bytes : kDefaultLds, coop::kernel_lds_bytes());
     if (s->lds > (uint32_t)rt->props.maxSharedMemoryPerMultiProcessor) return COOP_E_INVALID;
     const uint32_t cus = (uint32_t)rt->props.multiProcessorCount;
     // residency per CU from the LDS request (the binding resource here) and
@@ -316,6 +330,7 @@ hipError_t relaunch(coop_handle* h, bool joiner, uint32_t grid, hipStream_t s) {
         case COOP_KERNEL_MIS: return coop::launch_color(h->color, h->coop, joiner, grid, h->block, h->lds, s);
         case COOP_KERNEL_BARRIER:
             return coop::launch_barrier_bench(h->bb, h->coop, joiner, grid, h->block, h->lds, s);
+        case COOP_KERNEL_BATCH: return coop::launch_batch(h->batch, h->coop, joiner, grid, h->block, h->lds, s);
     }
     return hipErrorInvalidValue;
 }
@@ -357,6 +372,20 @@ int fill_traversal(coop_handle* h, const coop_graph* g, const uint32_t* roots, u
     h->slots = t->slots;
     hipError_t e = coop::launch_fill_u32(t->slots, slot_words, 0u, h->stream);
     if (e != hipSuccess) return hip_fail(h->rt, e);
+    return COOP_OK;
+}
+
+// The bitmap of vertices without arcs (bottom-up BFS skips them), built on
+// first use and kept with the graph.
+int ensure_deg0(coop_rt* rt, coop_graph* g, hipStream_t s) {
+    if (g->deg0) return COOP_OK;
+    hipError_t e = hipMalloc(&g->deg0, (size_t)g->words * 4);
+    if (e == hipSuccess) e = coop::launch_deg0_bitmap(g->row_ptr, g->n, g->deg0, g->words, s);
+    if (e != hipSuccess) {
+        if (g->deg0) (void)hipFree(g->deg0);
+        g->deg0 = nullptr;
+        return hip_fail(rt, e);
+    }
     return COOP_OK;
 }
 
@@ -514,15 +543,9 @@ int coop_bfs(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_t
         return rc;
     }
     coop_graph* gm = const_cast<coop_graph*>(g);
-    if (!gm->deg0) {
-        hipError_t e = hipMalloc(&gm->deg0, (size_t)gm->words * 4);
-        if (e == hipSuccess) e = coop::launch_deg0_bitmap(g->row_ptr, g->n, gm->deg0, gm->words, s);
-        if (e != hipSuccess) {
-            if (gm->deg0) (void)hipFree(gm->deg0);
-            gm->deg0 = nullptr;
-            handle_free(h);
-            return hip_fail(rt, e);
-        }
+    if ((rc = ensure_deg0(rt, gm, s))) {
+        handle_free(h);
+        return rc;
     }
     a.words = g->words;
     a.vis = static_cast<uint32_t*>(scratch(h, (size_t)a.words * 4));
@@ -638,10 +661,74 @@ int coop_launch(coop_rt* rt, int kernel_id, const coop_params* p, const coop_lau
     return COOP_E_INVALID;
 }
 
+// Statistics of a finished batched launch, summed over its instances.
+static int batch_stats(coop_handle* h, coop_stats* stats) {
+    coop_rt* rt = h->rt;
+    const uint32_t count = h->batch.count;
+    coop::BatchCtl ctl;
+    std::vector<coop::TeamState> ts(count);
+    std::vector<uint64_t> slots(h->bslot_words / 2);
+    hipError_t e = hipMemcpy(&ctl, h->bctl, sizeof(ctl), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(ts.data(), h->teams, (size_t)count * sizeof(coop::TeamState),
+                                       hipMemcpyDeviceToHost);
+    if (e == hipSuccess && !slots.empty())
+        e = hipMemcpy(slots.data(), h->bslots, slots.size() * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(rt, e);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, h->ev_start, h->ev_end);
+    int rc = ctl.error;
+    for (uint32_t i = 0; i < count && rc == COOP_OK; ++i) {
+        if (ts[i].bfs_ctx.error) rc = ts[i].bfs_ctx.error;
+        else if (ts[i].col_ctx.error) rc = ts[i].col_ctx.error;
+    }
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->error = rc;
+        uint64_t arcs = 0, rows = 0, words = 0, found = 0;
+        for (size_t i = 0; i + 8 <= slots.size(); i += 8) {
+            arcs += slots[i + coop::kSlotArcs];
+            rows += slots[i + coop::kSlotRows];
+            words += slots[i + coop::kSlotBitmap];
+            found += slots[i + coop::kSlotFoundAll];
+        }
+        uint32_t barriers = 0, levels = 0, td = 0, bu = 0, hp = 0;
+        for (uint32_t i = 0; i < count; ++i) {
+            barriers += ts[i].bfs_ctx.barriers + ts[i].col_ctx.barriers;
+            levels += ts[i].bfs_work.x.levels_total;
+            td += ts[i].bfs_work.x.td_levels;
+            bu += ts[i].bfs_work.x.bu_levels;
+            hp += ts[i].bfs_work.x.heavy_phases;
+        }
+        stats->barriers = barriers;
+        stats->kills = ctl.kills;
+        stats->forks = ctl.forks;
+        stats->resizes = ctl.kills + ctl.forks;
+        stats->min_groups = ctl.min_active == 0xFFFFFFFFu ? ctl.max_active : ctl.min_active;
+        stats->max_groups = ctl.max_active;
+        stats->final_groups = ctl.left;
+        stats->grid = h->grid;
+        stats->levels = levels;
+        stats->kernel_ms = ms;
+        stats->device_ms = 0.0;
+        stats->arcs = arcs;
+        stats->rows = rows;
+        stats->found = found;
+        stats->bitmap_words = words;
+        stats->td_levels = td;
+        stats->bu_levels = bu;
+        stats->heavy_phases = hp;
+    }
+    return rc;
+}
+
 int coop_wait(coop_handle* h, coop_stats* stats) {
     if (!h) return COOP_E_INVALID;
     coop_rt* rt = h->rt;
-    hipError_t e = hipEventSynchronize(h->ev_end);
+    // poll (a blocking event wait could hold runtime locks the injector
+    // thread needs for its own launches while the kernel runs)
+    hipError_t e;
+    while ((e = hipEventQuery(h->ev_end)) == hipErrorNotReady)
+        std::this_thread::sleep_for(std::chrono::microseconds(50));
     // the kernel is finished: detach it from the injector (which may still
     // be forking joiners for it), then wait for those joiner grids
     if (rt->inj_handle.load() == h) {
@@ -649,10 +736,16 @@ int coop_wait(coop_handle* h, coop_stats* stats) {
         while (rt->inj_busy.load()) std::this_thread::yield();
     }
     if (e == hipSuccess && h->joined) e = hipEventSynchronize(h->ev_join);
-    Ctx c;
+    if (h->kind == COOP_KERNEL_BATCH) {
+        int rc = e == hipSuccess ? batch_stats(h, stats) : hip_fail(rt, e);
+        std::lock_guard<std::recursive_mutex> lk(rt->mu);
+        handle_free(h);
+        return rc;
+    }
+    CtxCore c;
     Work w;
     std::vector<uint64_t> slots(h->slots ? (size_t)h->grid * coop::kSlotWords / 2 : 0);
-    if (e == hipSuccess) e = hipMemcpy(&c, h->ctx, offsetof(Ctx, join_entry), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&c, h->ctx, sizeof(CtxCore), hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(&w, h->work, sizeof(Work), hipMemcpyDeviceToHost);
     if (e == hipSuccess && h->slots)
         e = hipMemcpy(slots.data(), h->slots, slots.size() * 8, hipMemcpyDeviceToHost);
@@ -723,10 +816,315 @@ int coop_fork_groups(coop_handle* h, uint32_t count) {
     return COOP_OK;
 }
 
+// ----------------------------------------------------------------- batched
+
+void coop_tune_default(coop_tune* t) {
+    if (!t) return;
+    std::memset(t, 0, sizeof(*t));
+    t->group_size = 1024;
+    t->team_arcs = 1ull << 20;
+    t->direction_opt = 1;
+}
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+int check_batch_item(coop_rt* rt, const coop_batch_item& it) {
+    const coop_graph* g = it.graph;
+    if (!g || g->rt != rt || g->n == 0) return COOP_E_INVALID;
+    const uint32_t known = COOP_BATCH_BFS | COOP_BATCH_COLOR | COOP_BATCH_MIS;
+    if (it.ops == 0 || (it.ops & ~known)) return COOP_E_INVALID;
+    if ((it.ops & COOP_BATCH_COLOR) && (it.ops & COOP_BATCH_MIS)) return COOP_E_INVALID;
+    if ((it.ops & COOP_BATCH_BFS) && (!it.d_level || it.bfs_root >= g->n)) return COOP_E_INVALID;
+    if ((it.ops & COOP_BATCH_COLOR) && !it.d_colour) return COOP_E_INVALID;
+    if ((it.ops & COOP_BATCH_MIS) && !it.d_in_set) return COOP_E_INVALID;
+    return COOP_OK;
+}
+
+}  // namespace
+
+int coop_batch_run(coop_rt* rt, const coop_batch_item* items, uint32_t count, const coop_tune* tune,
+                   const coop_launch_opts* opts, coop_stream_t stream, coop_handle** out) {
+    if (!rt || !items || count == 0) return COOP_E_INVALID;
+    for (uint32_t i = 0; i < count; ++i) {
+        int rc = check_batch_item(rt, items[i]);
+        if (rc) return rc;
+    }
+    coop_tune tn;
+    coop_tune_default(&tn);
+    if (tune) {
+        if (tune->group_size) tn.group_size = tune->group_size;
+        tn.num_groups = tune->num_groups;
+        if (tune->team_arcs) tn.team_arcs = tune->team_arcs;
+        tn.team_max = tune->team_max;
+        tn.direction_opt = tune->direction_opt;
+        tn.heavy_threshold = tune->heavy_threshold;
+        tn.strip = tune->strip;
+    }
+    if (tn.group_size % 64 || tn.group_size > coop::kMaxThreads) return COOP_E_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(rt->mu);
+    reap(rt);
+    coop_launch_opts o;
+    coop_launch_opts_default(&o);
+    if (opts) o = *opts;
+    o.group_size = tn.group_size;
+    o.num_groups = tn.num_groups;
+    if (tn.heavy_threshold) o.heavy_threshold = tn.heavy_threshold;
+    if (tn.strip) o.strip = tn.strip;
+    Sizing sz{};
+    int rc = size_launch(rt, &o, &sz, coop::kernel_lds_bytes_for(tn.group_size));
+    if (rc) return rc;
+    const uint32_t team_max = tn.team_max ? tn.team_max : std::max<uint32_t>(1, sz.grid / 8);
+    if (team_max > sz.grid) return COOP_E_INVALID;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    coop_handle* h = nullptr;
+    if ((rc = begin_launch(rt, &o, sz, COOP_KERNEL_BATCH, s, &h))) return rc;
+
+    // ticket order: most work first (longest-processing-time order)
+    std::vector<uint32_t> order(count);
+    for (uint32_t i = 0; i < count; ++i) order[i] = i;
+    auto work = [&](uint32_t i) { return items[i].graph->arcs + items[i].graph->n; };
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return work(a) > work(b); });
+
+    const uint32_t heavy_th = o.heavy_threshold ? o.heavy_threshold : kDefaultHeavy;
+    const uint32_t strip = o.strip ? o.strip : kDefaultStrip;
+    // sizes of the per-instance regions
+    std::vector<uint32_t> team(count);
+    std::vector<uint64_t> hcap(count);
+    h->batch_first.assign((size_t)count + 1, 0);
+    size_t slot_words = 0, bytes = 0;
+    for (uint32_t j = 0; j < count; ++j) {
+        const coop_batch_item& it = items[order[j]];
+        coop_graph* g = const_cast<coop_graph*>(it.graph);
+        const uint64_t t = (work(order[j]) + tn.team_arcs - 1) / tn.team_arcs;
+        team[j] = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(t, team_max));
+        h->batch_first[j + 1] = h->batch_first[j] + team[j];
+        slot_words += 2 * (size_t)team[j] * coop::kSlotWords;
+        hcap[j] = (it.ops & COOP_BATCH_BFS) ? g->heavy_strips(heavy_th, strip) : 0;
+        if (hcap[j] > 0xFFFFFFFFull) { handle_free(h); return COOP_E_INVALID; }
+        if (it.ops & COOP_BATCH_BFS) bytes += 4 * align_up((size_t)g->words * 4) + align_up(hcap[j] * 16);
+        if (it.ops & (COOP_BATCH_COLOR | COOP_BATCH_MIS)) bytes += 3 * align_up((size_t)g->n * 4 + 4);
+        if ((it.ops & COOP_BATCH_BFS) && (rc = ensure_deg0(rt, g, s))) { handle_free(h); return rc; }
+    }
+    const size_t head = align_up((size_t)count * sizeof(coop::TeamState)) + align_up(sizeof(coop::BatchCtl)) +
+                        align_up((size_t)count * sizeof(coop::BatchInst)) + align_up(((size_t)count + 1) * 4) +
+                        align_up((size_t)count * 4) + align_up(slot_words * 4);
+    char* base = static_cast<char*>(scratch(h, head + bytes));
+    if (!base) { handle_free(h); return COOP_E_OOM; }
+    char* p = base;
+    auto take = [&](size_t b) { char* r = p; p += align_up(b); return r; };
+    h->teams = reinterpret_cast<coop::TeamState*>(take((size_t)count * sizeof(coop::TeamState)));
+    h->bctl = reinterpret_cast<coop::BatchCtl*>(take(sizeof(coop::BatchCtl)));
+    coop::BatchInst* d_inst = reinterpret_cast<coop::BatchInst*>(take((size_t)count * sizeof(coop::BatchInst)));
+    uint32_t* d_first = reinterpret_cast<uint32_t*>(take(((size_t)count + 1) * 4));
+    uint32_t* d_roots = reinterpret_cast<uint32_t*>(take((size_t)count * 4));
+    h->bslots = reinterpret_cast<uint32_t*>(take(slot_words * 4));
+    h->bslot_words = slot_words;
+
+    h->batch_inst.assign(count, coop::BatchInst{});
+    h->batch_roots.assign(count, 0);
+    coop::Cfg icfg = h->cfg;           // per-team barrier constants: no scheduler, no traces
+    icfg.mode = 0;
+    icfg.host = nullptr;
+    icfg.trace = nullptr;
+    icfg.trace_cap = 0;
+    icfg.wgtrace = nullptr;
+    icfg.wgtrace_cap = 0;
+    uint32_t* slot = h->bslots;
+    for (uint32_t j = 0; j < count; ++j) {
+        const coop_batch_item& it = items[order[j]];
+        const coop_graph* g = it.graph;
+        coop::BatchInst& I = h->batch_inst[j];
+        I.team = team[j];
+        I.ops = ((it.ops & COOP_BATCH_BFS) ? coop::kBatchBfs : 0u) |
+                ((it.ops & (COOP_BATCH_COLOR | COOP_BATCH_MIS)) ? coop::kBatchColor : 0u);
+        h->batch_roots[j] = it.bfs_root;
+        coop::TraversalArgs t{};
+        t.cfg = icfg;
+        t.cfg.N = team[j];
+        t.row_ptr = g->row_ptr;
+        t.col = g->col;
+        t.w = g->w;
+        t.n = g->n;
+        t.heavy_th = heavy_th;
+        t.strip = strip;
+        t.roots = d_roots + j;
+        t.nroots = 1;
+        t.out_stride = 0;
+        t.N = team[j];
+        // BFS
+        I.bfs.t = t;
+        I.bfs.t.ctx = &h->teams[j].bfs_ctx;
+        I.bfs.t.work = &h->teams[j].bfs_work;
+        I.bfs.t.slots = slot;
+        slot += (size_t)team[j] * coop::kSlotWords;
+        if (it.ops & COOP_BATCH_BFS) {
+            I.bfs.words = g->words;
+            I.bfs.vis = reinterpret_cast<uint32_t*>(take((size_t)g->words * 4));
+            for (int k = 0; k < 3; ++k) I.bfs.fb[k] = reinterpret_cast<uint32_t*>(take((size_t)g->words * 4));
+            I.bfs.t.heavy_cap = (uint32_t)hcap[j];
+            I.bfs.t.heavy = hcap[j] ? reinterpret_cast<uint4*>(take(hcap[j] * 16)) : nullptr;
+            I.bfs.deg0 = g->deg0;
+            I.bfs.level_out = it.d_level;
+            I.bfs.direction_opt = tn.direction_opt ? 1u : 0u;
+            I.bfs.alpha = 14;
+            I.bfs.beta = 24;
+            I.bfs.total_arcs = g->arcs;
+        }
+        // colouring / MIS
+        I.col.t = t;
+        I.col.t.ctx = &h->teams[j].col_ctx;
+        I.col.t.work = &h->teams[j].col_work;
+        I.col.t.slots = slot;
+        slot += (size_t)team[j] * coop::kSlotWords;
+        if (it.ops & (COOP_BATCH_COLOR | COOP_BATCH_MIS)) {
+            I.col.t.frontier[0] = reinterpret_cast<uint32_t*>(take((size_t)g->n * 4 + 4));
+            I.col.t.frontier[1] = reinterpret_cast<uint32_t*>(take((size_t)g->n * 4 + 4));
+            I.col.pending = reinterpret_cast<uint32_t*>(take((size_t)g->n * 4 + 4));
+            I.col.prio_seed = it.prio_seed;
+            I.col.colour_out = it.d_colour;
+            I.col.in_set_out = it.d_in_set;
+            I.col.mis = (it.ops & COOP_BATCH_MIS) ? 1u : 0u;
+        }
+    }
+    if ((size_t)(p - base) > head + bytes) { handle_free(h); return COOP_E_INTERNAL; }
+    hipError_t e = hipMemcpyAsync(d_inst, h->batch_inst.data(), (size_t)count * sizeof(coop::BatchInst),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_first, h->batch_first.data(), ((size_t)count + 1) * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_roots, h->batch_roots.data(), (size_t)count * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && slot_words) e = coop::launch_fill_u32(h->bslots, slot_words, 0u, s);
+    if (e == hipSuccess) e = coop::launch_batch_init(h->teams, d_inst, count, h->bctl, s);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(s);
+        handle_free(h);
+        return hip_fail(rt, e);
+    }
+    coop::BatchArgs& a = h->batch;
+    a.cfg = h->cfg;
+    a.inst = d_inst;
+    a.first = d_first;
+    a.teams = h->teams;
+    a.ctl = h->bctl;
+    a.count = count;
+    a.team_max = team_max;
+    (void)hipEventRecord(h->ev_init, s);
+    (void)hipEventRecord(h->ev_start, s);
+    return finish_launch(rt, h, relaunch(h, false, h->grid, s), out);
+}
+
+namespace {
+
+struct TuneKey {
+    std::string arch;
+    uint32_t count;
+    uint64_t sum_n, sum_arcs, max_work;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(arch, count, sum_n, sum_arcs, max_work) <
+               std::tie(o.arch, o.count, o.sum_n, o.sum_arcs, o.max_work);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<coop_tune, double>> g_tune_cache;
+
+}  // namespace
+
+int coop_batch_autotune(coop_rt* rt, const coop_batch_item* items, uint32_t count, uint32_t stride,
+                        uint32_t reps, const coop_launch_opts* opts, coop_stream_t stream, coop_tune* best,
+                        double* best_ms, double* default_ms) {
+    if (!rt || !items || count == 0 || !best) return COOP_E_INVALID;
+    for (uint32_t i = 0; i < count; ++i) {
+        int rc = check_batch_item(rt, items[i]);
+        if (rc) return rc;
+    }
+    TuneKey key{rt->props.gcnArchName, count, 0, 0, 0};
+    for (uint32_t i = 0; i < count; ++i) {
+        key.sum_n += items[i].graph->n;
+        key.sum_arcs += items[i].graph->arcs;
+        key.max_work = std::max<uint64_t>(key.max_work, items[i].graph->n + items[i].graph->arcs);
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *best = it->second.first;
+            if (best_ms) *best_ms = it->second.second;
+            if (default_ms) *default_ms = -1.0;
+            return COOP_OK;
+        }
+    }
+    if (stride == 0) stride = 1;
+    if (reps == 0) reps = 3;
+    std::vector<coop_batch_item> sub;
+    for (uint32_t i = 0; i < count; i += stride) sub.push_back(items[i]);
+    int err = COOP_OK;
+    auto time_it = [&](const coop_tune& t) -> double {
+        std::vector<double> ms;
+        for (uint32_t r = 0; r < reps; ++r) {
+            coop_handle* h = nullptr;
+            int rc = coop_batch_run(rt, sub.data(), (uint32_t)sub.size(), &t, opts, stream, &h);
+            coop_stats st{};
+            if (rc == COOP_OK) rc = coop_wait(h, &st);
+            if (rc != COOP_OK) {
+                if (rc != COOP_E_INVALID) err = rc;
+                return 1e30;
+            }
+            ms.push_back(st.kernel_ms);
+        }
+        return percentile(ms, 0.5);
+    };
+    coop_tune cur;
+    coop_tune_default(&cur);
+    double cur_ms = time_it(cur);
+    if (err) return err;
+    const double def_ms = cur_ms;
+    // coordinate search: group size, team work, BFS direction rule, team cap
+    const uint32_t sizes[] = {256, 512, 1024};
+    const uint64_t team_arcs[] = {1ull << 16, 1ull << 18, 1ull << 19, 1ull << 20, 1ull << 21, 1ull << 22,
+                                  1ull << 24};
+    for (int pass = 0; pass < 2; ++pass) {
+        for (uint32_t gs : sizes) {
+            if (gs == cur.group_size) continue;
+            coop_tune c = cur;
+            c.group_size = gs;
+            const double ms = time_it(c);
+            if (err) return err;
+            if (ms < cur_ms * 0.98) { cur = c; cur_ms = ms; }
+        }
+        for (uint64_t ta : team_arcs) {
+            if (ta == cur.team_arcs) continue;
+            coop_tune c = cur;
+            c.team_arcs = ta;
+            const double ms = time_it(c);
+            if (err) return err;
+            if (ms < cur_ms * 0.98) { cur = c; cur_ms = ms; }
+        }
+        {
+            coop_tune c = cur;
+            c.direction_opt = cur.direction_opt ? 0u : 1u;
+            const double ms = time_it(c);
+            if (err) return err;
+            if (ms < cur_ms * 0.98) { cur = c; cur_ms = ms; }
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = std::make_pair(cur, cur_ms);
+    }
+    *best = cur;
+    if (best_ms) *best_ms = cur_ms;
+    if (default_ms) *default_ms = def_ms;
+    return COOP_OK;
+}
+
 // ----------------------------------------------------------------- co-task
 
 static int cotask_once(coop_rt* rt, const coop_cotask_cfg* cfg, hipStream_t s, coop_handle* h,
-                       double* lat, double* gat, double* busy_ms) {
+                       double* lat, double* gat, double* busy_ms, double* t_req_out = nullptr,
+                       double* t_end_out = nullptr) {
     const uint32_t lds = cfg->lds_bytes ? cfg->lds_bytes : kDefaultLds;
     coop::CotaskArgs a{};
     a.busy_ticks = cfg->busy_ns * (uint64_t)rt->wall_khz / 1000000ull;
@@ -751,6 +1149,8 @@ static int cotask_once(coop_rt* rt, const coop_cotask_cfg* cfg, hipStream_t s, c
     if (h) coop_set_target(h, h->grid);
     if (lat) *lat = t_end - t_req;
     if (gat) *gat = t_gather - t_req;
+    if (t_req_out) *t_req_out = t_req;
+    if (t_end_out) *t_end_out = t_end;
     if (busy_ms) {
         const uint64_t a0 = __atomic_load_n(&rt->h_stamp[0], __ATOMIC_ACQUIRE);
         const uint64_t a1 = __atomic_load_n(&rt->h_stamp[1], __ATOMIC_ACQUIRE);
@@ -777,6 +1177,8 @@ int coop_injector_start(coop_rt* rt, coop_handle* h, const coop_cotask_cfg* cfg)
     rt->inj_lat.clear();
     rt->inj_gather.clear();
     rt->inj_busy_ms.clear();
+    rt->inj_setup_max = rt->inj_restore_max = 0;
+    rt->inj_late = 0;
     rt->inj_error = 0;
     rt->injector = std::thread([rt]() {
         (void)hipSetDevice(rt->device);
@@ -790,13 +1192,17 @@ int coop_injector_start(coop_rt* rt, coop_handle* h, const coop_cotask_cfg* cfg)
                     (int64_t)std::min(1000.0, (next - t) * 1000.0)));
                 continue;
             }
-            next += (double)cfg.period_ns / 1e6;
+            const double period_ms = (double)cfg.period_ns / 1e6;
+            if (t - next > period_ms) ++rt->inj_late;
+            next += period_ms;
             rt->inj_busy = 1;
             coop_handle* h = rt->inj_handle.load();
             if (h && handle_done(h)) h = nullptr;
-            double lat = 0, gat = 0, busy = 0;
-            int rc = cotask_once(rt, &cfg, rt->cotask_stream, h, &lat, &gat, &busy);
+            double lat = 0, gat = 0, busy = 0, t_req = t, t_end = t;
+            int rc = cotask_once(rt, &cfg, rt->cotask_stream, h, &lat, &gat, &busy, &t_req, &t_end);
             if (rc == COOP_OK && h && !handle_done(h)) rc = coop_fork_groups(h, cfg.groups);
+            rt->inj_setup_max = std::max(rt->inj_setup_max, t_req - t);
+            rt->inj_restore_max = std::max(rt->inj_restore_max, now_ms() - t_end);
             rt->inj_busy = 0;
             if (rc != COOP_OK) { rt->inj_error = rc; break; }
             rt->inj_lat.push_back(lat);
@@ -825,6 +1231,9 @@ int coop_injector_stop(coop_rt* rt, coop_cotask_stats* out) {
         double s = 0;
         for (double b : rt->inj_busy_ms) s += b;
         out->busy_mean_ms = rt->inj_busy_ms.empty() ? 0 : s / (double)rt->inj_busy_ms.size();
+        out->setup_max_ms = rt->inj_setup_max;
+        out->restore_max_ms = rt->inj_restore_max;
+        out->late_periods = rt->inj_late;
     }
     return rt->inj_error;
 }

@@ -1,0 +1,782 @@
+// Device building blocks of the level-synchronous traversals, shared by the
+// resizable persistent kernels (one traversal over all workgroups) and the
+// batched kernel (one team of workgroups per graph instance).
+//
+// Design rules measured on MI355X: a device-scope atomic on one address
+// costs ~11 ns and serialises across the chip, random atomics execute at
+// the memory side (~27 G/s), random L2-hit loads reach ~270 G/s. So:
+//  * work of a level is distributed statically over the M x (waves per
+//    workgroup) wave slots of the interval (units u, u + W, u + 2W, ...);
+//    no claim counter;
+//  * per-workgroup statistics go to a private slot (one cache line per
+//    logical id) summed by the master step; no shared counter;
+//  * queue outputs are compacted (wave ballot + mbcnt) into per-wave LDS
+//    buffers and flushed with one atomic per workgroup per phase;
+//  * BFS keeps its frontiers as bitmaps (three rotating ones) and switches
+//    between top-down levels (walk the frontier's neighbour lists, claim
+//    targets with one atomic OR) and bottom-up levels (every unvisited
+//    vertex looks for a parent in the frontier bitmap; no atomics at all)
+//    by the frontier/unvisited edge-count rule of Beamer, Asanovic and
+//    Patterson (SC 2012);
+//  * a wave walks the concatenated neighbour lists of up to 64 vertices,
+//    64 x UNROLL arcs per step, each lane finding its source vertex by a
+//    binary search over the wave's degree prefix in LDS; vertices above a
+//    degree threshold are cut into fixed-size arc strips processed by all
+//    waves in a HEAVY phase of the same level.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "coop_device.hpp"
+#include "coop_internal.h"
+
+using namespace coop;
+
+namespace {
+
+constexpr uint32_t kWave = 64;
+constexpr uint32_t kUnroll = 8;                   // arcs per lane per step
+constexpr uint32_t kOutCap = 1024;                // per-wave output buffer (entries)
+constexpr uint32_t kFlushAt = kOutCap - kWave * kUnroll;
+constexpr uint32_t kInf = 0xFFFFFFFFu;
+
+// phases and flags carried in the release word
+constexpr uint32_t kPhShift = 4;
+constexpr uint32_t kPhMask = 7u << kPhShift;
+constexpr uint32_t kPhStart = 0u << kPhShift;     // registration barrier
+constexpr uint32_t kPhInit = 1u << kPhShift;      // clear per-source state
+constexpr uint32_t kPhTD = 2u << kPhShift;        // top-down: walk the frontier
+constexpr uint32_t kPhHeavy = 3u << kPhShift;     // walk the heavy strips
+constexpr uint32_t kPhBU = 4u << kPhShift;        // bottom-up: unvisited vertices look for a parent
+constexpr uint32_t kPhSetup = 5u << kPhShift;     // colouring: count higher-priority neighbours
+constexpr uint32_t kPhOut = 6u << kPhShift;       // SSSP: copy a source's distances out
+constexpr uint32_t kFlagSel = 1u << 8;            // queue engine: which buffer is input
+constexpr uint32_t kFlagAdv = 1u << 9;            // this barrier advanced the level
+constexpr uint32_t kRotShift = 10;                // BFS: frontier bitmap rotation (0..2)
+constexpr uint32_t kRotMask = 3u << kRotShift;
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint32_t wave_id() { return threadIdx.x / kWave; }
+__device__ __forceinline__ uint32_t num_waves() { return blockDim.x / kWave; }
+
+__device__ __forceinline__ uint32_t mbcnt(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const uint32_t l = lane_id();
+#pragma unroll
+    for (uint32_t d = 1; d < kWave; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, kWave);
+        if (l >= d) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint32_t bcast(uint32_t x, uint32_t src) { return __shfl(x, src, kWave); }
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
+#pragma unroll
+    for (uint32_t d = kWave / 2; d >= 1; d >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)x, d, kWave);
+        const uint32_t hi = __shfl_xor((uint32_t)(x >> 32), d, kWave);
+        x += ((uint64_t)hi << 32) | lo;
+    }
+    return x;
+}
+
+// ----------------------------------------------------------- LDS layout
+
+struct WaveLds {
+    uint32_t excl[kWave + 1];   // degree prefix of the wave's vertices
+    uint32_t start[kWave];      // first arc of each vertex
+    uint32_t pay[kWave];        // algorithm payload (distance, degree ...)
+    uint32_t out_n;             // entries in the output buffer
+    uint32_t out[kOutCap];
+};
+
+struct BlockLds {
+    BarrierLds bar;
+    uint32_t level, root, aux, in_size;
+    uint32_t wave_base[kMaxWaves];
+    uint64_t acc[8];            // per-workgroup statistics of the phase
+    uint64_t red[8][kMaxWaves]; // master reductions
+    WaveLds wave[kMaxWaves];
+};
+
+// Per-wave statistics, flushed to the workgroup accumulators at phase end.
+struct Stats {
+    uint64_t found = 0, mf = 0, arcs = 0, rows = 0, words = 0;
+};
+
+__device__ void stats_to_lds(BlockLds& sh, const Stats& s) {
+    const uint64_t v[5] = {wave_sum64(s.found), wave_sum64(s.mf), wave_sum64(s.arcs),
+                           wave_sum64(s.rows), wave_sum64(s.words)};
+    if (lane_id() == 0)
+        for (int i = 0; i < 5; ++i)
+            if (v[i]) atomicAdd(reinterpret_cast<unsigned long long*>(&sh.acc[i]),
+                                (unsigned long long)v[i]);
+}
+
+// Add the workgroup's phase statistics to its slot (after a __syncthreads);
+// fire-and-forget atomics, so nobody waits for the round trip.
+__device__ void acc_to_slot(BlockLds& sh, uint32_t* slots, uint32_t id) {
+    if (threadIdx.x < 5) {
+        uint64_t* s = reinterpret_cast<uint64_t*>(slots + (size_t)id * kSlotWords);
+        const uint64_t v = sh.acc[threadIdx.x];
+        if (v) {
+            // fields 0,1 are per level; 2,3,4 cumulative; found is also kept cumulatively
+            add_nr64(&s[threadIdx.x], v);
+            if (threadIdx.x == 0) add_nr64(&s[kSlotFoundAll], v);
+        }
+        sh.acc[threadIdx.x] = 0;
+    }
+}
+
+// Master step helper: sum the per-level fields (found, mf) of every slot
+// (all N logical ids) and clear them. Called by all threads of the master
+// workgroup; tot[0..1] valid in all.
+__device__ void master_sum_slots(BlockLds& sh, uint32_t* slots, uint32_t N, uint64_t* tot) {
+    uint64_t part[2] = {0, 0};
+    for (uint32_t i = threadIdx.x; i < N; i += blockDim.x) {
+        uint64_t* s = reinterpret_cast<uint64_t*>(slots + (size_t)i * kSlotWords);
+        const uint64_t a = s[0], b = s[1];
+        if (a | b) {
+            part[0] += a;
+            part[1] += b;
+            s[0] = 0;
+            s[1] = 0;
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+        const uint64_t w = wave_sum64(part[f]);
+        if (lane_id() == 0) sh.red[f][wave_id()] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+        uint64_t t = 0;
+        for (uint32_t w = 0; w < num_waves(); ++w) t += sh.red[f][w];
+        tot[f] = t;
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------ output queue
+
+// Append this wave's ballot winners (lanes with `win`) to its LDS buffer.
+__device__ __forceinline__ void wave_push(WaveLds& w, bool win, uint32_t v) {
+    const uint64_t mask = __ballot(win);
+    if (!mask) return;
+    const uint32_t base = w.out_n;
+    if (win) w.out[base + mbcnt(mask)] = v;
+    __builtin_amdgcn_wave_barrier();
+    if (lane_id() == 0) w.out_n = base + (uint32_t)__popcll(mask);
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ void wave_flush(WaveLds& w, uint32_t* out_tail, uint32_t* out) {
+    const uint32_t cnt = w.out_n;
+    if (cnt == 0) return;
+    uint32_t base = 0;
+    if (lane_id() == 0) base = add_relaxed(out_tail, cnt);
+    base = bcast(base, 0);
+    for (uint32_t i = lane_id(); i < cnt; i += kWave) out[base + i] = w.out[i];
+    __builtin_amdgcn_wave_barrier();
+    if (lane_id() == 0) w.out_n = 0;
+    __builtin_amdgcn_wave_barrier();
+}
+
+// End of a phase: one reservation for the whole workgroup.
+__device__ void wg_flush(BlockLds& sh, uint32_t* out_tail, uint32_t* out) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (uint32_t w = 0; w < num_waves(); ++w) {
+            sh.wave_base[w] = tot;
+            tot += sh.wave[w].out_n;
+        }
+        const uint32_t base = tot ? add_relaxed(out_tail, tot) : 0u;
+        for (uint32_t w = 0; w < num_waves(); ++w) sh.wave_base[w] += base;
+    }
+    __syncthreads();
+    WaveLds& w = sh.wave[wave_id()];
+    const uint32_t cnt = w.out_n, base = sh.wave_base[wave_id()];
+    for (uint32_t i = lane_id(); i < cnt; i += kWave) out[base + i] = w.out[i];
+    __builtin_amdgcn_wave_barrier();
+    if (lane_id() == 0) w.out_n = 0;
+}
+
+// ---------------------------------------------------------- expansion
+
+// Owner of flattened arc index e inside the wave: largest i with excl[i] <= e.
+__device__ __forceinline__ uint32_t owner_of(const WaveLds& w, uint32_t e) {
+    uint32_t lo = 0, hi = kWave;        // excl[lo] <= e < excl[hi]
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (w.excl[mid] <= e) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Walk the concatenated neighbour lists described by excl/start/pay (total
+// arcs `total`), UNROLL arcs per lane per step, coalesced column loads.
+template <class Visit>
+__device__ __forceinline__ void walk_arcs(WaveLds& w, uint32_t total, const uint32_t* __restrict__ col,
+                                          Visit& visit, Stats& st) {
+    st.arcs += lane_id() == 0 ? total : 0u;
+    for (uint32_t base = 0; base < total; base += kWave * kUnroll) {
+        uint32_t arc[kUnroll], u[kUnroll], pay[kUnroll];
+        bool ok[kUnroll];
+#pragma unroll
+        for (uint32_t j = 0; j < kUnroll; ++j) {
+            const uint32_t e = base + j * kWave + lane_id();
+            ok[j] = e < total;
+            const uint32_t o = owner_of(w, ok[j] ? e : 0u);
+            arc[j] = w.start[o] + (ok[j] ? e - w.excl[o] : 0u);
+            pay[j] = w.pay[o];
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kUnroll; ++j) u[j] = ok[j] ? __builtin_nontemporal_load(&col[arc[j]]) : 0u;
+        visit.step(ok, arc, u, pay, w, st);
+        visit.maybe_flush(w);
+    }
+}
+
+// One heavy strip {payload, first arc, length} walked by one wave.
+template <class Visit>
+__device__ __forceinline__ void walk_strip(WaveLds& w, uint32_t pay0, uint32_t a0, uint32_t len,
+                                           const uint32_t* __restrict__ col, Visit& visit, Stats& st) {
+    st.arcs += lane_id() == 0 ? len : 0u;
+    for (uint32_t base = 0; base < len; base += kWave * kUnroll) {
+        uint32_t arc[kUnroll], u[kUnroll], pay[kUnroll];
+        bool ok[kUnroll];
+#pragma unroll
+        for (uint32_t j = 0; j < kUnroll; ++j) {
+            const uint32_t e = base + j * kWave + lane_id();
+            ok[j] = e < len;
+            arc[j] = a0 + (ok[j] ? e : 0u);
+            pay[j] = pay0;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kUnroll; ++j) u[j] = ok[j] ? __builtin_nontemporal_load(&col[arc[j]]) : 0u;
+        visit.step(ok, arc, u, pay, w, st);
+        visit.maybe_flush(w);
+    }
+}
+
+// Expand one batch of up to 64 vertices (lane l holds vertex v if `act`):
+// heavy vertices are queued as strips, the rest are walked by this wave.
+template <class Visit>
+__device__ __forceinline__ void expand_batch(const TraversalArgs& a, Work* wk, WaveLds& w, bool act,
+                                             uint32_t v, Visit& visit, Stats& st) {
+    uint32_t s0 = 0, deg = 0, pay = 0;
+    if (act) {
+        s0 = a.row_ptr[v];
+        deg = a.row_ptr[v + 1] - s0;
+        pay = visit.payload(v);
+        st.rows += 1;
+    }
+    const bool heavy = deg > a.heavy_th;
+    const uint64_t hmask = __ballot(heavy);
+    if (hmask) {
+        const uint32_t ns = heavy ? (deg + a.strip - 1) / a.strip : 0u;
+        const uint32_t incl = wave_incl_scan(ns);
+        const uint32_t tot = bcast(incl, kWave - 1);
+        uint32_t b = 0;
+        if (lane_id() == kWave - 1) b = add_relaxed(&wk->heavy_tail, tot);
+        b = bcast(b, kWave - 1);
+        if (heavy) {
+            uint32_t k = b + incl - ns;
+            for (uint32_t j = 0; j < ns; ++j, ++k) {
+                const uint32_t off = j * a.strip;
+                const uint32_t len = deg - off < a.strip ? deg - off : a.strip;
+                if (k < a.heavy_cap) a.heavy[k] = make_uint4(pay, s0 + off, len, v);
+            }
+            deg = 0;
+        }
+    }
+    const uint32_t incl = wave_incl_scan(deg);
+    w.excl[lane_id()] = incl - deg;
+    w.start[lane_id()] = s0;
+    w.pay[lane_id()] = pay;
+    if (lane_id() == kWave - 1) w.excl[kWave] = incl;
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t total = bcast(incl, kWave - 1);
+    if (total) walk_arcs(w, total, a.col, visit, st);
+    __builtin_amdgcn_wave_barrier();
+}
+
+// HEAVY phase: strips distributed statically over the interval's waves.
+template <class Visit>
+__device__ void heavy_phase(const TraversalArgs& a, uint32_t nstrips, uint32_t gw, uint32_t W, WaveLds& w,
+                            Visit& visit, Stats& st) {
+    if (nstrips > a.heavy_cap) nstrips = a.heavy_cap;
+    for (uint32_t s = gw; s < nstrips; s += W) {
+        const uint4 rec = a.heavy[s];
+        const uint32_t pay = visit.strip_payload(rec.x, rec.w);
+        walk_strip(w, pay, rec.y, rec.z, a.col, visit, st);
+    }
+}
+
+// ------------------------------------------------------------------ BFS
+
+struct BfsTopDown {
+    uint32_t* vis;
+    uint32_t* nxt;
+    uint32_t* level;
+    const uint32_t* row_ptr;
+    uint32_t next_level;
+    uint32_t count_mf;
+
+    __device__ __forceinline__ uint32_t payload(uint32_t) const { return 0; }
+    __device__ __forceinline__ uint32_t strip_payload(uint32_t p, uint32_t) const { return p; }
+    __device__ __forceinline__ void maybe_flush(WaveLds&) {}
+
+    // Claim unvisited targets: a plain load filters most arcs, the atomic OR
+    // on the visited set decides the single winner, which writes the level
+    // and marks the next frontier.
+    __device__ __forceinline__ void step(const bool* ok, const uint32_t*, const uint32_t* u, const uint32_t*,
+                                         WaveLds&, Stats& st) {
+        uint32_t word[kUnroll];
+#pragma unroll
+        for (uint32_t j = 0; j < kUnroll; ++j) word[j] = ok[j] ? vis[u[j] >> 5] : ~0u;
+#pragma unroll
+        for (uint32_t j = 0; j < kUnroll; ++j) {
+            const uint32_t bit = 1u << (u[j] & 31);
+            if (ok[j] && !(word[j] & bit)) {
+                const uint32_t old = __hip_atomic_fetch_or(&vis[u[j] >> 5], bit, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+                if (!(old & bit)) {
+                    level[u[j]] = next_level;
+                    __hip_atomic_fetch_or(&nxt[u[j] >> 5], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    st.found += 1;
+                    if (count_mf) {
+                        st.mf += row_ptr[u[j] + 1] - row_ptr[u[j]];
+                        st.rows += 1;
+                    }
+                }
+            }
+        }
+    }
+};
+
+// Bottom-up level: every unvisited vertex with arcs scans its neighbours for
+// one in the current frontier; the first hit makes it a member of the next
+// level. A wave owns blocks of 32 bitmap words (1024 vertices): lanes 0..31
+// load one visited word each, the unvisited vertices with arcs are compacted
+// into an LDS list, and the list is probed two candidates per lane, so every
+// batch is full and two independent load chains are in flight per lane.
+// Found bits are gathered in LDS and each block's visited and next-frontier
+// words are written once, with plain stores (no other wave owns them).
+__device__ void bfs_bottom_up(const BfsArgs& p, WaveLds& wl, const uint32_t* cur, uint32_t* nxt,
+                              uint32_t* level, uint32_t next_level, uint32_t gw, uint32_t W, Stats& st) {
+    constexpr uint32_t kBlockWords = 32;
+    const uint32_t blocks = p.words / kBlockWords;
+    const uint32_t l = lane_id();
+    uint32_t* list = wl.out;            // up to 1024 candidates
+    uint32_t* fw = wl.excl;             // found bits of the block's 32 words
+    for (uint32_t b = gw; b < blocks; b += W) {
+        const uint32_t wi = b * kBlockWords + (l & 31);
+        uint32_t vw = 0, cand = 0;
+        if (l < 32) {
+            vw = p.vis[wi];
+            cand = ~(vw | p.deg0[wi]);
+            fw[l] = 0;
+        }
+        st.words += (l == 0) ? 2u * kBlockWords : 0u;
+        const uint32_t cnt = __popc(cand);
+        const uint32_t incl = wave_incl_scan(cnt);
+        const uint32_t total = bcast(incl, kWave - 1);
+        if (total == 0) continue;
+        uint32_t pos = incl - cnt;
+        while (cand) {
+            list[pos++] = wi * 32u + (uint32_t)(__ffs(cand) - 1);
+            cand &= cand - 1;
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t base = 0; base < total; base += 2 * kWave) {
+            uint32_t v[2], k[2], e[2], s0[2];
+            bool hit[2] = {false, false};
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const uint32_t i = base + c * kWave + l;
+                v[c] = i < total ? list[i] : 0xFFFFFFFFu;
+                s0[c] = k[c] = e[c] = 0;
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                if (v[c] != 0xFFFFFFFFu) {
+                    s0[c] = k[c] = p.t.row_ptr[v[c]];
+                    e[c] = p.t.row_ptr[v[c] + 1];
+                    st.rows += 1;
+                }
+            }
+            while (__ballot((k[0] < e[0] && !hit[0]) || (k[1] < e[1] && !hit[1]))) {
+                uint32_t u[2][4];
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        u[c][j] = (!hit[c] && k[c] + j < e[c]) ? p.t.col[k[c] + j] : 0xFFFFFFFFu;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    if (hit[c] || k[c] >= e[c]) continue;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (u[c][j] != 0xFFFFFFFFu) hit[c] |= ((cur[u[c][j] >> 5] >> (u[c][j] & 31)) & 1u) != 0;
+                    const uint32_t got = e[c] - k[c] < 4 ? e[c] - k[c] : 4u;
+                    st.arcs += got;
+                    k[c] += got;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                if (hit[c]) {
+                    level[v[c]] = next_level;
+                    atomicOr(&fw[(v[c] >> 5) - b * kBlockWords], 1u << (v[c] & 31));
+                    st.found += 1;
+                    st.mf += e[c] - s0[c];
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (l < 32) {
+            const uint32_t f = fw[l];
+            if (f) {
+                p.vis[wi] = vw | f;
+                nxt[wi] = f;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Top-down level over a frontier bitmap: each wave takes blocks of 64 words
+// (2048 vertices); every round it takes the lowest remaining vertex of each
+// lane's word, so a batch holds up to 64 frontier vertices.
+__device__ void bfs_top_down(const BfsArgs& p, Work* wk, WaveLds& w, const uint32_t* cur, BfsTopDown& vis,
+                             uint32_t gw, uint32_t W, Stats& st) {
+    const uint32_t blocks = p.words / kWave;
+    for (uint32_t b = gw; b < blocks; b += W) {
+        uint32_t word = cur[b * kWave + lane_id()];
+        st.words += lane_id() == 0 ? kWave : 0u;
+        while (__ballot(word != 0)) {
+            const bool act = word != 0;
+            uint32_t v = 0;
+            if (act) {
+                v = (b * kWave + lane_id()) * 32u + (uint32_t)(__ffs(word) - 1);
+                word &= word - 1;
+            }
+            expand_batch(p.t, wk, w, act, v, vis, st);
+        }
+    }
+}
+
+// Clear a bitmap share: words gw*64 + lane, then + W*64 ...
+__device__ __forceinline__ void clear_share(uint32_t* bm, uint32_t words, uint32_t gw, uint32_t W) {
+    for (uint32_t i = gw * kWave + lane_id(); i < words; i += W * kWave) bm[i] = 0;
+}
+
+// Level partials that survive the TD -> HEAVY barrier live in Work::pad5.
+// One BFS phase for member `id` of `M` (the interval's membership):
+// INIT clears the per-source state, TD/HEAVY expand the frontier, BU probes
+// the unvisited vertices. Statistics go to the member's slot.
+__device__ __forceinline__ void bfs_phase(const BfsArgs& p, BlockLds& sh, uint32_t ph, uint32_t flags,
+                                          uint32_t level, uint32_t root, uint32_t id, uint32_t M) {
+    const TraversalArgs& t = p.t;
+    Work* wk = t.work;
+    const uint32_t nw = num_waves();
+    const uint32_t rot = (flags & kRotMask) >> kRotShift;
+    uint32_t* cur = p.fb[rot];
+    uint32_t* nxt = p.fb[(rot + 1) % 3];
+    uint32_t* spare = p.fb[(rot + 2) % 3];
+    uint32_t* lvl = p.level_out + (size_t)root * t.out_stride;
+    const uint32_t gw = id * nw + wave_id();
+    const uint32_t W = M * nw;
+    Stats st;
+    if (ph == kPhInit) {
+        const uint32_t tid = id * blockDim.x + threadIdx.x, stride = M * blockDim.x;
+        for (uint32_t i = tid; i < t.n; i += stride) lvl[i] = kInf;
+        for (uint32_t i = tid; i < p.words; i += stride) {
+            p.vis[i] = 0;
+            p.fb[0][i] = 0;
+            p.fb[1][i] = 0;
+            p.fb[2][i] = 0;
+        }
+    } else if (ph == kPhTD || ph == kPhHeavy) {
+        BfsTopDown vis{p.vis, nxt, lvl, t.row_ptr, level + 1, p.direction_opt};
+        WaveLds& w = sh.wave[wave_id()];
+        if (ph == kPhTD) {
+            clear_share(spare, p.words, gw, W);
+            bfs_top_down(p, wk, w, cur, vis, gw, W, st);
+        } else {
+            heavy_phase(t, wk->x.in_size, gw, W, w, vis, st);
+        }
+    } else if (ph == kPhBU) {
+        clear_share(spare, p.words, gw, W);
+        bfs_bottom_up(p, sh.wave[wave_id()], cur, nxt, lvl, level + 1, gw, W, st);
+    }
+    if (ph != kPhStart && ph != kPhInit) {
+        stats_to_lds(sh, st);
+        __syncthreads();
+        acc_to_slot(sh, t.slots, id);
+    }
+}
+
+// BFS master step (all threads of the master workgroup): per-level
+// bookkeeping, HEAVY follow-up, direction of the next level (Beamer's
+// alpha/beta rule), next source or done. Returns the release flags.
+__device__ __forceinline__ uint32_t bfs_master(const BfsArgs& p, BlockLds& sh, CtxCore* c, uint32_t ph, uint32_t cur_flags) {
+    const TraversalArgs& t = p.t;
+    Work* wk = t.work;
+    uint64_t tot[2];
+    master_sum_slots(sh, t.slots, t.N, tot);
+    if (threadIdx.x == 0) {
+        XferR x = wk->load_x();                 // one batch of loads
+        const uint32_t hs = ld_relaxed(&wk->heavy_tail);
+        uint32_t res = 0;
+        const uint32_t r = (cur_flags & kRotMask) >> kRotShift;
+        if (ph == kPhStart) {
+            x.root() = 0;
+            res = kPhInit;
+        } else if (ph == kPhInit) {
+            const uint32_t src = t.roots[x.root()];
+            uint32_t* lv = p.level_out + (size_t)x.root() * t.out_stride;
+            lv[src] = 0;
+            p.vis[src >> 5] |= 1u << (src & 31);
+            p.fb[0][src >> 5] |= 1u << (src & 31);
+            x.level() = 0;
+            x.nf_prev() = 1;
+            x.m_visited_lo() = t.row_ptr[src + 1] - t.row_ptr[src];
+            x.m_visited_hi() = 0;
+            x.lvl_found() = 0;
+            x.lvl_mf_lo() = x.lvl_mf_hi() = 0;
+            wk->heavy_tail = 0;
+            res = kPhTD;                        // rotation 0: current = fb[0]
+        } else {
+            // level partials (a TD level may be followed by a HEAVY phase)
+            const uint64_t mf_lvl = join64(x.lvl_mf_lo(), x.lvl_mf_hi()) + tot[1];
+            const uint32_t nf_lvl = x.lvl_found() + (uint32_t)tot[0];
+            if (ph == kPhTD && hs > 0) {
+                if (hs > t.heavy_cap) raise_error(c, kErrInternal);
+                x.in_size() = hs;
+                wk->heavy_tail = 0;
+                x.lvl_found() = nf_lvl;
+                x.lvl_mf_lo() = (uint32_t)mf_lvl;
+                x.lvl_mf_hi() = (uint32_t)(mf_lvl >> 32);
+                x.heavy_phases() += 1;
+                res = (cur_flags & kRotMask) | kPhHeavy;
+            } else {
+                x.lvl_found() = 0;
+                x.lvl_mf_lo() = x.lvl_mf_hi() = 0;
+                if (hs) wk->heavy_tail = 0;
+                x.levels_total() += 1;
+                if (ph == kPhBU) x.bu_levels() += 1; else x.td_levels() += 1;
+                if (nf_lvl == 0) {
+                    x.root() += 1;
+                    res = x.root() >= t.nroots ? kFlagDone : (kPhInit | kFlagAdv);
+                } else {
+                    // direction of the next level
+                    const uint64_t mv = join64(x.m_visited_lo(), x.m_visited_hi()) + mf_lvl;
+                    x.m_visited_lo() = (uint32_t)mv;
+                    x.m_visited_hi() = (uint32_t)(mv >> 32);
+                    const uint64_t m_u = p.total_arcs > mv ? p.total_arcs - mv : 0;
+                    uint32_t nph = kPhTD;
+                    if (p.direction_opt) {
+                        if (ph == kPhBU)
+                            nph = ((uint64_t)nf_lvl * p.beta < t.n && nf_lvl < x.nf_prev()) ? kPhTD : kPhBU;
+                        else
+                            nph = (mf_lvl * p.alpha > m_u) ? kPhBU : kPhTD;
+                    }
+                    x.nf_prev() = nf_lvl;
+                    x.level() += 1;
+                    res = nph | kFlagAdv | (((r + 1) % 3) << kRotShift);
+                }
+            }
+        }
+        wk->store_x(x);
+        sh.bar.flags = res;
+    }
+    __syncthreads();
+    return sh.bar.flags;
+}
+
+// Follow the transmitted BFS state locally after a barrier.
+__device__ __forceinline__ void bfs_follow(uint32_t ph, uint32_t nflags, uint32_t& level, uint32_t& root) {
+    const uint32_t nph = nflags & kPhMask;
+    if (nph == kPhInit) {
+        if (ph != kPhStart) root += 1;
+        level = 0;
+    } else if (ph == kPhInit) {
+        level = 0;
+    } else if (nflags & kFlagAdv) {
+        level += 1;
+    }
+}
+
+// ----------------------------------------------- colouring and MIS (JP DAG)
+
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+
+// Priority key (h(v), v), higher first; h(v) = output v of SplitMix64 from
+// state prio_seed.
+__device__ __forceinline__ bool key_higher(uint64_t hu, uint32_t u, uint64_t hv, uint32_t v) {
+    return hu > hv || (hu == hv && u > v);
+}
+__device__ __forceinline__ uint64_t key_hash(uint64_t seed, uint32_t v) {
+    return splitmix64(seed + (uint64_t)v * kGamma);
+}
+
+// Decide one vertex whose higher-priority neighbours are all final: colour =
+// smallest colour none of them has (or MIS membership).
+__device__ __forceinline__ void color_vertex(const ColorArgs& p, uint32_t v, bool valid, Stats& st) {
+    if (!valid) return;
+    const uint64_t hv = key_hash(p.prio_seed, v);
+    const uint32_t a0 = p.t.row_ptr[v], a1 = p.t.row_ptr[v + 1];
+    st.rows += 1;
+    st.arcs += a1 - a0;
+    if (p.mis) {
+        bool blocked = false;
+        for (uint32_t e = a0; e < a1 && !blocked; ++e) {
+            const uint32_t u = p.t.col[e];
+            if (key_higher(key_hash(p.prio_seed, u), u, hv, v)) blocked = p.in_set_out[u] != 0;
+        }
+        p.in_set_out[v] = blocked ? 0 : 1;
+    } else {
+        uint32_t base = 0, c = 0;
+        for (;;) {
+            uint64_t used = 0;
+            for (uint32_t e = a0; e < a1; ++e) {
+                const uint32_t u = p.t.col[e];
+                if (key_higher(key_hash(p.prio_seed, u), u, hv, v)) {
+                    const uint32_t cu = p.colour_out[u] - base;
+                    if (cu < 64) used |= 1ull << cu;
+                }
+            }
+            if (~used) {
+                c = base + (uint32_t)__ffsll((long long)~used) - 1;
+                break;
+            }
+            base += 64;
+        }
+        p.colour_out[v] = c;
+    }
+}
+
+// Release the lower-priority neighbours of v; one whose count of undecided
+// higher neighbours reaches 0 is queued for the next round.
+__device__ __forceinline__ void release_lower(const ColorArgs& p, uint32_t v, bool valid, WaveLds& w,
+                                              uint32_t* out_tail, uint32_t* out, Stats& st) {
+    const uint64_t hv = valid ? key_hash(p.prio_seed, v) : 0;
+    uint32_t e = valid ? p.t.row_ptr[v] : 0;
+    const uint32_t a1 = valid ? p.t.row_ptr[v + 1] : 0;
+    for (;;) {
+        const bool more = e < a1;
+        if (!__ballot(more)) break;
+        bool win = false;
+        uint32_t u = 0;
+        if (more) {
+            u = p.t.col[e];
+            if (!key_higher(key_hash(p.prio_seed, u), u, hv, v)) {
+                const uint32_t old = __hip_atomic_fetch_sub(&p.pending[u], 1u, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
+                win = old == 1;
+            }
+            ++e;
+        }
+        st.found += win ? 1u : 0u;
+        wave_push(w, win, u);
+        if (w.out_n > kFlushAt) wave_flush(w, out_tail, out);
+    }
+}
+
+// Colouring / MIS: SETUP counts every vertex's higher-priority neighbours
+// and queues the sources of the priority DAG; each round decides its
+// frontier and releases the next one.
+// One colouring/MIS phase for member `id` of `M`: SETUP counts every
+// vertex's higher-priority neighbours and queues the sources of the
+// priority DAG; TD decides the round's frontier and releases the next one.
+__device__ __forceinline__ void color_phase(const ColorArgs& p, BlockLds& sh, uint32_t ph, uint32_t flags,
+                                            uint32_t id, uint32_t M) {
+    const TraversalArgs& t = p.t;
+    Work* wk = t.work;
+    const uint32_t nw = num_waves();
+    const bool sel = (flags & kFlagSel) != 0;
+    uint32_t* in = t.frontier[sel ? 1 : 0];
+    uint32_t* out = t.frontier[sel ? 0 : 1];
+    const uint32_t gw = id * nw + wave_id();
+    const uint32_t W = M * nw;
+    WaveLds& w = sh.wave[wave_id()];
+    Stats st;
+    if (ph == kPhSetup) {
+        const uint32_t units = (t.n + kWave - 1) / kWave;
+        for (uint32_t u = gw; u < units; u += W) {
+            const uint32_t v = u * kWave + lane_id();
+            const bool valid = v < t.n;
+            uint32_t cnt = 0;
+            if (valid) {
+                const uint64_t hv = key_hash(p.prio_seed, v);
+                for (uint32_t e = t.row_ptr[v]; e < t.row_ptr[v + 1]; ++e) {
+                    const uint32_t x = t.col[e];
+                    cnt += key_higher(key_hash(p.prio_seed, x), x, hv, v) ? 1u : 0u;
+                }
+                p.pending[v] = cnt;
+            }
+            wave_push(w, valid && cnt == 0, v);
+            if (w.out_n > kFlushAt) wave_flush(w, &wk->out_tail, out);
+        }
+        wg_flush(sh, &wk->out_tail, out);
+    } else if (ph == kPhTD) {
+        if (threadIdx.x == 0) sh.in_size = wk->x.in_size;
+        __syncthreads();
+        const uint32_t size = sh.in_size;
+        const uint32_t units = (size + kWave - 1) / kWave;
+        for (uint32_t u = gw; u < units; u += W) {
+            const uint32_t i = u * kWave + lane_id();
+            const bool valid = i < size;
+            const uint32_t v = valid ? in[i] : 0u;
+            color_vertex(p, v, valid, st);
+            release_lower(p, v, valid, w, &wk->out_tail, out, st);
+        }
+        wg_flush(sh, &wk->out_tail, out);
+        stats_to_lds(sh, st);
+        __syncthreads();
+        acc_to_slot(sh, t.slots, id);
+    }
+}
+
+// Colouring master step: the output queue of the round becomes the input
+// of the next; an empty queue ends the run.
+__device__ __forceinline__ uint32_t color_master(const ColorArgs& p, BlockLds& sh, uint32_t ph, uint32_t cur_flags) {
+    const TraversalArgs& t = p.t;
+    Work* wk = t.work;
+    uint64_t tot[2];
+    master_sum_slots(sh, t.slots, t.N, tot);
+    if (threadIdx.x == 0) {
+        XferR x = wk->load_x();
+        const uint32_t ot = ld_relaxed(&wk->out_tail);
+        uint32_t res;
+        if (ph == kPhStart) {
+            if (ot) wk->out_tail = 0;
+            res = kPhSetup;           // SETUP writes buffer 1 (sel = 0)
+        } else {
+            wk->out_tail = 0;
+            x.in_size() = ot;
+            x.level() += 1;
+            x.levels_total() += 1;
+            res = ot == 0 ? kFlagDone : (((cur_flags & kFlagSel) ^ kFlagSel) | kPhTD | kFlagAdv);
+        }
+        wk->store_x(x);
+        sh.bar.flags = res;
+    }
+    __syncthreads();
+    return sh.bar.flags;
+}
+
+}  // namespace

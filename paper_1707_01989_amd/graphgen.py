@@ -141,6 +141,30 @@ def er(n: int, avg_deg: float, seed: int) -> Graph:
                             family="er", avg_deg=avg_deg, seed=seed)
 
 
+def batch_sizes(count: int = 512, seed0: int = 1000, log2_lo: float = 10.0, log2_hi: float = 18.0,
+                deg_lo: float = 4.0, deg_hi: float = 32.0) -> list[tuple[int, float, int]]:
+    """(n_i, d_i, seed_i) of a batch of ER instances: instance i uses seed
+    seed0 + i; n_i = floor(2^U(log2_lo, log2_hi)) (log-uniform vertex
+    count), d_i = U(deg_lo, deg_hi) (average degree), both drawn from
+    stream 11 of that seed."""
+    out = []
+    for i in range(count):
+        s = seed0 + i
+        n = int(np.floor(2.0 ** (log2_lo + (log2_hi - log2_lo) * real(s, 11, 0))))
+        d = deg_lo + (deg_hi - deg_lo) * real(s, 11, 1)
+        out.append((n, d, s))
+    return out
+
+
+def er_batch(count: int = 512, seed0: int = 1000, workers: int = 8, **kw) -> list[Graph]:
+    """The ER instances of batch_sizes(), generated in parallel threads (the
+    C generator releases the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+    sizes = batch_sizes(count, seed0, **kw)
+    with ThreadPoolExecutor(max_workers=max(1, workers)) as ex:
+        return list(ex.map(lambda t: er(t[0], t[1], t[2]), sizes))
+
+
 def grid(R: int, C: int) -> Graph:
     m = R * (C - 1) + (R - 1) * C
     eu = np.zeros(max(m, 1), dtype=np.uint32)
