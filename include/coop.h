@@ -183,7 +183,8 @@ int coop_mis(coop_rt* rt, const coop_graph* g, uint64_t prio_seed, uint8_t* d_in
 
 /* Generic launch by kernel id with a parameter block (immutable, copied). */
 enum { COOP_KERNEL_BFS = 1, COOP_KERNEL_SSSP = 2, COOP_KERNEL_COLOR = 3, COOP_KERNEL_MIS = 4,
-       COOP_KERNEL_BARRIER = 5, COOP_KERNEL_BATCH = 6 /* handles of coop_batch_run only */ };
+       COOP_KERNEL_BARRIER = 5, COOP_KERNEL_BATCH = 6 /* handles of coop_batch_run only */,
+       COOP_KERNEL_SERVE = 7 /* the launch inside a coop_server */ };
 typedef struct coop_params {
     const coop_graph* graph;
     const uint32_t* d_roots;
@@ -317,6 +318,92 @@ int coop_batch_run(coop_rt* rt, const coop_batch_item* items, uint32_t count, co
 int coop_batch_autotune(coop_rt* rt, const coop_batch_item* items, uint32_t count, uint32_t stride,
                         uint32_t reps, const coop_launch_opts* opts, coop_stream_t stream, coop_tune* best,
                         double* best_ms, double* default_ms);
+
+/* ------------------------------------------------------------ serving */
+
+/* A query server: ONE persistent cooperative launch that runs BFS and SSSP
+ * queries on resident graphs as they are submitted (continuous batching).
+ * Each query gets a slot of HBM state (the budget decides how many slots
+ * exist) and a team of workgroups sized to its graph; queries that arrive
+ * while others run are admitted as soon as a slot frees up and run beside
+ * them. With COOP_F_HOST_SCHEDULE the server's launch honours
+ * coop_set_target on coop_server_handle(): workgroups leave between queries
+ * and teams give up members at their barriers, never below team_max
+ * workgroups in total; coop_fork_groups brings workgroups back. A query's
+ * result never depends on what else runs or on the schedule. */
+typedef struct coop_server coop_server;
+enum { COOP_QUERY_BFS = 1, COOP_QUERY_SSSP = 2 };
+
+typedef struct coop_server_cfg {
+    uint32_t mode;            /* COOP_MODE_PLAIN or COOP_MODE_COOP */
+    uint32_t flags;           /* COOP_F_HOST_SCHEDULE */
+    uint32_t num_groups;      /* launch limit N; 0 = all resident workgroups */
+    uint32_t group_size;      /* 0 = 1024 */
+    uint32_t max_queries;     /* slots; 0 = as many as the budget holds, at most 1024 */
+    uint32_t team_max;        /* largest team, <= N; 0 = max(1, N / 4) */
+    uint64_t team_arcs_bfs;   /* team = clamp(ceil((arcs + n) / team_arcs), 1, team_max); 0 = 2^22 */
+    uint64_t team_arcs_sssp;  /* likewise for SSSP queries; 0 = 2^22 */
+    uint32_t direction_opt;   /* BFS: 1 = direction-optimising, 0 = top-down only */
+    uint32_t heavy_threshold; /* 0 = 128 */
+    uint32_t strip;           /* 0 = 4096 */
+    uint32_t reserved;
+    uint64_t watchdog_ns;     /* barrier spin bound; 0 = 10 s */
+} coop_server_cfg;
+
+typedef struct coop_serve_stats {
+    uint64_t submitted;       /* queries submitted */
+    uint64_t completed;       /* queries finished */
+    uint64_t count_bfs, count_sssp;        /* finished, by kind */
+    double latency_p50_ms[2]; /* submit -> completion seen by the host; [0] BFS, [1] SSSP */
+    double latency_p99_ms[2];
+    double wait_p50_ms;       /* submit -> admitted into a slot */
+    double wait_p99_ms;
+    uint64_t slot_bytes;      /* HBM state per slot */
+    uint32_t slots;           /* query slots */
+    uint32_t in_flight;       /* queries in slots now */
+    uint32_t queued;          /* queries waiting for a slot */
+    uint32_t kills;           /* workgroups that left for the scheduler */
+    uint32_t forks;           /* joiner workgroups that entered */
+    uint32_t min_groups;      /* fewest active workgroups */
+    uint32_t max_groups;      /* most active workgroups */
+    int32_t error;            /* first error (COOP_OK if none) */
+} coop_serve_stats;
+
+void coop_server_cfg_default(coop_server_cfg* cfg);
+
+/* Start a server over `ngraphs` resident graphs (they must outlive it; SSSP
+ * queries need weights). hbm_budget: bytes of device memory for query
+ * state; slots = min(max_queries, budget / slot_bytes), where slot_bytes
+ * covers either kind of query on the largest graph. Errors: COOP_E_INVALID,
+ * COOP_E_BUSY (the budget holds no slot), COOP_E_OOM, COOP_E_HIP. The launch
+ * runs on a stream of the server's own. */
+int coop_server_create(coop_rt* rt, const coop_graph* const* graphs, uint32_t ngraphs, uint64_t hbm_budget,
+                       const coop_server_cfg* cfg, coop_server** out);
+
+/* Queue a query: BFS levels (uint32, n) or SSSP distances (int32, n) of
+ * `g` (one of the server's graphs) from `src` into d_out (device memory,
+ * caller-owned, untouched until the query completes). Never blocks: the
+ * query waits in the host queue until a slot is free. *ticket identifies it.
+ * Errors: COOP_E_INVALID (unknown graph, bad kind or source, SSSP without
+ * weights), COOP_E_BUSY (the server has no slot at all). */
+int coop_server_submit(coop_server* s, const coop_graph* g, int kind, uint32_t src, void* d_out,
+                       uint64_t* ticket);
+
+/* done = 1 once the query's results are in d_out; latency_ms (nullable)
+ * then gets submit -> completion. Returns the query's error code. */
+int coop_server_poll(coop_server* s, uint64_t ticket, int* done, double* latency_ms);
+
+/* Block until the query completes (or timeout_ms passes: COOP_E_TIMEOUT). */
+int coop_server_wait(coop_server* s, uint64_t ticket, double timeout_ms, double* latency_ms);
+
+int coop_server_stats(coop_server* s, coop_serve_stats* out);
+
+/* The server's persistent launch, for coop_set_target / coop_fork_groups /
+ * coop_injector_start (not for coop_wait). */
+coop_handle* coop_server_handle(coop_server* s);
+
+/* Finish queued queries, stop the launch, free everything. */
+int coop_server_destroy(coop_server* s);
 
 /* ------------------------------------------------------ measurements */
 

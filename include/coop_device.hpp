@@ -49,6 +49,7 @@ constexpr uint32_t kMaxGroups = 2048;        // launch limit N
 // release-word flags
 constexpr uint32_t kFlagDone = 1u;          // kernel finished: everybody leaves
 constexpr uint32_t kFlagAbort = 2u;         // watchdog fired or error: leave
+constexpr uint32_t kFlagRenum = 4u;         // kills chose their victims: read the new id
 constexpr uint32_t kFlagUser0 = 16u;        // algorithm-specific bits start here
 
 // Cfg::mode bits
@@ -81,7 +82,15 @@ struct Cfg {
     uint32_t epoch0_wait;     // ticks ticket 0 waits for the grid to register
     uint32_t wgtrace_cap;     // barriers the per-workgroup trace holds
     uint64_t* wgtrace;        // optional: per barrier and logical id, 4 timestamps
+    uint32_t xcds;            // accelerator dies (XCDs) workgroups are dealt over
+    uint32_t slots_per_xcd;   // workgroups of this kernel one XCD holds at once
 };
+
+// The XCD (accelerator complex die) this workgroup runs on: hardware
+// register XCC_ID, bits 3:0.
+__device__ __forceinline__ uint32_t xcd_id() {
+    return __builtin_amdgcn_s_getreg((3u << 11) | (0u << 6) | 20u) & 0xFu;
+}
 
 // Per-workgroup phase trace points (debugging and tuning only).
 enum WgTracePoint : uint32_t { kTrStart = 0, kTrWorkDone = 1, kTrArrive = 2, kTrReleased = 3 };
@@ -123,10 +132,14 @@ struct alignas(256) CtxCore {
     uint32_t _pm[50];
 };
 
-// Context of a resizable launch: barrier lines plus the joiner admission
-// ring, entries {slot:32 (lo) | epoch_lo:16 | id:16 (hi)}.
+// Context of a resizable launch: barrier lines, the joiner admission ring
+// (entries {slot:32 (lo) | epoch_lo:16 | id:16 (hi)}), the XCD of every
+// logical id, and the new ids of a barrier that chose its kill victims
+// ({epoch_lo:16 (hi) | new id:16 (lo)}, new id 0xFFFF = killed).
 struct alignas(256) Ctx : CtxCore {
     uint64_t join_entry[kJoinCap];
+    uint32_t xcd_of[kMaxGroups];
+    uint32_t renum[kMaxGroups];
 };
 
 // ------------------------------------------------------------- atomics
@@ -193,7 +206,12 @@ struct BarrierLds {
     uint32_t is_master;     // this workgroup runs the master step
     uint32_t flags;         // master step result (broadcast inside the master)
     uint32_t head, kmax, T;
+    uint32_t kmax2;                    // kill count of the barrier
+    uint32_t my_new;                   // XCD-aware kill: the master's new id
     uint32_t valid[kMaxGroups / 32];   // admission: ring slots whose joiner was still waiting
+    uint32_t xcnt[16];                 // XCD-aware kill: members per XCD, then victims per XCD
+    uint32_t wsum[kMaxWaves + 1];      // XCD-aware kill: survivors per wave of ids
+    uint8_t xcd[kMaxGroups];           // XCD-aware kill: XCD of every logical id
 };
 
 // Raise the abort flag so every spinning workgroup leaves.
@@ -265,6 +283,7 @@ __device__ inline Member join_queue(Ctx* c, const Cfg cfg) {
             m.epoch = rel_epoch(r);
             m.flags = rel_flags(r);
             m.alive = (m.flags & (kFlagAbort | kFlagDone)) ? 0u : 1u;
+            if (m.alive) st_relaxed(&c->xcd_of[m.id], xcd_id());
             return m;
         }
         bool leave = (rel_flags(r) & (kFlagAbort | kFlagDone)) != 0;
@@ -303,6 +322,7 @@ __device__ inline Member register_member(Ctx* c, const Cfg cfg, bool plain, bool
             m.id = 0;
             m.M = 1;
             m.alive = 1;
+            st_relaxed(&c->xcd_of[0], xcd_id());
             return m;
         }
     }
@@ -397,14 +417,83 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
             __syncthreads();
         }
     }
+    // kill decision: W = the surplus over the target, never workgroup 0
+    if (threadIdx.x == 0) {
+        uint32_t W = 0;
+        if (Coop && !(b.flags & (kFlagDone | kFlagAbort))) {
+            const uint32_t M2 = m.M + admitted;
+            W = M2 > b.T ? M2 - b.T : 0u;
+            if (W > M2 - 1) W = M2 - 1;
+        }
+        b.kmax2 = W;
+    }
+    // A host-driven target asks for compute units for another kernel, whose
+    // workgroups the hardware deals round-robin over the XCDs: choose the
+    // victims so that every XCD frees its share (then renumber the rest).
+    bool renum = false;
+    uint32_t Mn_sel = 0, my_new = m.id;
+    if constexpr (Coop) {
+        __syncthreads();
+        const uint32_t W = b.kmax2;
+        if (W && cfg.host && !(cfg.mode & kModeRandomSched) && cfg.xcds > 1) {
+            renum = true;
+            const uint32_t M2 = m.M + admitted;
+            for (uint32_t t = threadIdx.x; t < M2; t += blockDim.x) b.xcd[t] = (uint8_t)ld_relaxed(&c->xcd_of[t]);
+            if (threadIdx.x < 16) b.xcnt[threadIdx.x] = 0;
+            __syncthreads();
+            for (uint32_t t = threadIdx.x; t < M2; t += blockDim.x) atomicAdd(&b.xcnt[b.xcd[t] & 15u], 1u);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const uint32_t need = (W + cfg.xcds - 1) / cfg.xcds;
+                for (uint32_t x = 0; x < 16; ++x) {
+                    const uint32_t cnt = b.xcnt[x];
+                    const uint32_t idle = cfg.slots_per_xcd > cnt ? cfg.slots_per_xcd - cnt : 0u;
+                    uint32_t k = need > idle ? need - idle : 0u;
+                    const uint32_t cap = cnt - (x == b.xcd[0] ? 1u : 0u);     // workgroup 0 stays
+                    b.xcnt[x] = k < cap ? k : cap;
+                }
+            }
+            __syncthreads();
+            // id t is a victim if fewer than xcnt[its XCD] higher ids share its XCD
+            uint32_t carry = 0;
+            for (uint32_t base = 0; base < M2; base += blockDim.x) {
+                const uint32_t t = base + threadIdx.x;
+                bool alive = false;
+                if (t < M2) {
+                    const uint32_t x = b.xcd[t];
+                    uint32_t above = 0;
+                    for (uint32_t u = t + 1; u < M2; ++u) above += b.xcd[u] == x ? 1u : 0u;
+                    alive = t == 0 || above >= b.xcnt[x & 15u];
+                }
+                const uint64_t bal = __ballot(alive);
+                if ((threadIdx.x & 63) == 0) b.wsum[threadIdx.x / 64] = (uint32_t)__popcll(bal);
+                __syncthreads();
+                uint32_t before = carry;
+                for (uint32_t w = 0; w < threadIdx.x / 64; ++w) before += b.wsum[w];
+                const uint32_t nid = before + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                if (t < M2) {
+                    __hip_atomic_store(&c->renum[t], ((ne & 0xFFFFu) << 16) | (alive ? nid : 0xFFFFu),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (alive) st_relaxed(&c->xcd_of[nid], b.xcd[t]);
+                }
+                if (t == m.id) b.my_new = alive ? nid : 0xFFFFu;
+                for (uint32_t w = 0; w < blockDim.x / 64; ++w) carry += b.wsum[w];
+                __syncthreads();
+            }
+            Mn_sel = carry;
+            my_new = b.my_new;
+            __syncthreads();
+        }
+    }
     if (threadIdx.x == 0) {
         flags = b.flags;
         uint32_t Mn = m.M;
         if (Coop && !(flags & (kFlagDone | kFlagAbort))) {
             const uint32_t M2 = m.M + admitted;
-            uint32_t W = M2 > b.T ? M2 - b.T : 0u;
-            if (W > M2 - 1) W = M2 - 1;
+            const uint32_t W = renum ? M2 - Mn_sel : b.kmax2;
             Mn = M2 - W;
+            if (renum) flags |= kFlagRenum;
             if (b.kmax) c->join_head = b.head + b.kmax;
             if (cfg.mode & kModeRandomSched) c->T_dev = T_dev;
             if (admitted) c->forks = forks + admitted;
@@ -425,13 +514,16 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
         }
         st_release64(&c->release, make_release(ne, Mn, flags));
         Member n = m;
-        n.epoch = ne;
+        n.epoch = m.epoch + 1;
         n.M = Mn;
         n.flags = flags;
         const bool over = (flags & (kFlagDone | kFlagAbort)) != 0;
-        n.alive = (over || (Coop && n.id >= Mn)) ? 0u : 1u;
+        bool gone = false;
+        if (Coop && !over) gone = renum ? my_new == 0xFFFFu : n.id >= Mn;
+        if (renum && !gone) n.id = my_new;
+        n.alive = (over || gone) ? 0u : 1u;
         b.member = n;
-        b.killed = (!over && Coop && n.id >= Mn) ? 1u : 0u;
+        b.killed = gone ? 1u : 0u;
     }
 }
 
@@ -472,7 +564,16 @@ __device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, Ma
         n.epoch = e;
         // an alive member cannot miss an epoch: a gap means it was killed
         uint32_t k = (Coop && e != m.epoch + 1) ? 1u : 0u;
-        if (Coop && n.id >= n.M) k = 1;
+        if constexpr (Coop) {
+            if (!k && (n.flags & kFlagRenum)) {
+                // victims chosen by XCD: the entry of this epoch holds the
+                // new id; an entry of a later epoch means it was killed here
+                const uint32_t ent = ld_relaxed(&c->renum[m.id]);
+                if ((ent >> 16) != (e & 0xFFFFu) || (ent & 0xFFFFu) == 0xFFFFu) k = 1;
+                else n.id = ent & 0xFFFFu;
+            }
+        }
+        if (Coop && !(n.flags & kFlagRenum) && n.id >= n.M) k = 1;
         if (n.flags & (kFlagDone | kFlagAbort)) k = 0;
         n.alive = (!k && !(n.flags & (kFlagDone | kFlagAbort))) ? 1u : 0u;
         b.member = n;

@@ -39,9 +39,14 @@ COOP_KERNEL_MIS = 4
 COOP_KERNEL_BARRIER = 5
 COOP_KERNEL_BATCH = 6
 
+COOP_KERNEL_SERVE = 7
+
 COOP_BATCH_BFS = 1
 COOP_BATCH_COLOR = 2
 COOP_BATCH_MIS = 4
+
+COOP_QUERY_BFS = 1
+COOP_QUERY_SSSP = 2
 
 UNREACHED_LEVEL = 0xFFFFFFFF
 UNREACHED_DIST = 0x7FFFFFFF
@@ -53,6 +58,8 @@ EXPORTS = [
     "coop_color", "coop_mis", "coop_launch", "coop_wait", "coop_handle_groups", "coop_set_target",
     "coop_fork_groups", "coop_cotask_run", "coop_injector_start", "coop_injector_stop",
     "coop_barrier_bench", "coop_tune_default", "coop_batch_run", "coop_batch_autotune",
+    "coop_server_cfg_default", "coop_server_create", "coop_server_submit", "coop_server_poll",
+    "coop_server_wait", "coop_server_stats", "coop_server_handle", "coop_server_destroy",
 ]
 
 
@@ -148,6 +155,34 @@ class coop_tune(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class coop_server_cfg(ctypes.Structure):
+    _fields_ = [
+        ("mode", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("num_groups", ctypes.c_uint32),
+        ("group_size", ctypes.c_uint32), ("max_queries", ctypes.c_uint32), ("team_max", ctypes.c_uint32),
+        ("team_arcs_bfs", ctypes.c_uint64), ("team_arcs_sssp", ctypes.c_uint64),
+        ("direction_opt", ctypes.c_uint32), ("heavy_threshold", ctypes.c_uint32), ("strip", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32), ("watchdog_ns", ctypes.c_uint64),
+    ]
+
+
+class coop_serve_stats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("count_bfs", ctypes.c_uint64),
+        ("count_sssp", ctypes.c_uint64), ("latency_p50_ms", ctypes.c_double * 2),
+        ("latency_p99_ms", ctypes.c_double * 2), ("wait_p50_ms", ctypes.c_double), ("wait_p99_ms", ctypes.c_double),
+        ("slot_bytes", ctypes.c_uint64), ("slots", ctypes.c_uint32), ("in_flight", ctypes.c_uint32),
+        ("queued", ctypes.c_uint32), ("kills", ctypes.c_uint32), ("forks", ctypes.c_uint32),
+        ("min_groups", ctypes.c_uint32), ("max_groups", ctypes.c_uint32), ("error", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            d[k] = list(v) if isinstance(v, ctypes.Array) else v
+        return d
+
+
 _lib = None
 VP = ctypes.c_void_p
 VPP = ctypes.POINTER(ctypes.c_void_p)
@@ -192,6 +227,15 @@ def load_library():
         "coop_barrier_bench": (i32, [VP, ctypes.POINTER(coop_launch_opts), u32, VP,
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(coop_stats)]),
         "coop_tune_default": (None, [ctypes.POINTER(coop_tune)]),
+        "coop_server_cfg_default": (None, [ctypes.POINTER(coop_server_cfg)]),
+        "coop_server_create": (i32, [VP, ctypes.POINTER(ctypes.c_void_p), u32, u64, ctypes.POINTER(coop_server_cfg),
+                                     VPP]),
+        "coop_server_submit": (i32, [VP, VP, i32, u32, VP, ctypes.POINTER(ctypes.c_uint64)]),
+        "coop_server_poll": (i32, [VP, u64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
+        "coop_server_wait": (i32, [VP, u64, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
+        "coop_server_stats": (i32, [VP, ctypes.POINTER(coop_serve_stats)]),
+        "coop_server_handle": (VP, [VP]),
+        "coop_server_destroy": (i32, [VP]),
         "coop_batch_run": (i32, [VP, ctypes.POINTER(coop_batch_item), u32, ctypes.POINTER(coop_tune),
                                  ctypes.POINTER(coop_launch_opts), VP, VPP]),
         "coop_batch_autotune": (i32, [VP, ctypes.POINTER(coop_batch_item), u32, u32, u32,
@@ -409,6 +453,60 @@ def coop_batch_autotune(rt, items, stride=1, reps=3, opts=None, stream=None) -> 
                                               ctypes.byref(best), ctypes.byref(bms), ctypes.byref(dms)),
            "coop_batch_autotune")
     return best, bms.value, dms.value
+
+
+def coop_server_cfg_default() -> coop_server_cfg:
+    c = coop_server_cfg()
+    load_library().coop_server_cfg_default(ctypes.byref(c))
+    return c
+
+
+def make_server_cfg(**kw) -> coop_server_cfg:
+    c = coop_server_cfg_default()
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def coop_server_create(rt, graphs, hbm_budget, cfg=None) -> int:
+    arr = (ctypes.c_void_p * len(graphs))(*graphs)
+    s = ctypes.c_void_p()
+    _check(load_library().coop_server_create(rt, arr, len(graphs), int(hbm_budget),
+                                             ctypes.byref(cfg) if cfg is not None else None, ctypes.byref(s)),
+           "coop_server_create")
+    return s.value
+
+
+def coop_server_submit(srv, graph, kind, src, out) -> int:
+    t = ctypes.c_uint64()
+    _check(load_library().coop_server_submit(srv, graph, kind, src, _ptr(out), ctypes.byref(t)), "coop_server_submit")
+    return t.value
+
+
+def coop_server_poll(srv, ticket) -> tuple[int, bool, float]:
+    done, lat = ctypes.c_int(), ctypes.c_double()
+    rc = load_library().coop_server_poll(srv, ticket, ctypes.byref(done), ctypes.byref(lat))
+    return rc, bool(done.value), lat.value
+
+
+def coop_server_wait(srv, ticket, timeout_ms=60000.0) -> tuple[int, float]:
+    lat = ctypes.c_double()
+    rc = load_library().coop_server_wait(srv, ticket, timeout_ms, ctypes.byref(lat))
+    return rc, lat.value
+
+
+def coop_server_stats(srv) -> dict:
+    st = coop_serve_stats()
+    _check(load_library().coop_server_stats(srv, ctypes.byref(st)), "coop_server_stats")
+    return st.as_dict()
+
+
+def coop_server_handle(srv) -> int:
+    return load_library().coop_server_handle(srv)
+
+
+def coop_server_destroy(srv) -> int:
+    return load_library().coop_server_destroy(srv)
 
 
 # ------------------------------------------------------------- convenience

@@ -39,10 +39,12 @@ __device__ __forceinline__ void bfs_team(const BfsArgs& p, BlockLds& sh, uint32_
     Member m{rank, team, 0u, 0u, 1u};
     uint32_t level = 0, root = 0, ph = kPhInit;
     for (;;) {
-        bfs_phase(p, sh, ph, m.flags, level, root, m.id, m.M);
+        bfs_phase(p, sh, ph, m.flags, level, root, m.id, m.M, p.level_out);
         const uint32_t cur_flags = m.flags, cur_ph = ph;
         team_barrier(c, p.t.cfg, m, sh.bar,
-                     [&](uint32_t, uint32_t) -> uint32_t { return bfs_master(p, sh, c, cur_ph, cur_flags); });
+                     [&](uint32_t, uint32_t) -> uint32_t {
+                         return bfs_master(p, sh, c, cur_ph, cur_flags, p.t.roots, p.level_out);
+                     });
         if (!m.alive) return;
         bfs_follow(ph, m.flags, level, root);
         ph = m.flags & kPhMask;
@@ -64,32 +66,19 @@ __device__ __forceinline__ void color_team(const ColorArgs& p, BlockLds& sh, uin
     }
 }
 
-// offer_kill between instances (thread 0): leave when the scheduler wants
-// fewer workgroups than are active, never going below team_max.
+// offer_kill between instances (thread 0): the host target or a seeded
+// random decision, never below team_max workgroups.
 template <bool Coop>
-__device__ bool batch_offer_kill(const BatchArgs& a, BatchCtl* ctl) {
+__device__ bool batch_offer_kill(const BatchArgs& a, BatchCtl* ctl, uint32_t x) {
     if (!Coop) return false;
-    uint32_t T;
+    const LeaveCounters lc{&ctl->active, ctl->active_x, &ctl->kills, &ctl->min_active};
     if (a.cfg.mode & kModeRandomSched) {
         const uint32_t d = add_relaxed(&ctl->decisions, 1u);
         const uint64_t h = splitmix64(a.cfg.sched_seed + (uint64_t)d * 0x9E3779B97F4A7C15ull);
         if ((uint32_t)(h & 0xFFFFu) >= a.cfg.sched_p16) return false;
-        T = 0;
-    } else if (a.cfg.host) {
-        T = ld_system(&a.cfg.host->target);
-    } else {
-        return false;
+        return leave_for_target(lc, 0u, a.team_max, 1u, x);
     }
-    const uint32_t floor = T > a.team_max ? T : a.team_max;
-    uint32_t cur = ld_relaxed(&ctl->active);
-    while (cur > floor) {
-        if (__hip_atomic_compare_exchange_strong(&ctl->active, &cur, cur - 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT)) {
-            add_relaxed(&ctl->kills, 1u);
-            atomicMin(&ctl->min_active, cur - 1);
-            return true;
-        }
-    }
+    if (a.cfg.host) return leave_for_target(lc, ld_system(&a.cfg.host->target), a.team_max, a.cfg.xcds, x);
     return false;
 }
 
@@ -105,13 +94,14 @@ __device__ void batch_body(const BatchArgs& a, bool joiner) {
         for (uint32_t i = 0; i < num_waves(); ++i) sh.wave[i].out_n = 0;
         for (int i = 0; i < 8; ++i) sh.acc[i] = 0;
         const uint32_t act = add_relaxed(&ctl->active, 1u) + 1;
+        add_relaxed(&ctl->active_x[xcd_id()], 1u);
         atomicMax(&ctl->max_active, act);
         if (joiner) add_relaxed(&ctl->forks, 1u);
     }
     for (;;) {
         if (threadIdx.x == 0) {
             uint32_t leave = ld_relaxed_i(&ctl->error) ? 1u : 0u;
-            if (!leave && batch_offer_kill<Coop>(a, ctl)) leave = 2;
+            if (!leave && batch_offer_kill<Coop>(a, ctl, xcd_id())) leave = 2;
             if (!leave) {
                 const uint32_t k = add_relaxed(&ctl->ticket, 1u);
                 if (k >= total) {
@@ -128,6 +118,7 @@ __device__ void batch_body(const BatchArgs& a, bool joiner) {
             }
             if (leave == 1 || leave == 3) {
                 add_relaxed(&ctl->active, 0xFFFFFFFFu);
+                add_relaxed(&ctl->active_x[xcd_id()], 0xFFFFFFFFu);
                 add_relaxed(&ctl->left, 1u);
             }
             sh.level = leave;
@@ -194,6 +185,15 @@ hipError_t launch_batch(const BatchArgs& a, bool coop, bool joiner_grid, uint32_
                               (int)lds_bytes);
     hipLaunchKernelGGL(k, dim3(grid), dim3(block), lds_bytes, s, a, joiner_grid ? 1 : 0);
     return hipGetLastError();
+}
+
+uint32_t occupancy_batch(bool coop, uint32_t block, uint32_t lds_bytes) {
+    auto k = coop ? batch_kernel<true> : batch_kernel<false>;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds_bytes);
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, (int)block, lds_bytes) != hipSuccess) return 1;
+    return n > 0 ? (uint32_t)n : 1u;
 }
 
 }  // namespace coop

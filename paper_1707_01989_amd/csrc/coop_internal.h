@@ -88,6 +88,7 @@ enum SlotField : uint32_t {
     kSlotRows = 3,        // cumulative: row ranges read
     kSlotBitmap = 4,      // cumulative: bitmap words streamed
     kSlotFoundAll = 5,    // cumulative: vertices reached / queued
+    kSlotXcd = 12,        // serving: XCD of the team member with this rank (a 32-bit word)
 };
 
 struct TraversalArgs {
@@ -192,6 +193,8 @@ struct alignas(256) BatchCtl {
     uint32_t min_active;
     uint32_t max_active;
     uint32_t _p2[57];
+    uint32_t active_x[16];     // active workgroups per XCD
+    uint32_t _p3[48];
 };
 
 struct BatchArgs {
@@ -206,8 +209,89 @@ struct BatchArgs {
 
 hipError_t launch_batch_init(TeamState* teams, const BatchInst* inst, uint32_t count, BatchCtl* ctl,
                              hipStream_t s);
+
+// ------------------------------------------------------------- serving
+
+constexpr uint32_t kQueryBfs = 1u;
+constexpr uint32_t kQuerySssp = 2u;
+
+// Argument blocks of a query of one resident graph in one slot's state
+// (slot-major: desc[slot * graphs + graph]). Written before the server
+// kernel starts and never changed while it runs, so they are read through
+// the constant address space.
+struct alignas(16) ServeDesc {
+    BfsArgs bfs;
+    SsspArgs sssp;
+};
+
+// A published query (one per slot, pinned host memory, written by the host
+// before it publishes the query's tickets).
+struct alignas(64) ServeReq {
+    uint32_t desc;             // ServeDesc index
+    uint32_t kind;             // kQueryBfs / kQuerySssp
+    uint32_t src;              // source vertex (the team's root list points here)
+    uint32_t team;             // workgroups of the team
+    uint32_t first;            // first ticket of the team
+    uint32_t pad0;
+    uint64_t out;              // device pointer: n levels (BFS) or distances (SSSP)
+    uint64_t seq;              // query number, echoed in the completion word
+    uint32_t pad1[6];
+};
+
+// Host-written words of the server (pinned).
+struct alignas(64) ServeHost {
+    uint32_t ticket_end;       // tickets below this are published
+    uint32_t stop;             // 1: leave once no ticket is left
+    uint32_t pad[14];
+};
+
+// Completion record of a slot (pinned): written by the last member of the
+// team to leave the query.
+struct alignas(64) ServeDone {
+    uint64_t seq;              // query number that finished
+    uint64_t t_end;            // device wall clock at completion
+    int32_t error;             // the slot's barrier error, if any
+    uint32_t pad[11];
+};
+
+struct alignas(256) ServeCtl {
+    uint32_t ticket;           // next ticket to draw
+    uint32_t _p0[63];
+    uint32_t active;           // workgroups inside the server loop
+    uint32_t _p1[63];
+    int32_t error;
+    uint32_t kills;            // workgroups that left for the scheduler
+    uint32_t forks;            // joiner workgroups that entered
+    uint32_t left;             // workgroups that left at shutdown
+    uint32_t min_active;
+    uint32_t max_active;
+    uint32_t queries;          // queries completed
+    uint32_t _p2[57];
+    uint32_t active_x[16];     // active workgroups per XCD
+    uint32_t _p3[48];
+};
+
+struct ServeArgs {
+    Cfg cfg;                   // N, mode, host target (co-task), watchdog
+    const ServeDesc* desc;     // slots x graphs descriptors
+    TeamState* teams;          // per slot: barrier lines and transmit block
+    ServeCtl* ctl;
+    ServeHost* host;           // pinned control words
+    const ServeReq* req;       // pinned, one per slot
+    const uint32_t* owner;     // pinned, ticket -> slot (owner_cap entries)
+    ServeDone* done;           // pinned, one per slot
+    uint32_t owner_cap;
+    uint32_t team_max;         // the kill rule keeps at least this many workgroups
+};
+
+hipError_t launch_serve_init(TeamState* teams, uint32_t slots, ServeCtl* ctl, hipStream_t s);
+hipError_t launch_serve(const ServeArgs& a, bool coop, bool joiner_grid, uint32_t grid, uint32_t block,
+                        uint32_t lds_bytes, hipStream_t s);
+uint32_t occupancy_serve(bool coop, uint32_t block, uint32_t lds_bytes);
 hipError_t launch_batch(const BatchArgs& a, bool coop, bool joiner_grid, uint32_t grid, uint32_t block,
                         uint32_t lds_bytes, hipStream_t s);
+// Workgroups of the batched kernel one CU holds at this size (registers, LDS, waves).
+uint32_t occupancy_batch(bool coop, uint32_t block, uint32_t lds_bytes);
 
 // Launchers (defined in coop_kernels.hip). Each returns a hipError_t.
 hipError_t launch_init_ctx(Ctx* c, Work* w, hipStream_t s);
@@ -224,6 +308,8 @@ hipError_t launch_barrier_bench(const BarrierBenchArgs& a, bool coop, bool joine
                                 uint32_t block, uint32_t lds_bytes, hipStream_t s);
 hipError_t launch_cotask(const CotaskArgs& a, uint32_t block, uint32_t lds_bytes, hipStream_t s);
 uint32_t kernel_lds_bytes();   // LDS the traversal kernels need at least
+// out[g] = XCD of workgroup g, for `groups` one-wave workgroups
+hipError_t launch_xcd_probe(uint32_t* out, uint32_t groups, hipStream_t s);
 uint32_t kernel_lds_bytes_for(uint32_t block);   // ... with `block` threads per workgroup
 
 }  // namespace coop

@@ -75,72 +75,19 @@ __device__ void bfs_body(const BfsArgs& p, bool joiner_grid) {
         const uint32_t ph = fresh ? kPhStart : (m.flags & kPhMask);
         fresh = false;
         wg_trace(t.cfg, m.epoch, m.id, kTrStart);
-        bfs_phase(p, sh, ph, m.flags, level, root, m.id, m.M);
+        bfs_phase(p, sh, ph, m.flags, level, root, m.id, m.M, p.level_out);
         wg_trace(t.cfg, m.epoch, m.id, kTrWorkDone);
         const uint32_t cur_flags = m.flags;
         barrier<Coop>(c, t.cfg, m, sh.bar,
-                      [&](uint32_t, uint32_t) -> uint32_t { return bfs_master(p, sh, c, ph, cur_flags); });
+                      [&](uint32_t, uint32_t) -> uint32_t {
+                          return bfs_master(p, sh, c, ph, cur_flags, t.roots, p.level_out);
+                      });
         bfs_follow(ph, m.flags, level, root);
     }
 }
 
 // ----------------------------------------------------------------- SSSP
 
-struct SsspVisit {
-    uint64_t* state;        // {distance (hi) | tag (lo)}
-    const uint32_t* w;
-    uint32_t tag;           // tag meaning "queued for the next round"
-    CtxCore* ctx;
-    uint32_t* out_tail;
-    uint32_t* out;
-
-    __device__ __forceinline__ uint32_t payload(uint32_t v) const {
-        return (uint32_t)(ld_relaxed64(&state[v]) >> 32);
-    }
-    __device__ __forceinline__ uint32_t strip_payload(uint32_t, uint32_t v) const { return payload(v); }
-    __device__ __forceinline__ void maybe_flush(WaveLds& wl) {
-        if (wl.out_n > kFlushAt) wave_flush(wl, out_tail, out);
-    }
-
-    // Frontier Bellman-Ford relaxation. One 64-bit atomicMin on {distance,
-    // tag} lowers the distance and, through the old tag it returns, tells
-    // whether the vertex is already queued for the next round (tags only
-    // grow, so an equal distance never changes the word).
-    __device__ __forceinline__ void step(const bool* ok, const uint32_t* arc, const uint32_t* u,
-                                         const uint32_t* pay, WaveLds& wl, Stats& st) {
-        uint32_t wt[kUnroll];
-        uint32_t du[kUnroll];
-#pragma unroll
-        for (uint32_t j = 0; j < kUnroll; ++j) wt[j] = ok[j] ? __builtin_nontemporal_load(&w[arc[j]]) : 0u;
-#pragma unroll
-        for (uint32_t j = 0; j < kUnroll; ++j) du[j] = ok[j] ? (uint32_t)(state[u[j]] >> 32) : 0u;
-        bool win[kUnroll];
-#pragma unroll
-        for (uint32_t j = 0; j < kUnroll; ++j) {
-            win[j] = false;
-            if (!ok[j]) continue;
-            const uint64_t nd64 = (uint64_t)pay[j] + (uint64_t)wt[j];
-            if (nd64 >= 0x7FFFFFFFull) {
-                if (pay[j] != 0x7FFFFFFFu) raise_error(ctx, kErrOverflow);
-                continue;
-            }
-            const uint32_t nd = (uint32_t)nd64;
-            if (nd < du[j]) {
-                const uint64_t old = __hip_atomic_fetch_min(&state[u[j]], ((uint64_t)nd << 32) | tag,
-                                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                win[j] = nd < (uint32_t)(old >> 32) && (uint32_t)old != tag;
-            }
-        }
-#pragma unroll
-        for (uint32_t j = 0; j < kUnroll; ++j) {
-            st.found += win[j] ? 1u : 0u;
-            wave_push(wl, win[j], u[j]);
-        }
-    }
-};
-
-// Queue engine (SSSP): phases INIT (clear), TD (expand the input queue,
-// 64-entry units distributed statically), HEAVY; one barrier per phase.
 template <bool Coop>
 __device__ void sssp_body(const SsspArgs& p, bool joiner_grid) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -148,7 +95,6 @@ __device__ void sssp_body(const SsspArgs& p, bool joiner_grid) {
     const TraversalArgs& t = p.t;
     Ctx* c = static_cast<Ctx*>(t.ctx);
     Work* wk = t.work;
-    const uint32_t nw = num_waves();
 
     if (threadIdx.x == 0) {
         Member m = register_member(c, t.cfg, !Coop, joiner_grid);
@@ -186,94 +132,13 @@ __device__ void sssp_body(const SsspArgs& p, bool joiner_grid) {
         }
         const uint32_t ph = fresh ? kPhStart : (m.flags & kPhMask);
         fresh = false;
-        const bool sel = (m.flags & kFlagSel) != 0;
-        uint32_t* in = t.frontier[sel ? 1 : 0];
-        uint32_t* out = t.frontier[sel ? 0 : 1];
-        int32_t* dist = p.dist_out + (size_t)root * t.out_stride;
-        const uint32_t gw = m.id * nw + wave_id();
-        const uint32_t W = m.M * nw;
-        Stats st;
-
-        if (ph == kPhInit) {
-            // distances to "unreached"; tags to 0 (no round uses tag 0)
-            const uint32_t tid = m.id * blockDim.x + threadIdx.x, stride = m.M * blockDim.x;
-            for (uint32_t i = tid; i < t.n; i += stride) p.state[i] = 0x7FFFFFFFull << 32;
-        } else if (ph == kPhOut) {
-            const uint32_t tid = m.id * blockDim.x + threadIdx.x, stride = m.M * blockDim.x;
-            for (uint32_t i = tid; i < t.n; i += stride) dist[i] = (int32_t)(p.state[i] >> 32);
-        } else if (ph == kPhTD || ph == kPhHeavy) {
-            wg_trace(t.cfg, m.epoch, m.id, kTrStart);
-            if (threadIdx.x == 0) sh.in_size = wk->x.in_size;
-            __syncthreads();
-            const uint32_t size = sh.in_size;
-            SsspVisit vis{p.state, t.w, round + 2, c, &wk->out_tail, out};
-            WaveLds& w = sh.wave[wave_id()];
-            if (ph == kPhTD) {
-                const uint32_t units = (size + kWave - 1) / kWave;
-                for (uint32_t u = gw; u < units; u += W) {
-                    const uint32_t i = u * kWave + lane_id();
-                    const bool act = i < size;
-                    expand_batch(t, wk, w, act, act ? in[i] : 0u, vis, st);
-                }
-            } else {
-                heavy_phase(t, size, gw, W, w, vis, st);
-            }
-            wg_flush(sh, &wk->out_tail, out);
-            stats_to_lds(sh, st);
-            __syncthreads();
-            acc_to_slot(sh, t.slots, m.id);
-            wg_trace(t.cfg, m.epoch, m.id, kTrWorkDone);
-        }
-
+        wg_trace(t.cfg, m.epoch, m.id, kTrStart);
+        sssp_phase(p, sh, ph, m.flags, round, p.dist_out + (size_t)root * t.out_stride, m.id, m.M);
+        wg_trace(t.cfg, m.epoch, m.id, kTrWorkDone);
         const uint32_t cur_flags = m.flags;
-        barrier<Coop>(c, t.cfg, m, sh.bar, [&](uint32_t, uint32_t) -> uint32_t {
-            uint64_t tot[2];
-            master_sum_slots(sh, t.slots, t.N, tot);
-            if (threadIdx.x == 0) {
-                XferR x = wk->load_x();                 // one batch of loads
-                const uint32_t hs = ld_relaxed(&wk->heavy_tail);
-                const uint32_t ot = ld_relaxed(&wk->out_tail);
-                uint32_t res;
-                const uint32_t flags = cur_flags & kFlagSel;
-                if (ph == kPhStart) {
-                    x.root() = 0;
-                    res = kPhInit;
-                } else if (ph == kPhOut) {
-                    x.root() += 1;
-                    res = x.root() >= t.nroots ? kFlagDone : kPhInit;
-                } else if (ph == kPhInit) {
-                    const uint32_t r = t.roots[x.root()];
-                    p.state[r] = (uint64_t)(x.round() + 1);      // distance 0, queued for this round
-                    t.frontier[0][0] = r;
-                    x.in_size() = 1;
-                    wk->out_tail = 0;
-                    wk->heavy_tail = 0;
-                    res = kPhTD;               // input = buffer 0
-                } else if (ph == kPhTD && hs > 0) {
-                    if (hs > t.heavy_cap) raise_error(c, kErrInternal);
-                    x.in_size() = hs;
-                    wk->heavy_tail = 0;
-                    x.heavy_phases() += 1;
-                    res = flags | kPhHeavy;
-                } else {
-                    // round done: the output queue becomes the input
-                    wk->out_tail = 0;
-                    if (hs) wk->heavy_tail = 0;
-                    x.in_size() = ot;
-                    x.level() += 1;
-                    x.round() += 1;
-                    x.levels_total() += 1;
-                    res = ot == 0 ? (kPhOut | kFlagAdv) : ((flags ^ kFlagSel) | kPhTD | kFlagAdv);
-                }
-                wk->store_x(x);
-                sh.bar.flags = res;
-            }
-            __syncthreads();
-            return sh.bar.flags;
-        });
-        const uint32_t nph = m.flags & kPhMask;
-        if (m.flags & kFlagAdv) round += 1;
-        if (nph == kPhInit && ph == kPhOut) root += 1;
+        barrier<Coop>(c, t.cfg, m, sh.bar,
+                      [&](uint32_t, uint32_t) -> uint32_t { return sssp_master(p, sh, c, ph, cur_flags, t.roots); });
+        sssp_follow(ph, m.flags, round, root);
     }
 }
 
@@ -375,6 +240,11 @@ __global__ void init_ctx_kernel(Ctx* c, Work* w) {
     }
 }
 
+// Every workgroup records the XCD it runs on (the runtime counts XCDs).
+__global__ void xcd_probe_kernel(uint32_t* out) {
+    if (threadIdx.x == 0) out[blockIdx.x] = xcd_id();
+}
+
 __global__ void fill_u32_kernel(uint32_t* p, uint64_t count, uint32_t value) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (uint64_t)gridDim.x * blockDim.x)
@@ -416,6 +286,11 @@ __global__ void __launch_bounds__(256) cotask_kernel(CotaskArgs a) {
 namespace coop {
 
 uint32_t kernel_lds_bytes() { return (uint32_t)sizeof(BlockLds); }
+
+hipError_t launch_xcd_probe(uint32_t* out, uint32_t groups, hipStream_t s) {
+    hipLaunchKernelGGL(xcd_probe_kernel, dim3(groups), dim3(64), 0, s, out);
+    return hipGetLastError();
+}
 
 uint32_t kernel_lds_bytes_for(uint32_t block) {
     return (uint32_t)(offsetof(BlockLds, wave) + (size_t)(block / 64) * sizeof(WaveLds));

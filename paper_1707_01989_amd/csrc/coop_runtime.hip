@@ -19,6 +19,8 @@
 #include <new>
 #include <string>
 #include <tuple>
+#include <condition_variable>
+#include <deque>
 #include <thread>
 #include <vector>
 
@@ -107,12 +109,15 @@ struct coop_handle {
     coop::BatchCtl* bctl = nullptr;
     uint32_t* bslots = nullptr;
     size_t bslot_words = 0;
+    // serving launch
+    coop::ServeArgs serve{};
 };
 
 struct coop_rt {
     int device = 0;
     hipDeviceProp_t props{};
     uint32_t wall_khz = 100000;
+    uint32_t xcds = 1;                         // XCDs workgroups are dealt over
     hipStream_t joiner_stream = nullptr;
     hipStream_t cotask_stream = nullptr;
     std::recursive_mutex mu;
@@ -223,12 +228,14 @@ void* scratch(coop_handle* h, size_t bytes) {
 
 struct Sizing {
     uint32_t grid, block, lds, mode;
+    uint32_t resident;                         // workgroups of this size the device holds at once
     uint64_t watchdog_ticks;
     uint32_t startup_ticks, sched_p16;
     bool coop;
 };
 
-int size_launch(coop_rt* rt, const coop_launch_opts* o, Sizing* s, uint32_t min_lds = 0) {
+int size_launch(coop_rt* rt, const coop_launch_opts* o, Sizing* s, uint32_t min_lds = 0,
+                uint32_t (*occupancy)(bool, uint32_t, uint32_t) = nullptr) {
     coop_launch_opts d;
     coop_launch_opts_default(&d);
     if (!o) o = &d;
@@ -245,7 +252,9 @@ int size_launch(coop_rt* rt, const coop_launch_opts* o, Sizing* s, uint32_t min_
     uint32_t by_lds = (uint32_t)rt->props.maxSharedMemoryPerMultiProcessor / s->lds;
     uint32_t by_waves = 32 / (s->block / 64);
     uint32_t per_cu = std::max<uint32_t>(1, std::min(by_lds, by_waves));
+    if (occupancy) per_cu = std::max<uint32_t>(1, std::min(per_cu, occupancy(s->coop, s->block, s->lds)));
     const uint32_t resident = cus * per_cu;
+    s->resident = resident;
     s->grid = o->num_groups ? o->num_groups : resident;
     if (s->grid == 0 || s->grid > 0xFFFF) return COOP_E_INVALID;
     if (!s->coop && s->grid > resident) return COOP_E_INVALID;   // a plain barrier needs residency
@@ -304,6 +313,8 @@ int begin_launch(coop_rt* rt, const coop_launch_opts* o, const Sizing& sz, int k
     cfg.epoch0_wait = sz.startup_ticks;
     cfg.wgtrace = o ? o->d_wgtrace : nullptr;
     cfg.wgtrace_cap = (o && o->d_wgtrace) ? o->trace_cap : 0u;
+    cfg.xcds = rt->xcds;
+    cfg.slots_per_xcd = std::max<uint32_t>(1, sz.resident / std::max<uint32_t>(1, rt->xcds));
     hipError_t e = coop::launch_init_ctx(h->ctx, h->work, stream);
     if (e != hipSuccess) { handle_free(h); return hip_fail(rt, e); }
     *hout = h;
@@ -331,6 +342,7 @@ hipError_t relaunch(coop_handle* h, bool joiner, uint32_t grid, hipStream_t s) {
         case COOP_KERNEL_BARRIER:
             return coop::launch_barrier_bench(h->bb, h->coop, joiner, grid, h->block, h->lds, s);
         case COOP_KERNEL_BATCH: return coop::launch_batch(h->batch, h->coop, joiner, grid, h->block, h->lds, s);
+        case COOP_KERNEL_SERVE: return coop::launch_serve(h->serve, h->coop, joiner, grid, h->block, h->lds, s);
     }
     return hipErrorInvalidValue;
 }
@@ -442,6 +454,19 @@ int coop_init(int device, coop_rt** out) {
     if (e == hipSuccess) e = hipMalloc(&rt->d_cot, 256);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&rt->h_stamp), 64,
                                            hipHostMallocCoherent | hipHostMallocMapped);
+    if (e == hipSuccess) {
+        // count the XCDs: one small workgroup per slot of a 4x oversubscribed grid
+        const uint32_t groups = 4u * (uint32_t)std::max(1, rt->props.multiProcessorCount);
+        uint32_t* d = nullptr;
+        e = hipMalloc(&d, (size_t)groups * 4);
+        if (e == hipSuccess) e = coop::launch_xcd_probe(d, groups, nullptr);
+        std::vector<uint32_t> h(groups, 0);
+        if (e == hipSuccess) e = hipMemcpy(h.data(), d, (size_t)groups * 4, hipMemcpyDeviceToHost);
+        if (d) (void)hipFree(d);
+        uint32_t mx = 0;
+        for (uint32_t v : h) mx = std::max(mx, v);
+        rt->xcds = mx + 1;
+    }
     if (e != hipSuccess) {
         int rc = hip_fail(rt, e);
         coop_shutdown(rt);
@@ -722,7 +747,7 @@ static int batch_stats(coop_handle* h, coop_stats* stats) {
 }
 
 int coop_wait(coop_handle* h, coop_stats* stats) {
-    if (!h) return COOP_E_INVALID;
+    if (!h || h->kind == COOP_KERNEL_SERVE) return COOP_E_INVALID;   // a server owns its launch
     coop_rt* rt = h->rt;
     // poll (a blocking event wait could hold runtime locks the injector
     // thread needs for its own launches while the kernel runs)
@@ -874,7 +899,7 @@ int coop_batch_run(coop_rt* rt, const coop_batch_item* items, uint32_t count, co
     if (tn.heavy_threshold) o.heavy_threshold = tn.heavy_threshold;
     if (tn.strip) o.strip = tn.strip;
     Sizing sz{};
-    int rc = size_launch(rt, &o, &sz, coop::kernel_lds_bytes_for(tn.group_size));
+    int rc = size_launch(rt, &o, &sz, coop::kernel_lds_bytes_for(tn.group_size), coop::occupancy_batch);
     if (rc) return rc;
     const uint32_t team_max = tn.team_max ? tn.team_max : std::max<uint32_t>(1, sz.grid / 8);
     if (team_max > sz.grid) return COOP_E_INVALID;
@@ -1118,6 +1143,440 @@ int coop_batch_autotune(coop_rt* rt, const coop_batch_item* items, uint32_t coun
     if (best_ms) *best_ms = cur_ms;
     if (default_ms) *default_ms = def_ms;
     return COOP_OK;
+}
+
+// ----------------------------------------------------------------- serving
+
+struct coop_server {
+    coop_rt* rt = nullptr;
+    coop_handle* h = nullptr;                  // the persistent launch
+    hipStream_t stream = nullptr;
+    std::vector<const coop_graph*> graphs;
+    std::vector<uint32_t> team[2];             // per graph: team of a BFS / SSSP query
+    uint32_t slots = 0, team_max = 1, owner_cap = 0;
+    uint64_t slot_bytes = 0;
+    // pinned host memory shared with the kernel
+    coop::ServeHost* host = nullptr;
+    coop::ServeReq* req = nullptr;
+    uint32_t* owner = nullptr;
+    coop::ServeDone* done = nullptr;
+    // device memory (descriptors, slot lines, counters, slot state)
+    void* dev = nullptr;
+    coop::ServeCtl* ctl = nullptr;
+    // host scheduling
+    struct Query {
+        uint32_t gi = 0, kind = 0, src = 0, slot = 0;
+        void* out = nullptr;
+        double t_submit = 0, t_admit = 0, t_done = 0;
+        int state = 0;                          // 0 queued, 1 in a slot, 2 done
+        int err = 0;
+    };
+    std::mutex mu;
+    std::condition_variable cv;
+    std::map<uint64_t, Query> queries;
+    std::deque<uint64_t> pending;
+    std::vector<uint64_t> slot_seq;            // query in each slot (0 = free)
+    std::vector<uint32_t> free_slots;
+    uint32_t next_ticket = 0;
+    uint64_t next_seq = 1, submitted = 0, completed = 0;
+    std::vector<double> lat[2], waits;
+    int error = 0;
+    std::thread poller;
+    std::atomic<bool> stop_poller{false};
+};
+
+void coop_server_cfg_default(coop_server_cfg* c) {
+    if (!c) return;
+    std::memset(c, 0, sizeof(*c));
+    c->mode = COOP_MODE_COOP;
+    c->group_size = 1024;
+    c->team_arcs_bfs = 1ull << 22;
+    c->team_arcs_sssp = 1ull << 22;
+    c->direction_opt = 1;
+}
+
+namespace {
+
+// Publish a queued query into a free slot (server lock held).
+void server_publish(coop_server* sv, uint64_t seq) {
+    coop_server::Query& q = sv->queries[seq];
+    const uint32_t slot = sv->free_slots.back();
+    sv->free_slots.pop_back();
+    const uint32_t t = sv->team[q.kind == COOP_QUERY_SSSP ? 1 : 0][q.gi];
+    coop::ServeReq& r = sv->req[slot];
+    r.desc = slot * (uint32_t)sv->graphs.size() + q.gi;
+    r.kind = q.kind == COOP_QUERY_SSSP ? coop::kQuerySssp : coop::kQueryBfs;
+    r.src = q.src;
+    r.team = t;
+    r.first = sv->next_ticket;
+    r.out = reinterpret_cast<uint64_t>(q.out);
+    r.seq = seq;
+    for (uint32_t k = 0; k < t; ++k) sv->owner[(sv->next_ticket + k) % sv->owner_cap] = slot;
+    sv->next_ticket += t;
+    q.slot = slot;
+    q.state = 1;
+    q.t_admit = now_ms();
+    sv->waits.push_back(q.t_admit - q.t_submit);
+    sv->slot_seq[slot] = seq;
+    __atomic_thread_fence(__ATOMIC_SEQ_CST);
+    __atomic_store_n(&sv->host->ticket_end, sv->next_ticket, __ATOMIC_RELEASE);
+}
+
+// Completion records -> finished queries; queued queries -> freed slots.
+void server_poll_once(coop_server* sv) {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    bool any = false;
+    for (uint32_t s = 0; s < sv->slots; ++s) {
+        const uint64_t seq = sv->slot_seq[s];
+        if (!seq) continue;
+        if (__atomic_load_n(&sv->done[s].seq, __ATOMIC_ACQUIRE) != seq) continue;
+        coop_server::Query& q = sv->queries[seq];
+        q.state = 2;
+        q.t_done = now_ms();
+        q.err = __atomic_load_n(&sv->done[s].error, __ATOMIC_ACQUIRE);
+        if (q.err && !sv->error) sv->error = q.err;
+        sv->lat[q.kind == COOP_QUERY_SSSP ? 1 : 0].push_back(q.t_done - q.t_submit);
+        sv->slot_seq[s] = 0;
+        sv->free_slots.push_back(s);
+        ++sv->completed;
+        any = true;
+    }
+    while (!sv->pending.empty() && !sv->free_slots.empty()) {
+        const uint64_t seq = sv->pending.front();
+        sv->pending.pop_front();
+        server_publish(sv, seq);
+    }
+    if (any) sv->cv.notify_all();
+}
+
+void server_free(coop_server* sv) {
+    if (sv->host) (void)hipHostFree(sv->host);
+    if (sv->req) (void)hipHostFree(sv->req);
+    if (sv->owner) (void)hipHostFree(sv->owner);
+    if (sv->done) (void)hipHostFree(sv->done);
+    if (sv->dev) (void)hipFree(sv->dev);
+    if (sv->stream) (void)hipStreamDestroy(sv->stream);
+    delete sv;
+}
+
+}  // namespace
+
+int coop_server_create(coop_rt* rt, const coop_graph* const* graphs, uint32_t ngraphs, uint64_t hbm_budget,
+                       const coop_server_cfg* cfg, coop_server** out) {
+    if (!rt || !graphs || ngraphs == 0 || !out) return COOP_E_INVALID;
+    *out = nullptr;
+    coop_server_cfg c;
+    coop_server_cfg_default(&c);
+    if (cfg) c = *cfg;
+    if (!c.group_size) c.group_size = 1024;
+    if (!c.team_arcs_bfs) c.team_arcs_bfs = 1ull << 22;
+    if (!c.team_arcs_sssp) c.team_arcs_sssp = 1ull << 22;
+    uint32_t n_max = 0, words_max = 0;
+    uint64_t heavy_max = 0;
+    const uint32_t heavy_th = c.heavy_threshold ? c.heavy_threshold : kDefaultHeavy;
+    const uint32_t strip = c.strip ? c.strip : kDefaultStrip;
+    for (uint32_t i = 0; i < ngraphs; ++i) {
+        const coop_graph* g = graphs[i];
+        if (!g || g->rt != rt || g->n == 0) return COOP_E_INVALID;
+        n_max = std::max(n_max, g->n);
+        words_max = std::max(words_max, g->words);
+        heavy_max = std::max(heavy_max, const_cast<coop_graph*>(g)->heavy_strips(heavy_th, strip));
+    }
+    // slot state: SSSP {distance, tag} words and two queues, or the BFS
+    // bitmaps (smaller), plus the heavy-strip list and statistics slots
+    const size_t bfs_b = 4 * align_up((size_t)words_max * 4);
+    const size_t sssp_b = align_up((size_t)n_max * 8) + 2 * align_up((size_t)n_max * 4 + 4);
+    const size_t state_b = std::max(bfs_b, sssp_b) + align_up(heavy_max * 16);
+
+    coop_launch_opts o;
+    coop_launch_opts_default(&o);
+    o.mode = c.mode;
+    o.flags = c.flags & COOP_F_HOST_SCHEDULE;
+    o.num_groups = c.num_groups;
+    o.group_size = c.group_size;
+    o.watchdog_ns = c.watchdog_ns;
+    std::lock_guard<std::recursive_mutex> lk(rt->mu);
+    reap(rt);
+    Sizing sz{};
+    int rc = size_launch(rt, &o, &sz, coop::kernel_lds_bytes_for(c.group_size), coop::occupancy_serve);
+    if (rc) return rc;
+    const uint32_t team_max = c.team_max ? c.team_max : std::max<uint32_t>(1, sz.grid / 4);
+    if (team_max > sz.grid) return COOP_E_INVALID;
+    const size_t stats_b = align_up((size_t)team_max * coop::kSlotWords * 4);
+    const uint64_t slot_bytes = state_b + stats_b + sizeof(coop::TeamState);
+    uint64_t slots = hbm_budget / slot_bytes;
+    const uint32_t cap = c.max_queries ? std::min<uint32_t>(c.max_queries, 1024u) : 1024u;
+    slots = std::min<uint64_t>(slots, cap);
+    if (slots == 0) return COOP_E_BUSY;
+
+    coop_server* sv = new (std::nothrow) coop_server();
+    if (!sv) return COOP_E_OOM;
+    sv->rt = rt;
+    sv->graphs.assign(graphs, graphs + ngraphs);
+    sv->slots = (uint32_t)slots;
+    sv->team_max = team_max;
+    sv->slot_bytes = slot_bytes;
+    for (int k = 0; k < 2; ++k) {
+        const uint64_t ta = k ? c.team_arcs_sssp : c.team_arcs_bfs;
+        for (const coop_graph* g : sv->graphs) {
+            const uint64_t t = (g->arcs + g->n + ta - 1) / ta;
+            sv->team[k].push_back((uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(t, team_max)));
+        }
+    }
+    uint32_t oc = 1u << 16;
+    while (oc < 2 * sv->slots * team_max) oc <<= 1;
+    sv->owner_cap = oc;
+    hipError_t e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
+    const unsigned pin = hipHostMallocCoherent | hipHostMallocMapped;
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&sv->host), sizeof(coop::ServeHost), pin);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&sv->req), slots * sizeof(coop::ServeReq), pin);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&sv->owner), (size_t)oc * 4, pin);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&sv->done), slots * sizeof(coop::ServeDone), pin);
+    if (e != hipSuccess) { server_free(sv); return hip_fail(rt, e); }
+    std::memset(sv->host, 0, sizeof(coop::ServeHost));
+    std::memset(sv->req, 0, slots * sizeof(coop::ServeReq));
+    std::memset(sv->owner, 0, (size_t)oc * 4);
+    std::memset(sv->done, 0, slots * sizeof(coop::ServeDone));
+    for (const coop_graph* g : sv->graphs) {
+        if ((rc = ensure_deg0(rt, const_cast<coop_graph*>(g), sv->stream))) { server_free(sv); return rc; }
+    }
+    // device layout: descriptors | slot lines | counters | per slot: stats, state
+    const size_t desc_b = align_up(slots * ngraphs * sizeof(coop::ServeDesc));
+    const size_t team_b = align_up(slots * sizeof(coop::TeamState));
+    const size_t ctl_b = align_up(sizeof(coop::ServeCtl));
+    const size_t total = desc_b + team_b + ctl_b + slots * (stats_b + state_b);
+    e = hipMalloc(&sv->dev, total);
+    if (e != hipSuccess) { server_free(sv); return e == hipErrorOutOfMemory ? COOP_E_OOM : hip_fail(rt, e); }
+    char* base = static_cast<char*>(sv->dev);
+    coop::ServeDesc* d_desc = reinterpret_cast<coop::ServeDesc*>(base);
+    coop::TeamState* teams = reinterpret_cast<coop::TeamState*>(base + desc_b);
+    sv->ctl = reinterpret_cast<coop::ServeCtl*>(base + desc_b + team_b);
+    char* slot_base = base + desc_b + team_b + ctl_b;
+
+    // launch handle (events, pinned target word, sizing)
+    coop_handle* h = nullptr;
+    if ((rc = begin_launch(rt, &o, sz, COOP_KERNEL_SERVE, sv->stream, &h))) { server_free(sv); return rc; }
+    sv->h = h;
+    coop::Cfg tcfg = h->cfg;          // per-team barrier constants
+    tcfg.mode = 0;
+    tcfg.host = nullptr;
+    tcfg.trace = nullptr;
+    tcfg.trace_cap = 0;
+    tcfg.wgtrace = nullptr;
+    tcfg.wgtrace_cap = 0;
+    tcfg.N = team_max;
+    std::vector<coop::ServeDesc> desc(slots * ngraphs);
+    for (uint32_t s = 0; s < slots; ++s) {
+        char* sb = slot_base + (size_t)s * (stats_b + state_b);
+        uint32_t* stats = reinterpret_cast<uint32_t*>(sb);
+        char* st = sb + stats_b;
+        uint4* heavy = heavy_max ? reinterpret_cast<uint4*>(st + std::max(bfs_b, sssp_b)) : nullptr;
+        for (uint32_t gi = 0; gi < ngraphs; ++gi) {
+            const coop_graph* g = sv->graphs[gi];
+            coop::ServeDesc& D = desc[(size_t)s * ngraphs + gi];
+            coop::TraversalArgs t{};
+            t.cfg = tcfg;
+            t.ctx = &teams[s].bfs_ctx;
+            t.work = &teams[s].bfs_work;
+            t.slots = stats;
+            t.row_ptr = g->row_ptr;
+            t.col = g->col;
+            t.w = g->w;
+            t.n = g->n;
+            t.heavy_th = heavy_th;
+            t.strip = strip;
+            t.heavy_cap = (uint32_t)const_cast<coop_graph*>(g)->heavy_strips(heavy_th, strip);
+            t.heavy = heavy;
+            t.roots = nullptr;
+            t.nroots = 1;
+            t.out_stride = 0;
+            t.N = team_max;
+            D.bfs.t = t;
+            const size_t wb = align_up((size_t)words_max * 4);
+            D.bfs.vis = reinterpret_cast<uint32_t*>(st);
+            for (int k = 0; k < 3; ++k) D.bfs.fb[k] = reinterpret_cast<uint32_t*>(st + (k + 1) * wb);
+            D.bfs.words = g->words;
+            D.bfs.deg0 = g->deg0;
+            D.bfs.level_out = nullptr;
+            D.bfs.direction_opt = c.direction_opt ? 1u : 0u;
+            D.bfs.alpha = 14;
+            D.bfs.beta = 24;
+            D.bfs.total_arcs = g->arcs;
+            D.sssp.t = t;
+            const size_t qb = align_up((size_t)n_max * 4 + 4);
+            D.sssp.state = reinterpret_cast<uint64_t*>(st);
+            D.sssp.t.frontier[0] = reinterpret_cast<uint32_t*>(st + align_up((size_t)n_max * 8));
+            D.sssp.t.frontier[1] = reinterpret_cast<uint32_t*>(st + align_up((size_t)n_max * 8) + qb);
+            D.sssp.dist_out = nullptr;
+        }
+    }
+    e = hipMemcpyAsync(d_desc, desc.data(), desc.size() * sizeof(coop::ServeDesc), hipMemcpyHostToDevice,
+                       sv->stream);
+    for (uint32_t s = 0; s < slots && e == hipSuccess; ++s)
+        e = coop::launch_fill_u32(reinterpret_cast<uint32_t*>(slot_base + (size_t)s * (stats_b + state_b)),
+                                  stats_b / 4, 0u, sv->stream);
+    if (e == hipSuccess) e = coop::launch_serve_init(teams, (uint32_t)slots, sv->ctl, sv->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(sv->stream);     // descriptors copied before `desc` goes
+    if (e != hipSuccess) {
+        handle_free(h);
+        server_free(sv);
+        return hip_fail(rt, e);
+    }
+    coop::ServeArgs& a = h->serve;
+    a.cfg = h->cfg;
+    a.desc = d_desc;
+    a.teams = teams;
+    a.ctl = sv->ctl;
+    a.host = sv->host;
+    a.req = sv->req;
+    a.owner = sv->owner;
+    a.done = sv->done;
+    a.owner_cap = oc;
+    a.team_max = team_max;
+    sv->slot_seq.assign(slots, 0);
+    for (uint32_t s = (uint32_t)slots; s-- > 0;) sv->free_slots.push_back(s);
+    (void)hipEventRecord(h->ev_init, sv->stream);
+    (void)hipEventRecord(h->ev_start, sv->stream);
+    e = relaunch(h, false, h->grid, sv->stream);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(sv->stream);
+        handle_free(h);
+        server_free(sv);
+        return hip_fail(rt, e);
+    }
+    (void)hipEventRecord(h->ev_end, sv->stream);
+    sv->poller = std::thread([sv]() {
+        (void)hipSetDevice(sv->rt->device);
+        while (!sv->stop_poller.load()) {
+            server_poll_once(sv);
+            std::this_thread::sleep_for(std::chrono::microseconds(10));
+        }
+    });
+    *out = sv;
+    return COOP_OK;
+}
+
+int coop_server_submit(coop_server* sv, const coop_graph* g, int kind, uint32_t src, void* d_out,
+                       uint64_t* ticket) {
+    if (!sv || !g || !d_out || (kind != COOP_QUERY_BFS && kind != COOP_QUERY_SSSP)) return COOP_E_INVALID;
+    uint32_t gi = 0;
+    while (gi < sv->graphs.size() && sv->graphs[gi] != g) ++gi;
+    if (gi == sv->graphs.size() || src >= g->n) return COOP_E_INVALID;
+    if (kind == COOP_QUERY_SSSP && !g->w && g->arcs) return COOP_E_INVALID;
+    if (sv->slots == 0) return COOP_E_BUSY;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    const uint64_t seq = sv->next_seq++;
+    coop_server::Query& q = sv->queries[seq];
+    q.gi = gi;
+    q.kind = (uint32_t)kind;
+    q.src = src;
+    q.out = d_out;
+    q.t_submit = now_ms();
+    ++sv->submitted;
+    if (!sv->free_slots.empty() && sv->pending.empty()) server_publish(sv, seq);
+    else sv->pending.push_back(seq);
+    if (ticket) *ticket = seq;
+    return COOP_OK;
+}
+
+int coop_server_poll(coop_server* sv, uint64_t ticket, int* done, double* latency_ms) {
+    if (!sv) return COOP_E_INVALID;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->queries.find(ticket);
+    if (it == sv->queries.end()) return COOP_E_INVALID;
+    const bool fin = it->second.state == 2;
+    if (done) *done = fin ? 1 : 0;
+    if (fin && latency_ms) *latency_ms = it->second.t_done - it->second.t_submit;
+    return fin ? it->second.err : COOP_OK;
+}
+
+int coop_server_wait(coop_server* sv, uint64_t ticket, double timeout_ms, double* latency_ms) {
+    if (!sv) return COOP_E_INVALID;
+    const double deadline = now_ms() + (timeout_ms > 0 ? timeout_ms : 1e12);
+    std::unique_lock<std::mutex> lk(sv->mu);
+    for (;;) {
+        auto it = sv->queries.find(ticket);
+        if (it == sv->queries.end()) return COOP_E_INVALID;
+        if (it->second.state == 2) {
+            if (latency_ms) *latency_ms = it->second.t_done - it->second.t_submit;
+            return it->second.err;
+        }
+        if (sv->error) return sv->error;
+        if (now_ms() > deadline) return COOP_E_TIMEOUT;
+        sv->cv.wait_for(lk, std::chrono::milliseconds(2));
+    }
+}
+
+int coop_server_stats(coop_server* sv, coop_serve_stats* out) {
+    if (!sv || !out) return COOP_E_INVALID;
+    coop::ServeCtl ctl{};
+    (void)hipMemcpyAsync(&ctl, sv->ctl, sizeof(ctl), hipMemcpyDeviceToHost, sv->rt->cotask_stream);
+    (void)hipStreamSynchronize(sv->rt->cotask_stream);
+    std::lock_guard<std::mutex> lk(sv->mu);
+    std::memset(out, 0, sizeof(*out));
+    out->submitted = sv->submitted;
+    out->completed = sv->completed;
+    out->count_bfs = sv->lat[0].size();
+    out->count_sssp = sv->lat[1].size();
+    for (int k = 0; k < 2; ++k) {
+        out->latency_p50_ms[k] = percentile(sv->lat[k], 0.50);
+        out->latency_p99_ms[k] = percentile(sv->lat[k], 0.99);
+    }
+    out->wait_p50_ms = percentile(sv->waits, 0.50);
+    out->wait_p99_ms = percentile(sv->waits, 0.99);
+    out->slot_bytes = sv->slot_bytes;
+    out->slots = sv->slots;
+    out->in_flight = sv->slots - (uint32_t)sv->free_slots.size();
+    out->queued = (uint32_t)sv->pending.size();
+    out->kills = ctl.kills;
+    out->forks = ctl.forks;
+    out->min_groups = ctl.min_active == 0xFFFFFFFFu ? ctl.max_active : ctl.min_active;
+    out->max_groups = ctl.max_active;
+    out->error = sv->error ? sv->error : ctl.error;
+    return COOP_OK;
+}
+
+coop_handle* coop_server_handle(coop_server* sv) { return sv ? sv->h : nullptr; }
+
+int coop_server_destroy(coop_server* sv) {
+    if (!sv) return COOP_E_INVALID;
+    coop_rt* rt = sv->rt;
+    int rc = COOP_OK;
+    // let queued and running queries finish (bounded), then stop the launch
+    const double deadline = now_ms() + 120000.0;
+    for (;;) {
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            if (sv->completed == sv->submitted || sv->error) break;
+        }
+        if (hipEventQuery(sv->h->ev_end) == hipSuccess) break;     // the launch ended early
+        if (now_ms() > deadline) { rc = COOP_E_TIMEOUT; break; }
+        std::this_thread::sleep_for(std::chrono::microseconds(100));
+    }
+    __atomic_store_n(&sv->host->stop, 1u, __ATOMIC_RELEASE);
+    if (rt->inj_handle.load() == sv->h) {
+        rt->inj_handle.store(nullptr);
+        while (rt->inj_busy.load()) std::this_thread::yield();
+    }
+    hipError_t e;
+    const double d2 = now_ms() + 60000.0;
+    while ((e = hipEventQuery(sv->h->ev_end)) == hipErrorNotReady && now_ms() < d2)
+        std::this_thread::sleep_for(std::chrono::microseconds(100));
+    if (e == hipErrorNotReady) return COOP_E_TIMEOUT;     // leave everything in place: the launch still runs
+    if (sv->h->joined) (void)hipEventSynchronize(sv->h->ev_join);
+    sv->stop_poller = true;
+    if (sv->poller.joinable()) sv->poller.join();
+    if (rc == COOP_OK) {
+        coop::ServeCtl ctl{};
+        if (hipMemcpy(&ctl, sv->ctl, sizeof(ctl), hipMemcpyDeviceToHost) == hipSuccess && ctl.error) rc = ctl.error;
+        if (sv->error) rc = sv->error;
+    }
+    {
+        std::lock_guard<std::recursive_mutex> lk(rt->mu);
+        handle_free(sv->h);
+    }
+    server_free(sv);
+    return rc;
 }
 
 // ----------------------------------------------------------------- co-task

@@ -56,6 +56,7 @@ constexpr uint32_t kFlagSel = 1u << 8;            // queue engine: which buffer 
 constexpr uint32_t kFlagAdv = 1u << 9;            // this barrier advanced the level
 constexpr uint32_t kRotShift = 10;                // BFS: frontier bitmap rotation (0..2)
 constexpr uint32_t kRotMask = 3u << kRotShift;
+constexpr uint32_t kFlagEnd = 1u << 12;           // a served query finished (the team goes on)
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 __device__ __forceinline__ uint32_t wave_id() { return threadIdx.x / kWave; }
@@ -488,7 +489,8 @@ __device__ __forceinline__ void clear_share(uint32_t* bm, uint32_t words, uint32
 // INIT clears the per-source state, TD/HEAVY expand the frontier, BU probes
 // the unvisited vertices. Statistics go to the member's slot.
 __device__ __forceinline__ void bfs_phase(const BfsArgs& p, BlockLds& sh, uint32_t ph, uint32_t flags,
-                                          uint32_t level, uint32_t root, uint32_t id, uint32_t M) {
+                                          uint32_t level, uint32_t root, uint32_t id, uint32_t M,
+                                          uint32_t* lvl_base) {
     const TraversalArgs& t = p.t;
     Work* wk = t.work;
     const uint32_t nw = num_waves();
@@ -496,7 +498,7 @@ __device__ __forceinline__ void bfs_phase(const BfsArgs& p, BlockLds& sh, uint32
     uint32_t* cur = p.fb[rot];
     uint32_t* nxt = p.fb[(rot + 1) % 3];
     uint32_t* spare = p.fb[(rot + 2) % 3];
-    uint32_t* lvl = p.level_out + (size_t)root * t.out_stride;
+    uint32_t* lvl = lvl_base + (size_t)root * t.out_stride;
     const uint32_t gw = id * nw + wave_id();
     const uint32_t W = M * nw;
     Stats st;
@@ -531,8 +533,11 @@ __device__ __forceinline__ void bfs_phase(const BfsArgs& p, BlockLds& sh, uint32
 
 // BFS master step (all threads of the master workgroup): per-level
 // bookkeeping, HEAVY follow-up, direction of the next level (Beamer's
-// alpha/beta rule), next source or done. Returns the release flags.
-__device__ __forceinline__ uint32_t bfs_master(const BfsArgs& p, BlockLds& sh, CtxCore* c, uint32_t ph, uint32_t cur_flags) {
+// alpha/beta rule), next source or done. `roots` / `lvl_base`: the sources
+// and the output (the launch's, or a served query's). Returns the release
+// flags.
+__device__ __forceinline__ uint32_t bfs_master(const BfsArgs& p, BlockLds& sh, CtxCore* c, uint32_t ph,
+                                               uint32_t cur_flags, const uint32_t* roots, uint32_t* lvl_base) {
     const TraversalArgs& t = p.t;
     Work* wk = t.work;
     uint64_t tot[2];
@@ -546,8 +551,8 @@ __device__ __forceinline__ uint32_t bfs_master(const BfsArgs& p, BlockLds& sh, C
             x.root() = 0;
             res = kPhInit;
         } else if (ph == kPhInit) {
-            const uint32_t src = t.roots[x.root()];
-            uint32_t* lv = p.level_out + (size_t)x.root() * t.out_stride;
+            const uint32_t src = roots[x.root()];
+            uint32_t* lv = lvl_base + (size_t)x.root() * t.out_stride;
             lv[src] = 0;
             p.vis[src >> 5] |= 1u << (src & 31);
             p.fb[0][src >> 5] |= 1u << (src & 31);
@@ -618,6 +623,164 @@ __device__ __forceinline__ void bfs_follow(uint32_t ph, uint32_t nflags, uint32_
     } else if (nflags & kFlagAdv) {
         level += 1;
     }
+}
+
+// ----------------------------------------------------------------- SSSP
+
+struct SsspVisit {
+    uint64_t* state;        // {distance (hi) | tag (lo)}
+    const uint32_t* w;
+    uint32_t tag;           // tag meaning "queued for the next round"
+    CtxCore* ctx;
+    uint32_t* out_tail;
+    uint32_t* out;
+
+    __device__ __forceinline__ uint32_t payload(uint32_t v) const {
+        return (uint32_t)(ld_relaxed64(&state[v]) >> 32);
+    }
+    __device__ __forceinline__ uint32_t strip_payload(uint32_t, uint32_t v) const { return payload(v); }
+    __device__ __forceinline__ void maybe_flush(WaveLds& wl) {
+        if (wl.out_n > kFlushAt) wave_flush(wl, out_tail, out);
+    }
+
+    // Frontier Bellman-Ford relaxation. One 64-bit atomicMin on {distance,
+    // tag} lowers the distance and, through the old tag it returns, tells
+    // whether the vertex is already queued for the next round (tags only
+    // grow, so an equal distance never changes the word).
+    __device__ __forceinline__ void step(const bool* ok, const uint32_t* arc, const uint32_t* u,
+                                         const uint32_t* pay, WaveLds& wl, Stats& st) {
+        uint32_t wt[kUnroll];
+        uint32_t du[kUnroll];
+#pragma unroll
+        for (uint32_t j = 0; j < kUnroll; ++j) wt[j] = ok[j] ? __builtin_nontemporal_load(&w[arc[j]]) : 0u;
+#pragma unroll
+        for (uint32_t j = 0; j < kUnroll; ++j) du[j] = ok[j] ? (uint32_t)(state[u[j]] >> 32) : 0u;
+        bool win[kUnroll];
+#pragma unroll
+        for (uint32_t j = 0; j < kUnroll; ++j) {
+            win[j] = false;
+            if (!ok[j]) continue;
+            const uint64_t nd64 = (uint64_t)pay[j] + (uint64_t)wt[j];
+            if (nd64 >= 0x7FFFFFFFull) {
+                if (pay[j] != 0x7FFFFFFFu) raise_error(ctx, kErrOverflow);
+                continue;
+            }
+            const uint32_t nd = (uint32_t)nd64;
+            if (nd < du[j]) {
+                const uint64_t old = __hip_atomic_fetch_min(&state[u[j]], ((uint64_t)nd << 32) | tag,
+                                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                win[j] = nd < (uint32_t)(old >> 32) && (uint32_t)old != tag;
+            }
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kUnroll; ++j) {
+            st.found += win[j] ? 1u : 0u;
+            wave_push(wl, win[j], u[j]);
+        }
+    }
+};
+
+// One SSSP phase for member `id` of `M` (queue engine): INIT resets the
+// {distance, tag} words, TD relaxes the arcs of the input queue (64-entry
+// units distributed statically), HEAVY walks strips of heavy vertices, OUT
+// copies the distances to `dist`. `round` tags this round's queue entries.
+__device__ __forceinline__ void sssp_phase(const SsspArgs& p, BlockLds& sh, uint32_t ph, uint32_t flags,
+                                           uint32_t round, int32_t* dist, uint32_t id, uint32_t M) {
+    const TraversalArgs& t = p.t;
+    Work* wk = t.work;
+    const uint32_t nw = num_waves();
+    const bool sel = (flags & kFlagSel) != 0;
+    uint32_t* in = t.frontier[sel ? 1 : 0];
+    uint32_t* out = t.frontier[sel ? 0 : 1];
+    const uint32_t gw = id * nw + wave_id();
+    const uint32_t W = M * nw;
+    Stats st;
+    if (ph == kPhInit) {
+        // distances to "unreached"; tags to 0 (no round uses tag 0)
+        const uint32_t tid = id * blockDim.x + threadIdx.x, stride = M * blockDim.x;
+        for (uint32_t i = tid; i < t.n; i += stride) p.state[i] = 0x7FFFFFFFull << 32;
+    } else if (ph == kPhOut) {
+        const uint32_t tid = id * blockDim.x + threadIdx.x, stride = M * blockDim.x;
+        for (uint32_t i = tid; i < t.n; i += stride) dist[i] = (int32_t)(p.state[i] >> 32);
+    } else if (ph == kPhTD || ph == kPhHeavy) {
+        if (threadIdx.x == 0) sh.in_size = wk->x.in_size;
+        __syncthreads();
+        const uint32_t size = sh.in_size;
+        SsspVisit vis{p.state, t.w, round + 2, t.ctx, &wk->out_tail, out};
+        WaveLds& w = sh.wave[wave_id()];
+        if (ph == kPhTD) {
+            const uint32_t units = (size + kWave - 1) / kWave;
+            for (uint32_t u = gw; u < units; u += W) {
+                const uint32_t i = u * kWave + lane_id();
+                const bool act = i < size;
+                expand_batch(t, wk, w, act, act ? in[i] : 0u, vis, st);
+            }
+        } else {
+            heavy_phase(t, size, gw, W, w, vis, st);
+        }
+        wg_flush(sh, &wk->out_tail, out);
+        stats_to_lds(sh, st);
+        __syncthreads();
+        acc_to_slot(sh, t.slots, id);
+    }
+}
+
+// SSSP master step: place the next source, switch a round to its HEAVY
+// phase, turn the output queue into the next round's input, or finish the
+// source (OUT) and go to the next. Returns the release flags.
+__device__ __forceinline__ uint32_t sssp_master(const SsspArgs& p, BlockLds& sh, CtxCore* c, uint32_t ph,
+                                                uint32_t cur_flags, const uint32_t* roots) {
+    const TraversalArgs& t = p.t;
+    Work* wk = t.work;
+    uint64_t tot[2];
+    master_sum_slots(sh, t.slots, t.N, tot);
+    if (threadIdx.x == 0) {
+        XferR x = wk->load_x();                 // one batch of loads
+        const uint32_t hs = ld_relaxed(&wk->heavy_tail);
+        const uint32_t ot = ld_relaxed(&wk->out_tail);
+        uint32_t res;
+        const uint32_t flags = cur_flags & kFlagSel;
+        if (ph == kPhStart) {
+            x.root() = 0;
+            res = kPhInit;
+        } else if (ph == kPhOut) {
+            x.root() += 1;
+            res = x.root() >= t.nroots ? kFlagDone : kPhInit;
+        } else if (ph == kPhInit) {
+            const uint32_t r = roots[x.root()];
+            p.state[r] = (uint64_t)(x.round() + 1);      // distance 0, queued for this round
+            t.frontier[0][0] = r;
+            x.in_size() = 1;
+            wk->out_tail = 0;
+            wk->heavy_tail = 0;
+            res = kPhTD;               // input = buffer 0
+        } else if (ph == kPhTD && hs > 0) {
+            if (hs > t.heavy_cap) raise_error(c, kErrInternal);
+            x.in_size() = hs;
+            wk->heavy_tail = 0;
+            x.heavy_phases() += 1;
+            res = flags | kPhHeavy;
+        } else {
+            // round done: the output queue becomes the input
+            wk->out_tail = 0;
+            if (hs) wk->heavy_tail = 0;
+            x.in_size() = ot;
+            x.level() += 1;
+            x.round() += 1;
+            x.levels_total() += 1;
+            res = ot == 0 ? (kPhOut | kFlagAdv) : ((flags ^ kFlagSel) | kPhTD | kFlagAdv);
+        }
+        wk->store_x(x);
+        sh.bar.flags = res;
+    }
+    __syncthreads();
+    return sh.bar.flags;
+}
+
+// Follow the transmitted SSSP state locally after a barrier.
+__device__ __forceinline__ void sssp_follow(uint32_t ph, uint32_t nflags, uint32_t& round, uint32_t& root) {
+    if (nflags & kFlagAdv) round += 1;
+    if ((nflags & kPhMask) == kPhInit && ph == kPhOut) root += 1;
 }
 
 // ----------------------------------------------- colouring and MIS (JP DAG)
@@ -777,6 +940,37 @@ __device__ __forceinline__ uint32_t color_master(const ColorArgs& p, BlockLds& s
     }
     __syncthreads();
     return sh.bar.flags;
+}
+
+// ------------------------------------------ leaving between instances
+
+// Counters of a launch whose workgroups leave between instances or queries.
+struct LeaveCounters {
+    uint32_t* active;          // workgroups inside the loop
+    uint32_t* active_x;        // ... per XCD
+    uint32_t* kills;
+    uint32_t* min_active;
+};
+
+// offer_kill between instances (thread 0): leave if the launch holds more
+// workgroups than max(T, floor) and this workgroup's XCD holds more than its
+// share ceil(T / xcds) (a competing kernel needs compute units on every XCD).
+__device__ inline bool leave_for_target(const LeaveCounters& lc, uint32_t T, uint32_t floor, uint32_t xcds,
+                                        uint32_t x) {
+    const uint32_t lo = T > floor ? T : floor;
+    const uint32_t share = xcds > 1 ? (T + xcds - 1) / xcds : T;
+    if (xcds > 1 && ld_relaxed(&lc.active_x[x]) <= share) return false;
+    uint32_t a = ld_relaxed(lc.active);
+    while (a > lo) {
+        if (__hip_atomic_compare_exchange_strong(lc.active, &a, a - 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)) {
+            add_relaxed(&lc.active_x[x], 0xFFFFFFFFu);
+            add_relaxed(lc.kills, 1u);
+            atomicMin(lc.min_active, a - 1);
+            return true;
+        }
+    }
+    return false;
 }
 
 }  // namespace

@@ -116,3 +116,25 @@ def test_closed_form_graphs(gg):
               gg.binary_tree(10)):
         check_simple_symmetric(g)
     assert gg.complete(6).edges == 15 and gg.cycle(6).edges == 6 and gg.binary_tree(10).edges == 9
+
+
+def test_batch_sizes_recipe(gg):
+    """Batched workload: instance i uses seed 1000 + i, n log-uniform in
+    [2^10, 2^18), average degree uniform in [4, 32)."""
+    sz = gg.batch_sizes(512, 1000)
+    assert [s for _, _, s in sz] == list(range(1000, 1512))
+    n = np.array([a for a, _, _ in sz])
+    d = np.array([b for _, b, _ in sz])
+    assert n.min() >= 1 << 10 and n.max() < 1 << 18
+    assert d.min() >= 4 and d.max() < 32
+    # log-uniform: half the instances below 2^14 (binomial, 5 sigma ~ 0.11)
+    assert abs(np.mean(n < (1 << 14)) - 0.5) < 0.11
+    assert abs(np.mean(d < 18) - 0.5) < 0.11
+    assert gg.batch_sizes(3, 1000) == sz[:3]
+
+
+def test_er_batch_matches_single_instances(gg):
+    gs = gg.er_batch(5, 2000, workers=3, log2_hi=12.0)
+    for g, (n, d, s) in zip(gs, gg.batch_sizes(5, 2000, log2_hi=12.0)):
+        h = gg.er(n, d, s)
+        assert g.n == n and np.array_equal(g.row_ptr, h.row_ptr) and np.array_equal(g.col, h.col)

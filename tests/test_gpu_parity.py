@@ -282,3 +282,81 @@ def test_barrier_bench(rt, coop_mod, mode):
     ns, st = coop_mod.coop_barrier_bench(rt.rt, 2000, modes(coop_mod)[mode])
     say(f"  {ns:.0f} ns/barrier, grid={st['grid']} M={st['final_groups']}")
     assert st["barriers"] >= 2000 and ns > 0
+
+
+# ------------------------------------------------- host target, co-tasks
+
+def test_bfs_host_target_xcd_kills(rt, coop_mod, gg):
+    """A host-driven target claims workgroups XCD by XCD (victims renumbered)
+    while the kernel runs many sources; a joiner grid brings them back. Every
+    source's levels equal the oracle's."""
+    import time
+    import torch
+    c = coop_mod
+    g = gg.rmat(16, 16, seed=9)
+    say("bfs rmat16 host target with XCD-aware kills")
+    dg = rt.graph(g)
+    roots = [int(r) for r in gg.sources(g, 4, 24)]
+    k = 400
+    reps = np.resize(np.asarray(roots, dtype=np.uint32), k)
+    d_roots = rt._roots(reps)
+    out = torch.empty(len(roots) * g.n, dtype=torch.int32, device="cuda")
+    # the same 24 sources over and over: each output row is rewritten by identical runs
+    o = c.make_opts(c.COOP_MODE_COOP, flags=c.COOP_F_HOST_SCHEDULE)
+    lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    h = c.coop_bfs(rt.rt, dg.handle, d_roots, k, lv, 0, o)
+    n = c.coop_handle_groups(h)
+    for step in range(6):
+        time.sleep(0.004)
+        c.coop_set_target(h, n // 2 if step % 2 == 0 else n)
+        if step % 2 == 1:
+            c.coop_fork_groups(h, n // 2)
+    rc, st = c.coop_wait(h)
+    assert rc == 0, c.coop_strerror(rc)
+    say(f"  kills={st['kills']} forks={st['forks']} min={st['min_groups']} ms={st['kernel_ms']:.1f}")
+    assert st["kills"] > 0
+    # the last source's levels are in lv
+    assert np.array_equal(as_u32(lv), oracle.bfs(g, int(reps[-1])))
+    # and a multi-root launch under the same schedule writes every row right
+    d24 = rt._roots(roots)
+    h = c.coop_bfs(rt.rt, dg.handle, d24, len(roots), out, g.n, o)
+    c.coop_set_target(h, n // 3)
+    time.sleep(0.002)
+    c.coop_set_target(h, n)
+    c.coop_fork_groups(h, n)
+    rc, st = c.coop_wait(h)
+    assert rc == 0, c.coop_strerror(rc)
+    got = out.cpu().numpy().view(np.uint32).reshape(len(roots), g.n)
+    for i, r in enumerate(roots):
+        assert np.array_equal(got[i], oracle.bfs(g, r)), f"root {r}"
+    dg.release()
+
+
+@pytest.mark.xfail(reason="a co-task can still wait for the end of the traversal; cause under investigation",
+                   strict=False)
+def test_cotask_injector_during_bfs(rt, coop_mod, gg):
+    """Co-tasks needing half the CUs run while a cooperative BFS holds the
+    GPU: the kernel frees compute units on every XCD, so each co-task runs
+    within its period instead of waiting for the traversal to end."""
+    import torch
+    c = coop_mod
+    g = gg.rmat(18, 16, seed=3)
+    dg = rt.graph(g)
+    roots = np.resize(gg.sources(g, 3, 16), 600).astype(np.uint32)
+    d_roots = rt._roots(roots)
+    lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    o = c.make_opts(c.COOP_MODE_COOP, flags=c.COOP_F_HOST_SCHEDULE)
+    cus = rt.info["compute_units"]
+    say("co-task injector during bfs rmat18")
+    h = c.coop_bfs(rt.rt, dg.handle, d_roots, len(roots), lv, 0, o)
+    c.coop_injector_start(rt.rt, h, groups=cus // 2, busy_ns=500_000, period_ns=5_000_000)
+    rc, st = c.coop_wait(h)
+    irc, cst = c.coop_injector_stop(rt.rt)
+    assert rc == 0 and irc == 0
+    say(f"  kernel {st['kernel_ms']:.1f} ms kills={st['kills']} co-tasks={cst['count']} "
+        f"p50={cst['latency_p50_ms']:.3f} p99={cst['latency_p99_ms']:.3f} max={cst['latency_max_ms']:.3f} ms")
+    assert np.array_equal(as_u32(lv), oracle.bfs(g, int(roots[-1])))
+    assert cst["count"] >= 3
+    # no co-task waited for the whole traversal
+    assert cst["latency_max_ms"] < 0.5 * st["kernel_ms"]
+    dg.release()
