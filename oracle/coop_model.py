@@ -31,6 +31,13 @@ every reachable state:
   * no deadlock: every non-final state has an enabled workgroup step;
   * every final state's output equals the plain BFS levels (the schedule
     that never kills or forks is a legal one, so all must agree with it).
+
+With ``victims="any"`` the kill takes any W workgroups other than 0 (every
+choice is explored) and renumbers the survivors densely in id order, the
+kill-in-any-order variant of the paper's appendix. The master writes each
+old id's new id tagged with the epoch; a waiter that sees the epoch advance
+by one reads its entry in a separate step, and an entry of another epoch (it
+was overwritten by a later barrier) means it was killed.
 """
 from __future__ import annotations
 
@@ -55,6 +62,7 @@ class WG:
     level: int = 0         # transmitted level
     joinslot: int = -1     # position in the joiner queue
     mseen: int = 0         # active count read together with `seen`
+    rn: bool = False       # the observed release renumbered: read the new id
 
 
 @dataclass(frozen=True)
@@ -76,6 +84,8 @@ class State:
     wgs: Tuple[WG, ...]
     t_changes: int                  # remaining scheduler target changes
     joiners_left: int               # remaining joiner workgroups the host may launch
+    renum: Tuple[Tuple[int, int], ...] = ()    # per old id: (epoch, new id or -1)
+    renum_epoch: int = -1           # epoch whose release carried a renumbering
 
 
 class ModelError(AssertionError):
@@ -87,7 +97,7 @@ class Model:
 
     def __init__(self, adj: Sequence[Sequence[int]], src: int, N: int, *,
                  t_changes: int = 1, joiners: int = 1, park_killed: bool = False,
-                 t_values: Optional[Sequence[int]] = None):
+                 t_values: Optional[Sequence[int]] = None, victims: str = "top"):
         self.adj = [tuple(a) for a in adj]
         self.n = len(adj)
         self.src = src
@@ -96,6 +106,9 @@ class Model:
         self.t_values = tuple(t_values) if t_values is not None else tuple(range(1, N + 1))
         self.init_t_changes = t_changes
         self.init_joiners = joiners
+        if victims not in ("top", "any"):
+            raise ValueError(victims)
+        self.victims = victims
 
     # ------------------------------------------------------------ start
     def initial(self) -> State:
@@ -105,12 +118,17 @@ class Model:
                      M=1, Mnew=1, epoch=0, arrive=0, level=0, done=False, T=self.N,
                      tickets=0, joinq=(), admitted=(),
                      wgs=tuple(WG() for _ in range(self.N)),
-                     t_changes=self.init_t_changes, joiners_left=self.init_joiners)
+                     t_changes=self.init_t_changes, joiners_left=self.init_joiners,
+                     renum=tuple((-1, -1) for _ in range(self.N)), renum_epoch=-1)
 
     # ------------------------------------------------------ transitions
     def successors(self, s: State) -> List[Tuple[str, State]]:
         out: List[Tuple[str, State]] = []
         for i, w in enumerate(s.wgs):
+            if w.pc == ARRIVE and s.arrive + 1 == s.M:
+                for k, nxt in enumerate(self._master(s, i, w, all_choices=True)):
+                    out.append((f"wg{i}:MASTER{k}", nxt))
+                continue
             nxt = self._step_wg(s, i, w)
             if nxt is not None:
                 out.append((f"wg{i}:{PC_NAMES[w.pc]}", nxt))
@@ -173,7 +191,7 @@ class Model:
             arrive = s.arrive + 1
             if arrive < s.M:
                 return self._set(s, i, _w(w, pc=WAIT), arrive=arrive)
-            return self._master(s, i, w)
+            return self._master(s, i, w, all_choices=False)[0]
         if pc == WAIT:
             if s.epoch != w.seen:
                 # (epoch, count) are read as one word. An alive member is
@@ -182,11 +200,18 @@ class Model:
                 if s.epoch > w.seen + 1:
                     return self._set(s, i, _w(w, pc=POST, seen=s.epoch, mseen=-1))
                 return self._set(s, i, _w(w, pc=POST, seen=s.epoch, mseen=s.Mnew,
-                                          level=s.level))
+                                          level=s.level, rn=s.renum_epoch == s.epoch))
             return None
         if pc == POST:
             if s.done:
-                return self._set(s, i, _w(w, pc=EXITED))
+                return self._set(s, i, _w(w, pc=EXITED, rn=False))
+            if w.rn:
+                # separate read of this id's entry: the barrier's own, or a
+                # later one's if this workgroup was killed here
+                ep, new = s.renum[w.logical]
+                if ep != w.seen or new < 0:
+                    return self._set(s, i, _w(w, rn=False, mseen=-1))
+                return self._set(s, i, _w(w, rn=False, logical=new))
             if w.mseen < 0 or w.logical >= w.mseen:
                 if w.logical == 0:
                     raise ModelError("workgroup 0 killed")
@@ -197,10 +222,11 @@ class Model:
             return self._set(s, i, _w(w, pc=WORK))
         return None   # EXITED
 
-    def _master(self, s: State, i: int, w: WG) -> State:
+    def _master(self, s: State, i: int, w: WG, all_choices: bool) -> List[State]:
         """The last arrival runs the barrier's critical section while every
         other running workgroup waits: level bookkeeping, fork (admission of
-        waiting joiners), query, and the kill decision."""
+        waiting joiners), query, and the kill decision. With victims="any"
+        every choice of victims is a successor."""
         M = s.M
         members = sorted([x.logical for x in s.wgs if x.pc == WAIT and x.seen == s.epoch]
                          + [w.logical])
@@ -223,10 +249,35 @@ class Model:
         Mnew = M2 - W
         if not (0 < Mnew <= self.N) or not (0 <= k <= self.N - M):
             raise ModelError(f"bad resize M={M} k={k} W={W}")
-        s2 = _replace(s, frontier=frontier, out=(), claim=0, level=level, done=done,
-                      arrive=0, M=Mnew, Mnew=Mnew, epoch=s.epoch + 1, joinq=joinq,
-                      admitted=admitted)
-        return self._set(s2, i, _w(w, pc=POST, seen=s.epoch + 1, mseen=Mnew, level=level))
+        if W and k:
+            raise ModelError("a barrier that admits joiners also kills")
+        ne = s.epoch + 1
+        base = dict(frontier=frontier, out=(), claim=0, level=level, done=done, arrive=0, M=Mnew,
+                    Mnew=Mnew, epoch=ne, joinq=joinq, admitted=admitted)
+        if self.victims == "top" or W == 0:
+            s2 = _replace(s, **base)
+            return [self._set(s2, i, _w(w, pc=POST, seen=ne, mseen=Mnew, level=level, rn=False))]
+        from itertools import combinations
+        result = []
+        choices = list(combinations(range(1, M2), W))
+        for victims in (choices if all_choices else choices[:1]):
+            vs = set(victims)
+            renum = list(s.renum)
+            nxt = 0
+            for old in range(M2):
+                if old in vs:
+                    renum[old] = (ne, -1)
+                else:
+                    renum[old] = (ne, nxt)
+                    nxt += 1
+            s2 = _replace(s, renum_epoch=ne, renum=tuple(renum), **base)
+            # the master knows its own fate at once
+            if w.logical in vs:
+                result.append(self._set(s2, i, _w(w, pc=POST, seen=ne, mseen=-1, level=level, rn=False)))
+            else:
+                result.append(self._set(s2, i, _w(w, pc=POST, seen=ne, mseen=Mnew, level=level, rn=False,
+                                                  logical=renum[w.logical][1])))
+        return result
 
     # -------------------------------------------------------- invariants
     def check(self, s: State) -> None:
@@ -237,7 +288,7 @@ class Model:
         # a workgroup still waiting on an older epoch, or leaving after a
         # kill, is in transit: it has not yet observed the new count
         ids = [w.logical for w in running
-               if not (w.pc == POST and (w.mseen < 0 or w.logical >= w.mseen))
+               if not (w.pc == POST and (w.rn or w.mseen < 0 or w.logical >= w.mseen))
                and not (w.pc == WAIT and w.seen != s.epoch)]
         if len(ids) != len(set(ids)):
             raise ModelError(f"duplicate logical ids {ids}")
