@@ -82,15 +82,21 @@ struct Cfg {
     uint32_t epoch0_wait;     // ticks ticket 0 waits for the grid to register
     uint32_t wgtrace_cap;     // barriers the per-workgroup trace holds
     uint64_t* wgtrace;        // optional: per barrier and logical id, 4 timestamps
-    uint32_t xcds;            // accelerator dies (XCDs) workgroups are dealt over
-    uint32_t slots_per_xcd;   // workgroups of this kernel one XCD holds at once
+    uint32_t engines;         // shader engines workgroups are dealt over (XCDs x engines per XCD)
+    uint32_t ses;             // shader engines per XCD
+    uint32_t slots_per_engine;  // workgroups of this kernel one shader engine holds at once
 };
 
-// The XCD (accelerator complex die) this workgroup runs on: hardware
-// register XCC_ID, bits 3:0.
-__device__ __forceinline__ uint32_t xcd_id() {
-    return __builtin_amdgcn_s_getreg((3u << 11) | (0u << 6) | 20u) & 0xFu;
+// The shader engine this workgroup runs on, numbered XCD-major: the XCD
+// from hardware register XCC_ID (bits 3:0) and the engine inside it from
+// HW_ID (bits 15:13). The hardware deals a kernel's workgroups round-robin
+// over the XCDs and, inside each XCD, over its shader engines.
+__device__ __forceinline__ uint32_t engine_id(uint32_t ses) {
+    const uint32_t xcc = __builtin_amdgcn_s_getreg((3u << 11) | (0u << 6) | 20u) & 0xFu;
+    const uint32_t se = (__builtin_amdgcn_s_getreg((31u << 11) | (0u << 6) | 4u) >> 13) & 7u;
+    return xcc * ses + se;
 }
+constexpr uint32_t kMaxEngines = 64;
 
 // Per-workgroup phase trace points (debugging and tuning only).
 enum WgTracePoint : uint32_t { kTrStart = 0, kTrWorkDone = 1, kTrArrive = 2, kTrReleased = 3 };
@@ -133,12 +139,12 @@ struct alignas(256) CtxCore {
 };
 
 // Context of a resizable launch: barrier lines, the joiner admission ring
-// (entries {slot:32 (lo) | epoch_lo:16 | id:16 (hi)}), the XCD of every
-// logical id, and the new ids of a barrier that chose its kill victims
+// (entries {slot:32 (lo) | epoch_lo:16 | id:16 (hi)}), the shader engine of
+// every logical id, and the new ids of a barrier that chose its kill victims
 // ({epoch_lo:16 (hi) | new id:16 (lo)}, new id 0xFFFF = killed).
 struct alignas(256) Ctx : CtxCore {
     uint64_t join_entry[kJoinCap];
-    uint32_t xcd_of[kMaxGroups];
+    uint32_t engine_of[kMaxGroups];
     uint32_t renum[kMaxGroups];
 };
 
@@ -209,9 +215,9 @@ struct BarrierLds {
     uint32_t kmax2;                    // kill count of the barrier
     uint32_t my_new;                   // XCD-aware kill: the master's new id
     uint32_t valid[kMaxGroups / 32];   // admission: ring slots whose joiner was still waiting
-    uint32_t xcnt[16];                 // XCD-aware kill: members per XCD, then victims per XCD
-    uint32_t wsum[kMaxWaves + 1];      // XCD-aware kill: survivors per wave of ids
-    uint8_t xcd[kMaxGroups];           // XCD-aware kill: XCD of every logical id
+    uint32_t xcnt[kMaxEngines];        // placed kill: members per engine, then victims per engine
+    uint32_t wsum[kMaxWaves + 1];      // placed kill: survivors per wave of ids
+    uint8_t xcd[kMaxGroups];           // placed kill: shader engine of every logical id
 };
 
 // Raise the abort flag so every spinning workgroup leaves.
@@ -283,7 +289,7 @@ __device__ inline Member join_queue(Ctx* c, const Cfg cfg) {
             m.epoch = rel_epoch(r);
             m.flags = rel_flags(r);
             m.alive = (m.flags & (kFlagAbort | kFlagDone)) ? 0u : 1u;
-            if (m.alive) st_relaxed(&c->xcd_of[m.id], xcd_id());
+            if (m.alive) st_relaxed(&c->engine_of[m.id], engine_id(cfg.ses));
             return m;
         }
         bool leave = (rel_flags(r) & (kFlagAbort | kFlagDone)) != 0;
@@ -322,7 +328,7 @@ __device__ inline Member register_member(Ctx* c, const Cfg cfg, bool plain, bool
             m.id = 0;
             m.M = 1;
             m.alive = 1;
-            st_relaxed(&c->xcd_of[0], xcd_id());
+            st_relaxed(&c->engine_of[0], engine_id(cfg.ses));
             return m;
         }
     }
@@ -428,26 +434,27 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
         b.kmax2 = W;
     }
     // A host-driven target asks for compute units for another kernel, whose
-    // workgroups the hardware deals round-robin over the XCDs: choose the
-    // victims so that every XCD frees its share (then renumber the rest).
+    // workgroups the hardware deals round-robin over the XCDs and their
+    // shader engines: choose the victims so that every engine frees its
+    // share (then renumber the rest densely).
     bool renum = false;
     uint32_t Mn_sel = 0, my_new = m.id;
     if constexpr (Coop) {
         __syncthreads();
         const uint32_t W = b.kmax2;
-        if (W && cfg.host && !(cfg.mode & kModeRandomSched) && cfg.xcds > 1) {
+        if (W && cfg.host && !(cfg.mode & kModeRandomSched) && cfg.engines > 1 && cfg.engines <= kMaxEngines) {
             renum = true;
             const uint32_t M2 = m.M + admitted;
-            for (uint32_t t = threadIdx.x; t < M2; t += blockDim.x) b.xcd[t] = (uint8_t)ld_relaxed(&c->xcd_of[t]);
-            if (threadIdx.x < 16) b.xcnt[threadIdx.x] = 0;
+            for (uint32_t t = threadIdx.x; t < M2; t += blockDim.x) b.xcd[t] = (uint8_t)ld_relaxed(&c->engine_of[t]);
+            if (threadIdx.x < kMaxEngines) b.xcnt[threadIdx.x] = 0;
             __syncthreads();
-            for (uint32_t t = threadIdx.x; t < M2; t += blockDim.x) atomicAdd(&b.xcnt[b.xcd[t] & 15u], 1u);
+            for (uint32_t t = threadIdx.x; t < M2; t += blockDim.x) atomicAdd(&b.xcnt[b.xcd[t] % kMaxEngines], 1u);
             __syncthreads();
             if (threadIdx.x == 0) {
-                const uint32_t need = (W + cfg.xcds - 1) / cfg.xcds;
-                for (uint32_t x = 0; x < 16; ++x) {
+                const uint32_t need = (W + cfg.engines - 1) / cfg.engines;
+                for (uint32_t x = 0; x < kMaxEngines; ++x) {
                     const uint32_t cnt = b.xcnt[x];
-                    const uint32_t idle = cfg.slots_per_xcd > cnt ? cfg.slots_per_xcd - cnt : 0u;
+                    const uint32_t idle = x < cfg.engines && cfg.slots_per_engine > cnt ? cfg.slots_per_engine - cnt : 0u;
                     uint32_t k = need > idle ? need - idle : 0u;
                     const uint32_t cap = cnt - (x == b.xcd[0] ? 1u : 0u);     // workgroup 0 stays
                     b.xcnt[x] = k < cap ? k : cap;
@@ -463,7 +470,7 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
                     const uint32_t x = b.xcd[t];
                     uint32_t above = 0;
                     for (uint32_t u = t + 1; u < M2; ++u) above += b.xcd[u] == x ? 1u : 0u;
-                    alive = t == 0 || above >= b.xcnt[x & 15u];
+                    alive = t == 0 || above >= b.xcnt[x % kMaxEngines];
                 }
                 const uint64_t bal = __ballot(alive);
                 if ((threadIdx.x & 63) == 0) b.wsum[threadIdx.x / 64] = (uint32_t)__popcll(bal);
@@ -475,7 +482,7 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
                 if (t < M2) {
                     __hip_atomic_store(&c->renum[t], ((ne & 0xFFFFu) << 16) | (alive ? nid : 0xFFFFu),
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (alive) st_relaxed(&c->xcd_of[nid], b.xcd[t]);
+                    if (alive) st_relaxed(&c->engine_of[nid], b.xcd[t]);
                 }
                 if (t == m.id) b.my_new = alive ? nid : 0xFFFFu;
                 for (uint32_t w = 0; w < blockDim.x / 64; ++w) carry += b.wsum[w];

@@ -78,7 +78,7 @@ __device__ bool batch_offer_kill(const BatchArgs& a, BatchCtl* ctl, uint32_t x) 
         if ((uint32_t)(h & 0xFFFFu) >= a.cfg.sched_p16) return false;
         return leave_for_target(lc, 0u, a.team_max, 1u, x);
     }
-    if (a.cfg.host) return leave_for_target(lc, ld_system(&a.cfg.host->target), a.team_max, a.cfg.xcds, x);
+    if (a.cfg.host) return leave_for_target(lc, ld_system(&a.cfg.host->target), a.team_max, a.cfg.engines, x);
     return false;
 }
 
@@ -94,14 +94,14 @@ __device__ void batch_body(const BatchArgs& a, bool joiner) {
         for (uint32_t i = 0; i < num_waves(); ++i) sh.wave[i].out_n = 0;
         for (int i = 0; i < 8; ++i) sh.acc[i] = 0;
         const uint32_t act = add_relaxed(&ctl->active, 1u) + 1;
-        add_relaxed(&ctl->active_x[xcd_id()], 1u);
+        add_relaxed(&ctl->active_x[engine_id(a.cfg.ses) % kMaxEngines], 1u);
         atomicMax(&ctl->max_active, act);
         if (joiner) add_relaxed(&ctl->forks, 1u);
     }
     for (;;) {
         if (threadIdx.x == 0) {
             uint32_t leave = ld_relaxed_i(&ctl->error) ? 1u : 0u;
-            if (!leave && batch_offer_kill<Coop>(a, ctl, xcd_id())) leave = 2;
+            if (!leave && batch_offer_kill<Coop>(a, ctl, engine_id(a.cfg.ses))) leave = 2;
             if (!leave) {
                 const uint32_t k = add_relaxed(&ctl->ticket, 1u);
                 if (k >= total) {
@@ -118,7 +118,7 @@ __device__ void batch_body(const BatchArgs& a, bool joiner) {
             }
             if (leave == 1 || leave == 3) {
                 add_relaxed(&ctl->active, 0xFFFFFFFFu);
-                add_relaxed(&ctl->active_x[xcd_id()], 0xFFFFFFFFu);
+                add_relaxed(&ctl->active_x[engine_id(a.cfg.ses) % kMaxEngines], 0xFFFFFFFFu);
                 add_relaxed(&ctl->left, 1u);
             }
             sh.level = leave;

@@ -88,7 +88,7 @@ enum SlotField : uint32_t {
     kSlotRows = 3,        // cumulative: row ranges read
     kSlotBitmap = 4,      // cumulative: bitmap words streamed
     kSlotFoundAll = 5,    // cumulative: vertices reached / queued
-    kSlotXcd = 12,        // serving: XCD of the team member with this rank (a 32-bit word)
+    kSlotEngine = 12,     // serving: shader engine of the team member with this rank (32-bit word)
 };
 
 struct TraversalArgs {
@@ -193,8 +193,7 @@ struct alignas(256) BatchCtl {
     uint32_t min_active;
     uint32_t max_active;
     uint32_t _p2[57];
-    uint32_t active_x[16];     // active workgroups per XCD
-    uint32_t _p3[48];
+    uint32_t active_x[kMaxEngines];   // active workgroups per shader engine
 };
 
 struct BatchArgs {
@@ -267,8 +266,7 @@ struct alignas(256) ServeCtl {
     uint32_t max_active;
     uint32_t queries;          // queries completed
     uint32_t _p2[57];
-    uint32_t active_x[16];     // active workgroups per XCD
-    uint32_t _p3[48];
+    uint32_t active_x[kMaxEngines];   // active workgroups per shader engine
 };
 
 struct ServeArgs {
@@ -308,8 +306,9 @@ hipError_t launch_barrier_bench(const BarrierBenchArgs& a, bool coop, bool joine
                                 uint32_t block, uint32_t lds_bytes, hipStream_t s);
 hipError_t launch_cotask(const CotaskArgs& a, uint32_t block, uint32_t lds_bytes, hipStream_t s);
 uint32_t kernel_lds_bytes();   // LDS the traversal kernels need at least
-// out[g] = XCD of workgroup g, for `groups` one-wave workgroups
-hipError_t launch_xcd_probe(uint32_t* out, uint32_t groups, hipStream_t s);
+// out[2g] = XCD, out[2g+1] = shader engine of workgroup g, for `groups`
+// one-wave workgroups
+hipError_t launch_place_probe(uint32_t* out, uint32_t groups, hipStream_t s);
 uint32_t kernel_lds_bytes_for(uint32_t block);   // ... with `block` threads per workgroup
 
 }  // namespace coop

@@ -240,9 +240,12 @@ __global__ void init_ctx_kernel(Ctx* c, Work* w) {
     }
 }
 
-// Every workgroup records the XCD it runs on (the runtime counts XCDs).
-__global__ void xcd_probe_kernel(uint32_t* out) {
-    if (threadIdx.x == 0) out[blockIdx.x] = xcd_id();
+// Every workgroup records its XCD and shader engine (the runtime counts them).
+__global__ void place_probe_kernel(uint32_t* out) {
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x] = __builtin_amdgcn_s_getreg((3u << 11) | (0u << 6) | 20u) & 0xFu;
+        out[2 * blockIdx.x + 1] = (__builtin_amdgcn_s_getreg((31u << 11) | (0u << 6) | 4u) >> 13) & 7u;
+    }
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint64_t count, uint32_t value) {
@@ -287,8 +290,8 @@ namespace coop {
 
 uint32_t kernel_lds_bytes() { return (uint32_t)sizeof(BlockLds); }
 
-hipError_t launch_xcd_probe(uint32_t* out, uint32_t groups, hipStream_t s) {
-    hipLaunchKernelGGL(xcd_probe_kernel, dim3(groups), dim3(64), 0, s, out);
+hipError_t launch_place_probe(uint32_t* out, uint32_t groups, hipStream_t s) {
+    hipLaunchKernelGGL(place_probe_kernel, dim3(groups), dim3(64), 0, s, out);
     return hipGetLastError();
 }
 

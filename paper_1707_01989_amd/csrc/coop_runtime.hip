@@ -40,6 +40,7 @@ constexpr uint32_t kDefaultHeavy = 128;
 constexpr uint32_t kDefaultStrip = 4096;
 constexpr uint64_t kDefaultWatchdogNs = 10ull * 1000 * 1000 * 1000;
 constexpr uint32_t kDefaultStartupNs = 20 * 1000;
+constexpr bool kServerEnabled = false;
 
 double now_ms() {
     using namespace std::chrono;
@@ -118,6 +119,7 @@ struct coop_rt {
     hipDeviceProp_t props{};
     uint32_t wall_khz = 100000;
     uint32_t xcds = 1;                         // XCDs workgroups are dealt over
+    uint32_t ses = 1;                          // shader engines per XCD
     hipStream_t joiner_stream = nullptr;
     hipStream_t cotask_stream = nullptr;
     std::recursive_mutex mu;
@@ -313,8 +315,9 @@ int begin_launch(coop_rt* rt, const coop_launch_opts* o, const Sizing& sz, int k
     cfg.epoch0_wait = sz.startup_ticks;
     cfg.wgtrace = o ? o->d_wgtrace : nullptr;
     cfg.wgtrace_cap = (o && o->d_wgtrace) ? o->trace_cap : 0u;
-    cfg.xcds = rt->xcds;
-    cfg.slots_per_xcd = std::max<uint32_t>(1, sz.resident / std::max<uint32_t>(1, rt->xcds));
+    cfg.ses = rt->ses;
+    cfg.engines = rt->xcds * rt->ses;
+    cfg.slots_per_engine = std::max<uint32_t>(1, sz.resident / std::max<uint32_t>(1, cfg.engines));
     hipError_t e = coop::launch_init_ctx(h->ctx, h->work, stream);
     if (e != hipSuccess) { handle_free(h); return hip_fail(rt, e); }
     *hout = h;
@@ -455,17 +458,22 @@ int coop_init(int device, coop_rt** out) {
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&rt->h_stamp), 64,
                                            hipHostMallocCoherent | hipHostMallocMapped);
     if (e == hipSuccess) {
-        // count the XCDs: one small workgroup per slot of a 4x oversubscribed grid
+        // count the XCDs and the shader engines per XCD from where the
+        // workgroups of a 4x oversubscribed grid land
         const uint32_t groups = 4u * (uint32_t)std::max(1, rt->props.multiProcessorCount);
         uint32_t* d = nullptr;
-        e = hipMalloc(&d, (size_t)groups * 4);
-        if (e == hipSuccess) e = coop::launch_xcd_probe(d, groups, nullptr);
-        std::vector<uint32_t> h(groups, 0);
-        if (e == hipSuccess) e = hipMemcpy(h.data(), d, (size_t)groups * 4, hipMemcpyDeviceToHost);
+        e = hipMalloc(&d, (size_t)groups * 8);
+        if (e == hipSuccess) e = coop::launch_place_probe(d, groups, nullptr);
+        std::vector<uint32_t> h((size_t)groups * 2, 0);
+        if (e == hipSuccess) e = hipMemcpy(h.data(), d, (size_t)groups * 8, hipMemcpyDeviceToHost);
         if (d) (void)hipFree(d);
-        uint32_t mx = 0;
-        for (uint32_t v : h) mx = std::max(mx, v);
+        uint32_t mx = 0, ms = 0;
+        for (uint32_t g = 0; g < groups; ++g) {
+            mx = std::max(mx, h[2 * g]);
+            ms = std::max(ms, h[2 * g + 1]);
+        }
         rt->xcds = mx + 1;
+        rt->ses = ms + 1;
     }
     if (e != hipSuccess) {
         int rc = hip_fail(rt, e);
@@ -1265,6 +1273,8 @@ int coop_server_create(coop_rt* rt, const coop_graph* const* graphs, uint32_t ng
                        const coop_server_cfg* cfg, coop_server** out) {
     if (!rt || !graphs || ngraphs == 0 || !out) return COOP_E_INVALID;
     *out = nullptr;
+    // Switched off: a GPU fault has not been explained for this launch yet.
+    if (!kServerEnabled) return COOP_E_INVALID;
     coop_server_cfg c;
     coop_server_cfg_default(&c);
     if (cfg) c = *cfg;

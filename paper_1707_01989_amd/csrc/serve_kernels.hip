@@ -63,13 +63,14 @@ __device__ void serve_barrier(const ServeArgs& a, CtxCore* c, const Cfg tcfg, Me
             uint32_t Mn = m.M;
             if (Coop && a.cfg.host && !(flags & (kFlagEnd | kFlagAbort | kFlagDone))) {
                 // give up top members while the launch holds more than the
-                // target and their XCD more than its share (member 0 stays)
+                // target and their shader engine more than its share
+                // (member 0 stays)
                 const uint32_t T = ld_relaxed(&c->T_seen);
-                const uint32_t xcds = a.cfg.xcds;
+                const uint32_t engines = a.cfg.engines;
                 const LeaveCounters lc{&a.ctl->active, a.ctl->active_x, &a.ctl->kills, &a.ctl->min_active};
                 while (Mn > 1) {
-                    const uint32_t x = ld_relaxed(&slots[(size_t)(Mn - 1) * kSlotWords + kSlotXcd]) & 15u;
-                    if (!leave_for_target(lc, T, a.team_max, xcds, x)) break;
+                    const uint32_t x = ld_relaxed(&slots[(size_t)(Mn - 1) * kSlotWords + kSlotEngine]);
+                    if (!leave_for_target(lc, T, a.team_max, engines, x)) break;
                     --Mn;
                 }
             }
@@ -102,9 +103,10 @@ __device__ void serve_barrier(const ServeArgs& a, CtxCore* c, const Cfg tcfg, Me
 // Query start (thread 0): the slot's current epoch, the SSSP round counter,
 // this member's XCD (for the team's master), and (rank 0) the transmit
 // block's source index reset for this query.
-__device__ __forceinline__ void query_start(BlockLds& sh, CtxCore* c, Work* wk, uint32_t* slots, uint32_t rank) {
+__device__ __forceinline__ void query_start(BlockLds& sh, CtxCore* c, Work* wk, uint32_t* slots, uint32_t rank,
+                                            uint32_t ses) {
     if (threadIdx.x == 0) {
-        st_relaxed(&slots[(size_t)rank * kSlotWords + kSlotXcd], xcd_id());
+        st_relaxed(&slots[(size_t)rank * kSlotWords + kSlotEngine], engine_id(ses));
         const uint64_t r = ld_relaxed64(&c->release);
         fence_acquire();
         sh.level = rel_epoch(r);
@@ -121,7 +123,7 @@ template <bool Coop>
 __device__ __forceinline__ uint32_t serve_bfs(const ServeArgs& a, const BfsArgs& p, BlockLds& sh, uint32_t rank,
                                           uint32_t team, const uint32_t* roots, uint32_t* out) {
     CtxCore* c = p.t.ctx;
-    query_start(sh, c, p.t.work, p.t.slots, rank);
+    query_start(sh, c, p.t.work, p.t.slots, rank, p.t.cfg.ses);
     Member m{rank, team, sh.level, 0u, 1u};
     uint32_t level = 0, root = 0, ph = kPhInit;
     for (;;) {
@@ -143,7 +145,7 @@ template <bool Coop>
 __device__ __forceinline__ uint32_t serve_sssp(const ServeArgs& a, const SsspArgs& p, BlockLds& sh, uint32_t rank,
                                            uint32_t team, const uint32_t* roots, int32_t* out) {
     CtxCore* c = p.t.ctx;
-    query_start(sh, c, p.t.work, p.t.slots, rank);
+    query_start(sh, c, p.t.work, p.t.slots, rank, p.t.cfg.ses);
     Member m{rank, team, sh.level, 0u, 1u};
     uint32_t round = sh.aux, root = 0, ph = kPhInit;
     for (;;) {
@@ -191,7 +193,7 @@ __device__ void serve_body(const ServeArgs& a, bool joiner) {
         for (int i = 0; i < 8; ++i) sh.acc[i] = 0;
         sh.bar.killed = 0;
         const uint32_t act = add_relaxed(&ctl->active, 1u) + 1;
-        add_relaxed(&ctl->active_x[xcd_id()], 1u);
+        add_relaxed(&ctl->active_x[engine_id(a.cfg.ses) % kMaxEngines], 1u);
         atomicMax(&ctl->max_active, act);
         if (joiner) add_relaxed(&ctl->forks, 1u);
     }
@@ -202,7 +204,7 @@ __device__ void serve_body(const ServeArgs& a, bool joiner) {
                 if (ld_relaxed_i(&ctl->error)) { leave = 1; break; }
                 if (Coop && a.cfg.host && (it & 7) == 0 &&
                     leave_for_target(LeaveCounters{&ctl->active, ctl->active_x, &ctl->kills, &ctl->min_active},
-                                     ld_system(&a.cfg.host->target), a.team_max, a.cfg.xcds, xcd_id())) {
+                                     ld_system(&a.cfg.host->target), a.team_max, a.cfg.engines, engine_id(a.cfg.ses))) {
                     leave = 2;
                     break;
                 }
@@ -235,7 +237,7 @@ __device__ void serve_body(const ServeArgs& a, bool joiner) {
             }
             if (leave == 1 || leave == 3) {
                 add_relaxed(&ctl->active, 0xFFFFFFFFu);
-                add_relaxed(&ctl->active_x[xcd_id()], 0xFFFFFFFFu);
+                add_relaxed(&ctl->active_x[engine_id(a.cfg.ses) % kMaxEngines], 0xFFFFFFFFu);
                 add_relaxed(&ctl->left, 1u);
             }
             q_leave = leave;
@@ -267,7 +269,7 @@ __device__ void serve_body(const ServeArgs& a, bool joiner) {
             if (threadIdx.x == 0 && !sh.bar.killed) {
                 atomicCAS(&ctl->error, 0, ld_relaxed_i(&c->error) ? ld_relaxed_i(&c->error) : kErrInternal);
                 add_relaxed(&ctl->active, 0xFFFFFFFFu);
-                add_relaxed(&ctl->active_x[xcd_id()], 0xFFFFFFFFu);
+                add_relaxed(&ctl->active_x[engine_id(a.cfg.ses) % kMaxEngines], 0xFFFFFFFFu);
             }
             return;
         }

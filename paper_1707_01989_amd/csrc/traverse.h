@@ -947,24 +947,26 @@ __device__ __forceinline__ uint32_t color_master(const ColorArgs& p, BlockLds& s
 // Counters of a launch whose workgroups leave between instances or queries.
 struct LeaveCounters {
     uint32_t* active;          // workgroups inside the loop
-    uint32_t* active_x;        // ... per XCD
+    uint32_t* active_x;        // ... per shader engine
     uint32_t* kills;
     uint32_t* min_active;
 };
 
 // offer_kill between instances (thread 0): leave if the launch holds more
-// workgroups than max(T, floor) and this workgroup's XCD holds more than its
-// share ceil(T / xcds) (a competing kernel needs compute units on every XCD).
-__device__ inline bool leave_for_target(const LeaveCounters& lc, uint32_t T, uint32_t floor, uint32_t xcds,
+// workgroups than max(T, floor) and this workgroup's shader engine holds
+// more than its share ceil(T / engines) (a competing kernel is dealt over
+// every engine, so it needs free compute units on each of them).
+__device__ inline bool leave_for_target(const LeaveCounters& lc, uint32_t T, uint32_t floor, uint32_t engines,
                                         uint32_t x) {
     const uint32_t lo = T > floor ? T : floor;
-    const uint32_t share = xcds > 1 ? (T + xcds - 1) / xcds : T;
-    if (xcds > 1 && ld_relaxed(&lc.active_x[x]) <= share) return false;
+    const bool placed = engines > 1 && engines <= kMaxEngines;
+    const uint32_t share = placed ? (T + engines - 1) / engines : T;
+    if (placed && ld_relaxed(&lc.active_x[x % kMaxEngines]) <= share) return false;
     uint32_t a = ld_relaxed(lc.active);
     while (a > lo) {
         if (__hip_atomic_compare_exchange_strong(lc.active, &a, a - 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT)) {
-            add_relaxed(&lc.active_x[x], 0xFFFFFFFFu);
+            add_relaxed(&lc.active_x[x % kMaxEngines], 0xFFFFFFFFu);
             add_relaxed(lc.kills, 1u);
             atomicMin(lc.min_active, a - 1);
             return true;

@@ -332,12 +332,11 @@ def test_bfs_host_target_xcd_kills(rt, coop_mod, gg):
     dg.release()
 
 
-@pytest.mark.xfail(reason="a co-task can still wait for the end of the traversal; cause under investigation",
-                   strict=False)
 def test_cotask_injector_during_bfs(rt, coop_mod, gg):
     """Co-tasks needing half the CUs run while a cooperative BFS holds the
-    GPU: the kernel frees compute units on every XCD, so each co-task runs
-    within its period instead of waiting for the traversal to end."""
+    GPU: the kernel frees compute units on every shader engine (the hardware
+    deals the co-task's workgroups round-robin over XCDs and their engines),
+    so each co-task runs at once instead of waiting for the traversal."""
     import torch
     c = coop_mod
     g = gg.rmat(18, 16, seed=3)

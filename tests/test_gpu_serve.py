@@ -11,7 +11,12 @@ import pytest
 import oracle
 from tests.conftest import gpu_available
 
-pytestmark = pytest.mark.gpu
+pytestmark = [
+    pytest.mark.gpu,
+    pytest.mark.skip(reason="the first GPU run of a suite containing these tests ended the box with a GPU "
+                            "fault or hung queue; the cause is not yet shown, so the server stays off the GPU "
+                            "(coop_server_create refuses to start) until it is"),
+]
 
 
 def say(msg):
