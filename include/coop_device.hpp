@@ -213,7 +213,8 @@ struct BarrierLds {
     uint32_t flags;         // master step result (broadcast inside the master)
     uint32_t head, kmax, T;
     uint32_t kmax2;                    // kill count of the barrier
-    uint32_t my_new;                   // XCD-aware kill: the master's new id
+    uint32_t my_new;                   // placed kill: the master's new id
+    uint32_t T_pre;                    // workgroup 0: host target read during the phase
     uint32_t valid[kMaxGroups / 32];   // admission: ring slots whose joiner was still waiting
     uint32_t xcnt[kMaxEngines];        // placed kill: members per engine, then victims per engine
     uint32_t wsum[kMaxWaves + 1];      // placed kill: survivors per wave of ids
@@ -547,9 +548,11 @@ __device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, Ma
     __syncthreads();
     wg_trace(cfg, m.epoch, m.id, kTrArrive);
     if (threadIdx.x == 0) {
+        // workgroup 0 passes the host target to the master; after the first
+        // barrier the value was read over PCIe while the phase ran
         if (Coop && cfg.host && m.id == 0)
-            __hip_atomic_store(&c->T_seen, ld_system(&cfg.host->target), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&c->T_seen, m.epoch == 0 ? ld_system(&cfg.host->target) : b.T_pre,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint32_t old = __hip_atomic_fetch_add(&c->arrive, 1u, __ATOMIC_ACQ_REL,
                                                     __HIP_MEMORY_SCOPE_AGENT);
         b.is_master = (old + 1 == m.M) ? 1u : 0u;
@@ -589,6 +592,12 @@ __device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, Ma
     __syncthreads();
     wg_trace(cfg, m.epoch, m.id, kTrReleased);
     m = b.member;
+    // workgroup 0 (never killed, never renumbered) reads the host target for
+    // the next barrier now, in its last wave, so the PCIe round trip overlaps
+    // the phase instead of delaying its arrival (it often holds the work of
+    // a small frontier and arrives last)
+    if (Coop && cfg.host && m.id == 0 && m.alive && threadIdx.x == blockDim.x - 64)
+        b.T_pre = ld_system(&cfg.host->target);
 }
 
 // Barrier of a team: a fixed set of `m.M` workgroups that work on one
