@@ -212,7 +212,6 @@ struct BarrierLds {
     uint32_t is_master;     // this workgroup runs the master step
     uint32_t flags;         // master step result (broadcast inside the master)
     uint32_t head, kmax, T;
-    uint32_t kmax2;                    // kill count of the barrier
     uint32_t my_new;                   // placed kill: the master's new id
     uint32_t T_pre;                    // workgroup 0: host target read during the phase
     uint32_t valid[kMaxGroups / 32];   // admission: ring slots whose joiner was still waiting
@@ -425,14 +424,14 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
         }
     }
     // kill decision: W = the surplus over the target, never workgroup 0
-    if (threadIdx.x == 0) {
-        uint32_t W = 0;
-        if (Coop && !(b.flags & (kFlagDone | kFlagAbort))) {
+    // (every thread computes it from the shared values of this step)
+    uint32_t W = 0;
+    if constexpr (Coop) {
+        if (!(b.flags & (kFlagDone | kFlagAbort))) {
             const uint32_t M2 = m.M + admitted;
             W = M2 > b.T ? M2 - b.T : 0u;
             if (W > M2 - 1) W = M2 - 1;
         }
-        b.kmax2 = W;
     }
     // A host-driven target asks for compute units for another kernel, whose
     // workgroups the hardware deals round-robin over the XCDs and their
@@ -441,8 +440,6 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
     bool renum = false;
     uint32_t Mn_sel = 0, my_new = m.id;
     if constexpr (Coop) {
-        __syncthreads();
-        const uint32_t W = b.kmax2;
         if (W && cfg.host && !(cfg.mode & kModeRandomSched) && cfg.engines > 1 && cfg.engines <= kMaxEngines) {
             renum = true;
             const uint32_t M2 = m.M + admitted;
@@ -499,13 +496,13 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
         uint32_t Mn = m.M;
         if (Coop && !(flags & (kFlagDone | kFlagAbort))) {
             const uint32_t M2 = m.M + admitted;
-            const uint32_t W = renum ? M2 - Mn_sel : b.kmax2;
-            Mn = M2 - W;
+            const uint32_t Wk = renum ? M2 - Mn_sel : W;
+            Mn = M2 - Wk;
             if (renum) flags |= kFlagRenum;
             if (b.kmax) c->join_head = b.head + b.kmax;
             if (cfg.mode & kModeRandomSched) c->T_dev = T_dev;
             if (admitted) c->forks = forks + admitted;
-            if (W) c->kills = kills + W;
+            if (Wk) c->kills = kills + Wk;
             if (Mn != m.M) c->resizes = resizes + 1;
             if (Mn < min_M) c->min_M = Mn;
             if (Mn > max_M) c->max_M = Mn;

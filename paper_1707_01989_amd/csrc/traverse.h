@@ -89,6 +89,13 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
     return x;
 }
 
+// Wave slot of this wave in the interval: units are dealt from the highest
+// logical id down, so a small frontier lands on the last workgroups and not
+// on workgroup 0 (which also relays the scheduler target every barrier).
+__device__ __forceinline__ uint32_t wave_slot(uint32_t id, uint32_t M, uint32_t nw) {
+    return (M - 1 - id) * nw + wave_id();
+}
+
 // ----------------------------------------------------------- LDS layout
 
 struct WaveLds {
@@ -123,14 +130,15 @@ __device__ void stats_to_lds(BlockLds& sh, const Stats& s) {
 }
 
 // Add the workgroup's phase statistics to its slot (after a __syncthreads);
-// fire-and-forget atomics, so nobody waits for the round trip.
-__device__ void acc_to_slot(BlockLds& sh, uint32_t* slots, uint32_t id) {
+// fire-and-forget atomics, so nobody waits for the round trip. Fields 0 and 1
+// are per level and only kept when the master step reads them (BFS);
+// fields 2, 3, 4 and the found total are cumulative.
+__device__ void acc_to_slot(BlockLds& sh, uint32_t* slots, uint32_t id, bool per_level = true) {
     if (threadIdx.x < 5) {
         uint64_t* s = reinterpret_cast<uint64_t*>(slots + (size_t)id * kSlotWords);
         const uint64_t v = sh.acc[threadIdx.x];
         if (v) {
-            // fields 0,1 are per level; 2,3,4 cumulative; found is also kept cumulatively
-            add_nr64(&s[threadIdx.x], v);
+            if (per_level || threadIdx.x >= 2) add_nr64(&s[threadIdx.x], v);
             if (threadIdx.x == 0) add_nr64(&s[kSlotFoundAll], v);
         }
         sh.acc[threadIdx.x] = 0;
@@ -499,7 +507,7 @@ __device__ __forceinline__ void bfs_phase(const BfsArgs& p, BlockLds& sh, uint32
     uint32_t* nxt = p.fb[(rot + 1) % 3];
     uint32_t* spare = p.fb[(rot + 2) % 3];
     uint32_t* lvl = lvl_base + (size_t)root * t.out_stride;
-    const uint32_t gw = id * nw + wave_id();
+    const uint32_t gw = wave_slot(id, M, nw);
     const uint32_t W = M * nw;
     Stats st;
     if (ph == kPhInit) {
@@ -692,7 +700,7 @@ __device__ __forceinline__ void sssp_phase(const SsspArgs& p, BlockLds& sh, uint
     const bool sel = (flags & kFlagSel) != 0;
     uint32_t* in = t.frontier[sel ? 1 : 0];
     uint32_t* out = t.frontier[sel ? 0 : 1];
-    const uint32_t gw = id * nw + wave_id();
+    const uint32_t gw = wave_slot(id, M, nw);
     const uint32_t W = M * nw;
     Stats st;
     if (ph == kPhInit) {
@@ -721,7 +729,7 @@ __device__ __forceinline__ void sssp_phase(const SsspArgs& p, BlockLds& sh, uint
         wg_flush(sh, &wk->out_tail, out);
         stats_to_lds(sh, st);
         __syncthreads();
-        acc_to_slot(sh, t.slots, id);
+        acc_to_slot(sh, t.slots, id, false);
     }
 }
 
@@ -732,8 +740,6 @@ __device__ __forceinline__ uint32_t sssp_master(const SsspArgs& p, BlockLds& sh,
                                                 uint32_t cur_flags, const uint32_t* roots) {
     const TraversalArgs& t = p.t;
     Work* wk = t.work;
-    uint64_t tot[2];
-    master_sum_slots(sh, t.slots, t.N, tot);
     if (threadIdx.x == 0) {
         XferR x = wk->load_x();                 // one batch of loads
         const uint32_t hs = ld_relaxed(&wk->heavy_tail);
@@ -873,7 +879,7 @@ __device__ __forceinline__ void color_phase(const ColorArgs& p, BlockLds& sh, ui
     const bool sel = (flags & kFlagSel) != 0;
     uint32_t* in = t.frontier[sel ? 1 : 0];
     uint32_t* out = t.frontier[sel ? 0 : 1];
-    const uint32_t gw = id * nw + wave_id();
+    const uint32_t gw = wave_slot(id, M, nw);
     const uint32_t W = M * nw;
     WaveLds& w = sh.wave[wave_id()];
     Stats st;
@@ -910,7 +916,7 @@ __device__ __forceinline__ void color_phase(const ColorArgs& p, BlockLds& sh, ui
         wg_flush(sh, &wk->out_tail, out);
         stats_to_lds(sh, st);
         __syncthreads();
-        acc_to_slot(sh, t.slots, id);
+        acc_to_slot(sh, t.slots, id, false);
     }
 }
 
@@ -919,8 +925,6 @@ __device__ __forceinline__ void color_phase(const ColorArgs& p, BlockLds& sh, ui
 __device__ __forceinline__ uint32_t color_master(const ColorArgs& p, BlockLds& sh, uint32_t ph, uint32_t cur_flags) {
     const TraversalArgs& t = p.t;
     Work* wk = t.work;
-    uint64_t tot[2];
-    master_sum_slots(sh, t.slots, t.N, tot);
     if (threadIdx.x == 0) {
         XferR x = wk->load_x();
         const uint32_t ot = ld_relaxed(&wk->out_tail);
