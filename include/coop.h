@@ -106,7 +106,7 @@ typedef struct coop_launch_opts {
     uint32_t lds_bytes;       /* LDS per workgroup; 0 = 96 KiB (one workgroup per CU) */
     uint32_t flags;           /* COOP_F_* */
     uint32_t heavy_threshold; /* degree above which a vertex is split into strips; 0 = 128 */
-    uint32_t strip;           /* arcs per strip; 0 = 4096 */
+    uint32_t strip;           /* arcs per strip; 0 = 512 */
     uint32_t startup_wait_ns; /* how long workgroup 0 waits for the grid to register; 0 = 20 us */
     uint64_t sched_seed;      /* COOP_F_RANDOM_SCHEDULE: seed */
     double sched_p;           /* COOP_F_RANDOM_SCHEDULE: P(target changes) per barrier */
@@ -289,7 +289,7 @@ typedef struct coop_tune {
     uint32_t team_max;        /* largest team; 0 = max(1, N / 8); must be <= N */
     uint32_t direction_opt;   /* BFS: 1 = direction-optimising, 0 = top-down only */
     uint32_t heavy_threshold; /* as coop_launch_opts; 0 = 128 */
-    uint32_t strip;           /* as coop_launch_opts; 0 = 4096 */
+    uint32_t strip;           /* as coop_launch_opts; 0 = 512 */
 } coop_tune;
 
 /* Defaults (what an untuned batch runs with). */
@@ -345,7 +345,7 @@ typedef struct coop_server_cfg {
     uint64_t team_arcs_sssp;  /* likewise for SSSP queries; 0 = 2^22 */
     uint32_t direction_opt;   /* BFS: 1 = direction-optimising, 0 = top-down only */
     uint32_t heavy_threshold; /* 0 = 128 */
-    uint32_t strip;           /* 0 = 4096 */
+    uint32_t strip;           /* 0 = 512 */
     uint32_t reserved;
     uint64_t watchdog_ns;     /* barrier spin bound; 0 = 10 s */
 } coop_server_cfg;

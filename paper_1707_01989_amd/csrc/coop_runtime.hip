@@ -37,7 +37,7 @@ namespace {
 
 constexpr uint32_t kDefaultLds = 96 * 1024;       // > half a CU's 160 KiB: one workgroup per CU
 constexpr uint32_t kDefaultHeavy = 128;
-constexpr uint32_t kDefaultStrip = 4096;
+constexpr uint32_t kDefaultStrip = 512;          // one wave walk step (64 lanes x 8 arcs)
 constexpr uint64_t kDefaultWatchdogNs = 10ull * 1000 * 1000 * 1000;
 constexpr uint32_t kDefaultStartupNs = 20 * 1000;
 constexpr bool kServerEnabled = false;

@@ -104,6 +104,7 @@ struct WaveLds {
     uint32_t pay[kWave];        // algorithm payload (distance, degree ...)
     uint32_t out_n;             // entries in the output buffer
     uint32_t out[kOutCap];
+    uint32_t lng[2 * kWave];    // bottom-up: candidates with long lists, scanned by the whole wave
 };
 
 struct BlockLds {
@@ -362,7 +363,7 @@ struct BfsTopDown {
                 const uint32_t old = __hip_atomic_fetch_or(&vis[u[j] >> 5], bit, __ATOMIC_RELAXED,
                                                            __HIP_MEMORY_SCOPE_AGENT);
                 if (!(old & bit)) {
-                    level[u[j]] = next_level;
+                    __builtin_nontemporal_store(next_level, &level[u[j]]);
                     __hip_atomic_fetch_or(&nxt[u[j] >> 5], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     st.found += 1;
                     if (count_mf) {
@@ -380,9 +381,23 @@ struct BfsTopDown {
 // level. A wave owns blocks of 32 bitmap words (1024 vertices): lanes 0..31
 // load one visited word each, the unvisited vertices with arcs are compacted
 // into an LDS list, and the list is probed two candidates per lane, so every
-// batch is full and two independent load chains are in flight per lane.
-// Found bits are gathered in LDS and each block's visited and next-frontier
-// words are written once, with plain stores (no other wave owns them).
+// batch is full and two independent load chains are in flight per lane. A
+// lane gives up after kLaneRounds steps of 4 arcs; the candidates still
+// unresolved (long lists without an early hit) are then scanned by the whole
+// wave, 256 arcs per step, so one long list no longer holds the wave (and
+// the level) for hundreds of dependent steps. Found bits are gathered in LDS
+// and each block's visited and next-frontier words are written once, with
+// plain stores (no other wave owns them).
+constexpr uint32_t kLaneRounds = 8;
+
+__device__ __forceinline__ void bu_mark(const BfsArgs& p, uint32_t* fw, uint32_t* level, uint32_t v,
+                                        uint32_t next_level, uint32_t block, uint32_t deg, Stats& st) {
+    __builtin_nontemporal_store(next_level, &level[v]);
+    atomicOr(&fw[(v >> 5) - block * 32u], 1u << (v & 31));
+    st.found += 1;
+    st.mf += deg;
+}
+
 __device__ void bfs_bottom_up(const BfsArgs& p, WaveLds& wl, const uint32_t* cur, uint32_t* nxt,
                               uint32_t* level, uint32_t next_level, uint32_t gw, uint32_t W, Stats& st) {
     constexpr uint32_t kBlockWords = 32;
@@ -426,7 +441,8 @@ __device__ void bfs_bottom_up(const BfsArgs& p, WaveLds& wl, const uint32_t* cur
                     st.rows += 1;
                 }
             }
-            while (__ballot((k[0] < e[0] && !hit[0]) || (k[1] < e[1] && !hit[1]))) {
+            for (uint32_t it = 0; it < kLaneRounds &&
+                                  __ballot((k[0] < e[0] && !hit[0]) || (k[1] < e[1] && !hit[1])); ++it) {
                 uint32_t u[2][4];
 #pragma unroll
                 for (int c = 0; c < 2; ++c)
@@ -444,15 +460,39 @@ __device__ void bfs_bottom_up(const BfsArgs& p, WaveLds& wl, const uint32_t* cur
                     k[c] += got;
                 }
             }
+            // resolved candidates; the rest go to the wave's long list
+            uint32_t nlong = 0;
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                if (hit[c]) {
-                    level[v[c]] = next_level;
-                    atomicOr(&fw[(v[c] >> 5) - b * kBlockWords], 1u << (v[c] & 31));
-                    st.found += 1;
-                    st.mf += e[c] - s0[c];
-                }
+                if (hit[c]) bu_mark(p, fw, level, v[c], next_level, b, e[c] - s0[c], st);
+                const bool lng = !hit[c] && k[c] < e[c];
+                const uint64_t mask = __ballot(lng);
+                if (lng) wl.lng[nlong + mbcnt(mask)] = v[c];
+                nlong += (uint32_t)__popcll(mask);
             }
+            __builtin_amdgcn_wave_barrier();
+            // long lists: the whole wave scans one candidate at a time
+            for (uint32_t i = 0; i < nlong; ++i) {
+                const uint32_t vv = wl.lng[i];
+                const uint32_t a0 = p.t.row_ptr[vv], a1 = p.t.row_ptr[vv + 1];
+                bool found = false;
+                for (uint32_t kk = a0 + 4 * kLaneRounds; kk < a1 && !found; kk += 4 * kWave) {
+                    uint32_t u[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const uint32_t a = kk + j * kWave + l;
+                        u[j] = a < a1 ? p.t.col[a] : 0xFFFFFFFFu;
+                    }
+                    bool h = false;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (u[j] != 0xFFFFFFFFu) h |= ((cur[u[j] >> 5] >> (u[j] & 31)) & 1u) != 0;
+                    found = __ballot(h) != 0;
+                    st.arcs += l == 0 ? (a1 - kk < 4 * kWave ? a1 - kk : 4 * kWave) : 0u;
+                }
+                if (found && l == 0) bu_mark(p, fw, level, vv, next_level, b, a1 - a0, st);
+            }
+            __builtin_amdgcn_wave_barrier();
         }
         __builtin_amdgcn_wave_barrier();
         if (l < 32) {
@@ -512,7 +552,9 @@ __device__ __forceinline__ void bfs_phase(const BfsArgs& p, BlockLds& sh, uint32
     Stats st;
     if (ph == kPhInit) {
         const uint32_t tid = id * blockDim.x + threadIdx.x, stride = M * blockDim.x;
-        for (uint32_t i = tid; i < t.n; i += stride) lvl[i] = kInf;
+        // the level array is output only: streamed, so it does not sit dirty
+        // in L2 for the next barrier's release to write back
+        for (uint32_t i = tid; i < t.n; i += stride) __builtin_nontemporal_store(kInf, &lvl[i]);
         for (uint32_t i = tid; i < p.words; i += stride) {
             p.vis[i] = 0;
             p.fb[0][i] = 0;
@@ -561,7 +603,7 @@ __device__ __forceinline__ uint32_t bfs_master(const BfsArgs& p, BlockLds& sh, C
         } else if (ph == kPhInit) {
             const uint32_t src = roots[x.root()];
             uint32_t* lv = lvl_base + (size_t)x.root() * t.out_stride;
-            lv[src] = 0;
+            __builtin_nontemporal_store(0u, &lv[src]);
             p.vis[src >> 5] |= 1u << (src & 31);
             p.fb[0][src >> 5] |= 1u << (src & 31);
             x.level() = 0;
@@ -709,7 +751,8 @@ __device__ __forceinline__ void sssp_phase(const SsspArgs& p, BlockLds& sh, uint
         for (uint32_t i = tid; i < t.n; i += stride) p.state[i] = 0x7FFFFFFFull << 32;
     } else if (ph == kPhOut) {
         const uint32_t tid = id * blockDim.x + threadIdx.x, stride = M * blockDim.x;
-        for (uint32_t i = tid; i < t.n; i += stride) dist[i] = (int32_t)(p.state[i] >> 32);
+        for (uint32_t i = tid; i < t.n; i += stride)
+            __builtin_nontemporal_store((int32_t)(p.state[i] >> 32), &dist[i]);
     } else if (ph == kPhTD || ph == kPhHeavy) {
         if (threadIdx.x == 0) sh.in_size = wk->x.in_size;
         __syncthreads();
