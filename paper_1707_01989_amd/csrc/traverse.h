@@ -380,12 +380,13 @@ struct BfsTopDown {
 // one in the current frontier; the first hit makes it a member of the next
 // level. A wave owns blocks of 32 bitmap words (1024 vertices): lanes 0..31
 // load one visited word each, the unvisited vertices with arcs are compacted
-// into an LDS list, and the list is probed two candidates per lane, so every
-// batch is full and two independent load chains are in flight per lane. A
-// lane gives up after kLaneRounds steps of 4 arcs; the candidates still
-// unresolved (long lists without an early hit) are then scanned by the whole
-// wave, 256 arcs per step, so one long list no longer holds the wave (and
-// the level) for hundreds of dependent steps. Found bits are gathered in LDS
+// into an LDS list, and each lane probes two candidates at a time, taking the
+// next candidate from the list as soon as one resolves, so two independent
+// load chains stay in flight per lane until the list runs dry. A lane gives
+// a candidate up after kLaneRounds steps of 4 arcs; such candidates (long
+// lists without an early hit) are scanned by the whole wave, 256 arcs per
+// step, so one long list does not hold the wave (and the level) for hundreds
+// of dependent steps. Found bits are gathered in LDS
 // and each block's visited and next-frontier words are written once, with
 // plain stores (no other wave owns them).
 constexpr uint32_t kLaneRounds = 8;
@@ -396,6 +397,34 @@ __device__ __forceinline__ void bu_mark(const BfsArgs& p, uint32_t* fw, uint32_t
     atomicOr(&fw[(v >> 5) - block * 32u], 1u << (v & 31));
     st.found += 1;
     st.mf += deg;
+}
+
+// Scan the deferred long lists with the whole wave, one candidate at a time,
+// 256 arcs per step, from where the lane left off (kLaneRounds x 4 arcs in).
+__device__ void bu_scan_long(const BfsArgs& p, WaveLds& wl, const uint32_t* cur, uint32_t* fw, uint32_t* level,
+                             uint32_t next_level, uint32_t block, uint32_t nlong, Stats& st) {
+    const uint32_t l = lane_id();
+    for (uint32_t i = 0; i < nlong; ++i) {
+        const uint32_t vv = wl.lng[i];
+        const uint32_t a0 = p.t.row_ptr[vv], a1 = p.t.row_ptr[vv + 1];
+        bool found = false;
+        for (uint32_t kk = a0 + 4 * kLaneRounds; kk < a1 && !found; kk += 4 * kWave) {
+            uint32_t u[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t a = kk + j * kWave + l;
+                u[j] = a < a1 ? p.t.col[a] : 0xFFFFFFFFu;
+            }
+            bool h = false;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (u[j] != 0xFFFFFFFFu) h |= ((cur[u[j] >> 5] >> (u[j] & 31)) & 1u) != 0;
+            found = __ballot(h) != 0;
+            st.arcs += l == 0 ? (a1 - kk < 4 * kWave ? a1 - kk : 4 * kWave) : 0u;
+        }
+        if (found && l == 0) bu_mark(p, fw, level, vv, next_level, block, a1 - a0, st);
+    }
+    __builtin_amdgcn_wave_barrier();
 }
 
 __device__ void bfs_bottom_up(const BfsArgs& p, WaveLds& wl, const uint32_t* cur, uint32_t* nxt,
@@ -424,75 +453,70 @@ __device__ void bfs_bottom_up(const BfsArgs& p, WaveLds& wl, const uint32_t* cur
             cand &= cand - 1;
         }
         __builtin_amdgcn_wave_barrier();
-        for (uint32_t base = 0; base < total; base += 2 * kWave) {
-            uint32_t v[2], k[2], e[2], s0[2];
-            bool hit[2] = {false, false};
+        // Two probe slots per lane; a slot that resolves its candidate takes
+        // the next one from the list, so the wave keeps 128 chains busy
+        // instead of waiting for the slowest lane of a batch.
+        uint32_t next = 0, nlong = 0;
+        uint32_t v[2] = {0, 0}, k[2] = {0, 0}, e[2] = {0, 0}, s0[2] = {0, 0}, rounds[2] = {0, 0};
+        bool act[2] = {false, false};
+        for (;;) {
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                const uint32_t i = base + c * kWave + l;
-                v[c] = i < total ? list[i] : 0xFFFFFFFFu;
-                s0[c] = k[c] = e[c] = 0;
-            }
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                if (v[c] != 0xFFFFFFFFu) {
-                    s0[c] = k[c] = p.t.row_ptr[v[c]];
-                    e[c] = p.t.row_ptr[v[c] + 1];
-                    st.rows += 1;
+                const bool need = !act[c];
+                const uint64_t mask = __ballot(need);
+                if (next < total && mask) {
+                    const uint32_t idx = next + mbcnt(mask);
+                    if (need && idx < total) {
+                        v[c] = list[idx];
+                        act[c] = true;
+                        rounds[c] = 0;
+                        s0[c] = k[c] = p.t.row_ptr[v[c]];
+                        e[c] = p.t.row_ptr[v[c] + 1];
+                        st.rows += 1;
+                    }
+                    next += (uint32_t)__popcll(mask);
                 }
             }
-            for (uint32_t it = 0; it < kLaneRounds &&
-                                  __ballot((k[0] < e[0] && !hit[0]) || (k[1] < e[1] && !hit[1])); ++it) {
-                uint32_t u[2][4];
+            if (!__ballot(act[0] || act[1])) break;
+            uint32_t u[2][4];
 #pragma unroll
-                for (int c = 0; c < 2; ++c)
+            for (int c = 0; c < 2; ++c)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        u[c][j] = (!hit[c] && k[c] + j < e[c]) ? p.t.col[k[c] + j] : 0xFFFFFFFFu;
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    if (hit[c] || k[c] >= e[c]) continue;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (u[c][j] != 0xFFFFFFFFu) hit[c] |= ((cur[u[c][j] >> 5] >> (u[c][j] & 31)) & 1u) != 0;
-                    const uint32_t got = e[c] - k[c] < 4 ? e[c] - k[c] : 4u;
-                    st.arcs += got;
-                    k[c] += got;
-                }
-            }
-            // resolved candidates; the rest go to the wave's long list
-            uint32_t nlong = 0;
+                for (int j = 0; j < 4; ++j)
+                    u[c][j] = (act[c] && k[c] + j < e[c]) ? p.t.col[k[c] + j] : 0xFFFFFFFFu;
+            bool defer[2] = {false, false};
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                if (hit[c]) bu_mark(p, fw, level, v[c], next_level, b, e[c] - s0[c], st);
-                const bool lng = !hit[c] && k[c] < e[c];
-                const uint64_t mask = __ballot(lng);
-                if (lng) wl.lng[nlong + mbcnt(mask)] = v[c];
+                if (!act[c]) continue;
+                bool hit = false;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (u[c][j] != 0xFFFFFFFFu) hit |= ((cur[u[c][j] >> 5] >> (u[c][j] & 31)) & 1u) != 0;
+                const uint32_t got = e[c] - k[c] < 4 ? e[c] - k[c] : 4u;
+                st.arcs += got;
+                k[c] += got;
+                rounds[c] += 1;
+                if (hit) {
+                    bu_mark(p, fw, level, v[c], next_level, b, e[c] - s0[c], st);
+                    act[c] = false;
+                } else if (k[c] >= e[c]) {
+                    act[c] = false;                  // no parent in this frontier
+                } else if (rounds[c] == kLaneRounds) {
+                    defer[c] = true;                 // long list: the whole wave scans it
+                    act[c] = false;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const uint64_t mask = __ballot(defer[c]);
+                if (defer[c]) wl.lng[nlong + mbcnt(mask)] = v[c];
                 nlong += (uint32_t)__popcll(mask);
             }
-            __builtin_amdgcn_wave_barrier();
-            // long lists: the whole wave scans one candidate at a time
-            for (uint32_t i = 0; i < nlong; ++i) {
-                const uint32_t vv = wl.lng[i];
-                const uint32_t a0 = p.t.row_ptr[vv], a1 = p.t.row_ptr[vv + 1];
-                bool found = false;
-                for (uint32_t kk = a0 + 4 * kLaneRounds; kk < a1 && !found; kk += 4 * kWave) {
-                    uint32_t u[4];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const uint32_t a = kk + j * kWave + l;
-                        u[j] = a < a1 ? p.t.col[a] : 0xFFFFFFFFu;
-                    }
-                    bool h = false;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (u[j] != 0xFFFFFFFFu) h |= ((cur[u[j] >> 5] >> (u[j] & 31)) & 1u) != 0;
-                    found = __ballot(h) != 0;
-                    st.arcs += l == 0 ? (a1 - kk < 4 * kWave ? a1 - kk : 4 * kWave) : 0u;
-                }
-                if (found && l == 0) bu_mark(p, fw, level, vv, next_level, b, a1 - a0, st);
+            if (nlong) {                             // at most 2 x 64 deferrals: the list's capacity
+                __builtin_amdgcn_wave_barrier();
+                bu_scan_long(p, wl, cur, fw, level, next_level, b, nlong, st);
+                nlong = 0;
             }
-            __builtin_amdgcn_wave_barrier();
         }
         __builtin_amdgcn_wave_barrier();
         if (l < 32) {
