@@ -350,27 +350,46 @@ struct BfsTopDown {
 
     // Claim unvisited targets: a plain load filters most arcs, the atomic OR
     // on the visited set decides the single winner, which writes the level
-    // and marks the next frontier.
+    // and marks the next frontier. All claims of a step are issued before
+    // any result is examined, so a step costs one atomic round trip however
+    // many of its arcs reach unvisited vertices.
     __device__ __forceinline__ void step(const bool* ok, const uint32_t*, const uint32_t* u, const uint32_t*,
                                          WaveLds&, Stats& st) {
-        uint32_t word[kUnroll];
+        uint32_t word[kUnroll], old[kUnroll];
 #pragma unroll
         for (uint32_t j = 0; j < kUnroll; ++j) word[j] = ok[j] ? vis[u[j] >> 5] : ~0u;
 #pragma unroll
         for (uint32_t j = 0; j < kUnroll; ++j) {
             const uint32_t bit = 1u << (u[j] & 31);
-            if (ok[j] && !(word[j] & bit)) {
-                const uint32_t old = __hip_atomic_fetch_or(&vis[u[j] >> 5], bit, __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT);
-                if (!(old & bit)) {
-                    __builtin_nontemporal_store(next_level, &level[u[j]]);
-                    __hip_atomic_fetch_or(&nxt[u[j] >> 5], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    st.found += 1;
-                    if (count_mf) {
-                        st.mf += row_ptr[u[j] + 1] - row_ptr[u[j]];
-                        st.rows += 1;
-                    }
+            old[j] = ~0u;
+            if (!(word[j] & bit))
+                old[j] = __hip_atomic_fetch_or(&vis[u[j] >> 5], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        bool won[kUnroll];
+#pragma unroll
+        for (uint32_t j = 0; j < kUnroll; ++j) {
+            const uint32_t bit = 1u << (u[j] & 31);
+            won[j] = !(old[j] & bit);
+            if (won[j]) {
+                __builtin_nontemporal_store(next_level, &level[u[j]]);
+                __hip_atomic_fetch_or(&nxt[u[j] >> 5], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                st.found += 1;
+            }
+        }
+        if (count_mf) {
+            uint32_t r0[kUnroll], r1[kUnroll];
+#pragma unroll
+            for (uint32_t j = 0; j < kUnroll; ++j) {
+                r0[j] = r1[j] = 0;
+                if (won[j]) {
+                    r0[j] = row_ptr[u[j]];
+                    r1[j] = row_ptr[u[j] + 1];
                 }
+            }
+#pragma unroll
+            for (uint32_t j = 0; j < kUnroll; ++j) {
+                st.mf += r1[j] - r0[j];
+                st.rows += won[j] ? 1u : 0u;
             }
         }
     }
@@ -701,6 +720,8 @@ __device__ __forceinline__ void bfs_follow(uint32_t ph, uint32_t nflags, uint32_
 
 // ----------------------------------------------------------------- SSSP
 
+constexpr uint32_t kRelaxBatch = 8;        // SSSP relaxations in flight per lane
+
 struct SsspVisit {
     uint64_t* state;        // {distance (hi) | tag (lo)}
     const uint32_t* w;
@@ -729,21 +750,35 @@ struct SsspVisit {
         for (uint32_t j = 0; j < kUnroll; ++j) wt[j] = ok[j] ? __builtin_nontemporal_load(&w[arc[j]]) : 0u;
 #pragma unroll
         for (uint32_t j = 0; j < kUnroll; ++j) du[j] = ok[j] ? (uint32_t)(state[u[j]] >> 32) : 0u;
-        bool win[kUnroll];
+        // which arcs lower their target: decided for the whole step first,
+        // so the relaxations below are issued back to back and their round
+        // trips overlap
+        uint32_t nd[kUnroll];
+        bool tr[kUnroll], ovf = false;
 #pragma unroll
         for (uint32_t j = 0; j < kUnroll; ++j) {
-            win[j] = false;
-            if (!ok[j]) continue;
             const uint64_t nd64 = (uint64_t)pay[j] + (uint64_t)wt[j];
-            if (nd64 >= 0x7FFFFFFFull) {
-                if (pay[j] != 0x7FFFFFFFu) raise_error(ctx, kErrOverflow);
-                continue;
+            const bool big = nd64 >= 0x7FFFFFFFull;
+            ovf |= ok[j] && big && pay[j] != 0x7FFFFFFFu;
+            nd[j] = (uint32_t)nd64;
+            tr[j] = ok[j] && !big && nd[j] < du[j];
+        }
+        if (ovf) raise_error(ctx, kErrOverflow);
+        bool win[kUnroll];
+#pragma unroll
+        for (uint32_t h = 0; h < kUnroll; h += kRelaxBatch) {
+            uint64_t old[kRelaxBatch];     // read only where tr[] is set
+#pragma unroll
+            for (uint32_t q = 0; q < kRelaxBatch; ++q) {
+                const uint32_t j = h + q;
+                if (tr[j])
+                    old[q] = __hip_atomic_fetch_min(&state[u[j]], ((uint64_t)nd[j] << 32) | tag,
+                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            const uint32_t nd = (uint32_t)nd64;
-            if (nd < du[j]) {
-                const uint64_t old = __hip_atomic_fetch_min(&state[u[j]], ((uint64_t)nd << 32) | tag,
-                                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                win[j] = nd < (uint32_t)(old >> 32) && (uint32_t)old != tag;
+#pragma unroll
+            for (uint32_t q = 0; q < kRelaxBatch; ++q) {
+                const uint32_t j = h + q;
+                win[j] = tr[j] && nd[j] < (uint32_t)(old[q] >> 32) && (uint32_t)old[q] != tag;
             }
         }
 #pragma unroll
