@@ -89,11 +89,15 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
     return x;
 }
 
-// Wave slot of this wave in the interval: units are dealt from the highest
-// logical id down, so a small frontier lands on the last workgroups and not
-// on workgroup 0 (which also relays the scheduler target every barrier).
+// Wave slot of this wave in the interval: units are dealt one per
+// workgroup before any workgroup gets a second, from the highest logical id
+// down. A small frontier (a few heavy strips, a thin SSSP wavefront) is then
+// spread over as many compute units (and XCDs) as it has units instead of
+// queueing on one compute unit's memory pipeline, and it avoids workgroup 0,
+// which also relays the scheduler target every barrier.
 __device__ __forceinline__ uint32_t wave_slot(uint32_t id, uint32_t M, uint32_t nw) {
-    return (M - 1 - id) * nw + wave_id();
+    (void)nw;
+    return wave_id() * M + (M - 1 - id);
 }
 
 // ----------------------------------------------------------- LDS layout
