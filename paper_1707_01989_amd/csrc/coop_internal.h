@@ -125,8 +125,9 @@ struct BfsArgs {
 
 struct SsspArgs {
     TraversalArgs t;
-    uint64_t* state;           // n words {distance:32 (hi) | round tag of the last queueing:32 (lo)}
-    int32_t* dist_out;         // nroots * out_stride (or n) distances
+    uint32_t* fb[3];           // rotating frontier bitmaps: current / next / being cleared
+    uint32_t words;            // bitmap words, multiple of 64
+    int32_t* dist_out;         // nroots * out_stride (or n) distances, also the working state
 };
 
 struct ColorArgs {

@@ -101,7 +101,6 @@ __device__ void sssp_body(const SsspArgs& p, bool joiner_grid) {
         if (Coop && m.alive && m.epoch == 0) startup_wait(c, t.cfg);
         const bool joined = m.alive && m.epoch != 0;
         sh.root = joined ? wk->x.root : 0u;
-        sh.aux = joined ? wk->x.round : 0u;
         for (uint32_t i = 0; i < num_waves(); ++i) sh.wave[i].out_n = 0;
         for (int i = 0; i < 8; ++i) sh.acc[i] = 0;
         sh.bar.member = m;
@@ -109,7 +108,7 @@ __device__ void sssp_body(const SsspArgs& p, bool joiner_grid) {
     }
     __syncthreads();
     Member m = sh.bar.member;
-    uint32_t root = sh.root, round = sh.aux;
+    uint32_t root = sh.root;
     bool fresh = m.epoch == 0;
 
     for (;;) {
@@ -120,12 +119,10 @@ __device__ void sssp_body(const SsspArgs& p, bool joiner_grid) {
                     sh.bar.member = join_queue(c, t.cfg);
                     sh.bar.killed = 0;
                     sh.root = wk->x.root;
-                    sh.aux = wk->x.round;
                 }
                 __syncthreads();
                 m = sh.bar.member;
                 root = sh.root;
-                round = sh.aux;
                 if (m.alive) continue;
             }
             return;
@@ -133,12 +130,14 @@ __device__ void sssp_body(const SsspArgs& p, bool joiner_grid) {
         const uint32_t ph = fresh ? kPhStart : (m.flags & kPhMask);
         fresh = false;
         wg_trace(t.cfg, m.epoch, m.id, kTrStart);
-        sssp_phase(p, sh, ph, m.flags, round, p.dist_out + (size_t)root * t.out_stride, m.id, m.M);
+        sssp_phase(p, sh, ph, m.flags, p.dist_out + (size_t)root * t.out_stride, m.id, m.M);
         wg_trace(t.cfg, m.epoch, m.id, kTrWorkDone);
         const uint32_t cur_flags = m.flags;
         barrier<Coop>(c, t.cfg, m, sh.bar,
-                      [&](uint32_t, uint32_t) -> uint32_t { return sssp_master(p, sh, c, ph, cur_flags, t.roots); });
-        sssp_follow(ph, m.flags, round, root);
+                      [&](uint32_t, uint32_t) -> uint32_t {
+                          return sssp_master(p, sh, c, ph, cur_flags, t.roots, p.dist_out);
+                      });
+        sssp_follow(ph, m.flags, root);
     }
 }
 

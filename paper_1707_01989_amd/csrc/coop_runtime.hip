@@ -608,13 +608,14 @@ int coop_sssp(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_
     coop_handle* h = nullptr;
     if ((rc = begin_launch(rt, opts, sz, COOP_KERNEL_SSSP, s, &h))) return rc;
     coop::SsspArgs& a = h->sssp;
-    if ((rc = fill_traversal(h, g, d_roots, nroots, out_stride, opts, &a.t, true, true))) {
+    if ((rc = fill_traversal(h, g, d_roots, nroots, out_stride, opts, &a.t, true, false))) {
         handle_free(h);
         return rc;
     }
-    a.state = static_cast<uint64_t*>(scratch(h, (size_t)g->n * 8));
+    a.words = g->words;
+    for (int i = 0; i < 3; ++i) a.fb[i] = static_cast<uint32_t*>(scratch(h, (size_t)a.words * 4));
     a.dist_out = d_dist;
-    if (!a.state) { handle_free(h); return COOP_E_OOM; }
+    if (!a.fb[0] || !a.fb[1] || !a.fb[2]) { handle_free(h); return COOP_E_OOM; }
     (void)hipEventRecord(h->ev_init, s);
     (void)hipEventRecord(h->ev_start, s);
     return finish_launch(rt, h, relaunch(h, false, h->grid, s), out);
@@ -1292,11 +1293,11 @@ int coop_server_create(coop_rt* rt, const coop_graph* const* graphs, uint32_t ng
         words_max = std::max(words_max, g->words);
         heavy_max = std::max(heavy_max, const_cast<coop_graph*>(g)->heavy_strips(heavy_th, strip));
     }
-    // slot state: SSSP {distance, tag} words and two queues, or the BFS
-    // bitmaps (smaller), plus the heavy-strip list and statistics slots
+    // slot state: the BFS visited and frontier bitmaps (SSSP uses the three
+    // frontier bitmaps; its distances live in the query's output), plus the
+    // heavy-strip list and statistics slots
     const size_t bfs_b = 4 * align_up((size_t)words_max * 4);
-    const size_t sssp_b = align_up((size_t)n_max * 8) + 2 * align_up((size_t)n_max * 4 + 4);
-    const size_t state_b = std::max(bfs_b, sssp_b) + align_up(heavy_max * 16);
+    const size_t state_b = bfs_b + align_up(heavy_max * 16);
 
     coop_launch_opts o;
     coop_launch_opts_default(&o);
@@ -1380,7 +1381,7 @@ int coop_server_create(coop_rt* rt, const coop_graph* const* graphs, uint32_t ng
         char* sb = slot_base + (size_t)s * (stats_b + state_b);
         uint32_t* stats = reinterpret_cast<uint32_t*>(sb);
         char* st = sb + stats_b;
-        uint4* heavy = heavy_max ? reinterpret_cast<uint4*>(st + std::max(bfs_b, sssp_b)) : nullptr;
+        uint4* heavy = heavy_max ? reinterpret_cast<uint4*>(st + bfs_b) : nullptr;
         for (uint32_t gi = 0; gi < ngraphs; ++gi) {
             const coop_graph* g = sv->graphs[gi];
             coop::ServeDesc& D = desc[(size_t)s * ngraphs + gi];
@@ -1413,10 +1414,8 @@ int coop_server_create(coop_rt* rt, const coop_graph* const* graphs, uint32_t ng
             D.bfs.beta = 24;
             D.bfs.total_arcs = g->arcs;
             D.sssp.t = t;
-            const size_t qb = align_up((size_t)n_max * 4 + 4);
-            D.sssp.state = reinterpret_cast<uint64_t*>(st);
-            D.sssp.t.frontier[0] = reinterpret_cast<uint32_t*>(st + align_up((size_t)n_max * 8));
-            D.sssp.t.frontier[1] = reinterpret_cast<uint32_t*>(st + align_up((size_t)n_max * 8) + qb);
+            for (int k = 0; k < 3; ++k) D.sssp.fb[k] = D.bfs.fb[k];
+            D.sssp.words = g->words;
             D.sssp.dist_out = nullptr;
         }
     }

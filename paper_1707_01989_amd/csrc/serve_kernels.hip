@@ -100,9 +100,9 @@ __device__ void serve_barrier(const ServeArgs& a, CtxCore* c, const Cfg tcfg, Me
     m = b.member;
 }
 
-// Query start (thread 0): the slot's current epoch, the SSSP round counter,
-// this member's XCD (for the team's master), and (rank 0) the transmit
-// block's source index reset for this query.
+// Query start (thread 0): the slot's current epoch, this member's shader
+// engine (for the team's master), and (rank 0) the transmit block's source
+// index reset for this query.
 __device__ __forceinline__ void query_start(BlockLds& sh, CtxCore* c, Work* wk, uint32_t* slots, uint32_t rank,
                                             uint32_t ses) {
     if (threadIdx.x == 0) {
@@ -110,7 +110,6 @@ __device__ __forceinline__ void query_start(BlockLds& sh, CtxCore* c, Work* wk, 
         const uint64_t r = ld_relaxed64(&c->release);
         fence_acquire();
         sh.level = rel_epoch(r);
-        sh.aux = ld_relaxed(&wk->x.round);
         if (rank == 0) st_relaxed(&wk->x.root, 0u);
     }
     __syncthreads();
@@ -140,24 +139,25 @@ __device__ __forceinline__ uint32_t serve_bfs(const ServeArgs& a, const BfsArgs&
     }
 }
 
-// An SSSP query (frontier Bellman-Ford); distances go to `out`.
+// An SSSP query (frontier Bellman-Ford); distances go to `out`, which is
+// also the query's working state.
 template <bool Coop>
 __device__ __forceinline__ uint32_t serve_sssp(const ServeArgs& a, const SsspArgs& p, BlockLds& sh, uint32_t rank,
                                            uint32_t team, const uint32_t* roots, int32_t* out) {
     CtxCore* c = p.t.ctx;
     query_start(sh, c, p.t.work, p.t.slots, rank, p.t.cfg.ses);
     Member m{rank, team, sh.level, 0u, 1u};
-    uint32_t round = sh.aux, root = 0, ph = kPhInit;
+    uint32_t root = 0, ph = kPhInit;
     for (;;) {
-        sssp_phase(p, sh, ph, m.flags, round, out, m.id, m.M);
+        sssp_phase(p, sh, ph, m.flags, out, m.id, m.M);
         const uint32_t cur_flags = m.flags, cur_ph = ph;
         serve_barrier<Coop>(a, c, p.t.cfg, m, sh.bar, p.t.slots, [&](uint32_t, uint32_t) -> uint32_t {
-            uint32_t f = sssp_master(p, sh, c, cur_ph, cur_flags, roots);
+            uint32_t f = sssp_master(p, sh, c, cur_ph, cur_flags, roots, out);
             return (f & kFlagDone) ? ((f & ~kFlagDone) | kFlagEnd) : f;
         });
         if (!m.alive) return 0;
         if (m.flags & kFlagEnd) return m.M;
-        sssp_follow(ph, m.flags, round, root);
+        sssp_follow(ph, m.flags, root);
         ph = m.flags & kPhMask;
     }
 }

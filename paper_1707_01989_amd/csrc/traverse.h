@@ -553,25 +553,43 @@ __device__ void bfs_bottom_up(const BfsArgs& p, WaveLds& wl, const uint32_t* cur
     }
 }
 
-// Top-down level over a frontier bitmap: each wave takes blocks of 64 words
-// (2048 vertices); every round it takes the lowest remaining vertex of each
-// lane's word, so a batch holds up to 64 frontier vertices.
+// Top-down step over a frontier bitmap. A unit is one bitmap word (32
+// vertices) and unit u belongs to wave slot u mod W, so a frontier that
+// fills a few hundred adjacent words still spreads over as many waves (and
+// workgroups). A wave gathers up to 32 of its words at a time (lane j loads
+// word gw + (k + j) W), compacts their set bits into its LDS list and
+// expands them 64 vertices per batch.
+template <class Visit>
+__device__ void expand_bitmap(const TraversalArgs& a, Work* wk, WaveLds& w, const uint32_t* cur, uint32_t words,
+                              uint32_t gw, uint32_t W, Visit& vis, Stats& st) {
+    const uint32_t l = lane_id();
+    uint32_t* list = w.out;             // up to 32 x 32 = 1024 vertices
+    for (uint32_t k = 0; gw + k * W < words; k += 32) {
+        const uint32_t wi = gw + (k + (l & 31)) * W;
+        uint32_t word = (l < 32 && wi < words) ? cur[wi] : 0u;
+        st.words += (l < 32 && wi < words) ? 1u : 0u;
+        const uint32_t cnt = __popc(word);
+        const uint32_t incl = wave_incl_scan(cnt);
+        const uint32_t total = bcast(incl, kWave - 1);
+        if (total == 0) continue;
+        uint32_t pos = incl - cnt;
+        while (word) {
+            list[pos++] = wi * 32u + (uint32_t)(__ffs(word) - 1);
+            word &= word - 1;
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t base = 0; base < total; base += kWave) {
+            const uint32_t i = base + l;
+            const bool act = i < total;
+            expand_batch(a, wk, w, act, act ? list[i] : 0u, vis, st);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 __device__ void bfs_top_down(const BfsArgs& p, Work* wk, WaveLds& w, const uint32_t* cur, BfsTopDown& vis,
                              uint32_t gw, uint32_t W, Stats& st) {
-    const uint32_t blocks = p.words / kWave;
-    for (uint32_t b = gw; b < blocks; b += W) {
-        uint32_t word = cur[b * kWave + lane_id()];
-        st.words += lane_id() == 0 ? kWave : 0u;
-        while (__ballot(word != 0)) {
-            const bool act = word != 0;
-            uint32_t v = 0;
-            if (act) {
-                v = (b * kWave + lane_id()) * 32u + (uint32_t)(__ffs(word) - 1);
-                word &= word - 1;
-            }
-            expand_batch(p.t, wk, w, act, v, vis, st);
-        }
-    }
+    expand_bitmap(p.t, wk, w, cur, p.words, gw, W, vis, st);
 }
 
 // Clear a bitmap share: words gw*64 + lane, then + W*64 ...
@@ -726,37 +744,36 @@ __device__ __forceinline__ void bfs_follow(uint32_t ph, uint32_t nflags, uint32_
 
 constexpr uint32_t kRelaxBatch = 8;        // SSSP relaxations in flight per lane
 
+// Frontier Bellman-Ford on the BFS engine's frontier bitmaps. The distances
+// live in the output array itself (INT32_MAX = unreached); a round expands
+// the vertices of the current bitmap and a relaxation that lowers dist[u]
+// sets u in the next bitmap, so no queue, no reservation and no per-vertex
+// round stamp are needed (setting a bit twice is harmless).
 struct SsspVisit {
-    uint64_t* state;        // {distance (hi) | tag (lo)}
+    uint32_t* dist;         // distances of the current source
     const uint32_t* w;
-    uint32_t tag;           // tag meaning "queued for the next round"
+    uint32_t* nxt;          // frontier bitmap of the next round
     CtxCore* ctx;
-    uint32_t* out_tail;
-    uint32_t* out;
 
-    __device__ __forceinline__ uint32_t payload(uint32_t v) const {
-        return (uint32_t)(ld_relaxed64(&state[v]) >> 32);
-    }
+    // a value read while other workgroups lower it can only be too large:
+    // the relaxation is then weaker, and the vertex is in the next round's
+    // bitmap anyway (whoever lowered it set its bit)
+    __device__ __forceinline__ uint32_t payload(uint32_t v) const { return dist[v]; }
     __device__ __forceinline__ uint32_t strip_payload(uint32_t, uint32_t v) const { return payload(v); }
-    __device__ __forceinline__ void maybe_flush(WaveLds& wl) {
-        if (wl.out_n > kFlushAt) wave_flush(wl, out_tail, out);
-    }
+    __device__ __forceinline__ void maybe_flush(WaveLds&) {}
 
-    // Frontier Bellman-Ford relaxation. One 64-bit atomicMin on {distance,
-    // tag} lowers the distance and, through the old tag it returns, tells
-    // whether the vertex is already queued for the next round (tags only
-    // grow, so an equal distance never changes the word).
+    // The arcs that would lower their target (by a plain probe) are decided
+    // for the whole step first, so the atomic minimums are issued back to
+    // back and their round trips overlap; the ones that lowered the value
+    // mark the target in the next bitmap (fire-and-forget OR).
     __device__ __forceinline__ void step(const bool* ok, const uint32_t* arc, const uint32_t* u,
-                                         const uint32_t* pay, WaveLds& wl, Stats& st) {
+                                         const uint32_t* pay, WaveLds&, Stats& st) {
         uint32_t wt[kUnroll];
         uint32_t du[kUnroll];
 #pragma unroll
         for (uint32_t j = 0; j < kUnroll; ++j) wt[j] = ok[j] ? __builtin_nontemporal_load(&w[arc[j]]) : 0u;
 #pragma unroll
-        for (uint32_t j = 0; j < kUnroll; ++j) du[j] = ok[j] ? (uint32_t)(state[u[j]] >> 32) : 0u;
-        // which arcs lower their target: decided for the whole step first,
-        // so the relaxations below are issued back to back and their round
-        // trips overlap
+        for (uint32_t j = 0; j < kUnroll; ++j) du[j] = ok[j] ? dist[u[j]] : 0u;
         uint32_t nd[kUnroll];
         bool tr[kUnroll], ovf = false;
 #pragma unroll
@@ -768,119 +785,107 @@ struct SsspVisit {
             tr[j] = ok[j] && !big && nd[j] < du[j];
         }
         if (ovf) raise_error(ctx, kErrOverflow);
-        bool win[kUnroll];
+        uint32_t old[kUnroll];              // read only where tr[] is set
 #pragma unroll
-        for (uint32_t h = 0; h < kUnroll; h += kRelaxBatch) {
-            uint64_t old[kRelaxBatch];     // read only where tr[] is set
-#pragma unroll
-            for (uint32_t q = 0; q < kRelaxBatch; ++q) {
-                const uint32_t j = h + q;
-                if (tr[j])
-                    old[q] = __hip_atomic_fetch_min(&state[u[j]], ((uint64_t)nd[j] << 32) | tag,
-                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-#pragma unroll
-            for (uint32_t q = 0; q < kRelaxBatch; ++q) {
-                const uint32_t j = h + q;
-                win[j] = tr[j] && nd[j] < (uint32_t)(old[q] >> 32) && (uint32_t)old[q] != tag;
-            }
-        }
+        for (uint32_t j = 0; j < kUnroll; ++j)
+            if (tr[j]) old[j] = __hip_atomic_fetch_min(&dist[u[j]], nd[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
         for (uint32_t j = 0; j < kUnroll; ++j) {
-            st.found += win[j] ? 1u : 0u;
-            wave_push(wl, win[j], u[j]);
+            if (tr[j] && nd[j] < old[j]) {
+                __hip_atomic_fetch_or(&nxt[u[j] >> 5], 1u << (u[j] & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                st.found += 1;
+            }
         }
     }
 };
 
-// One SSSP phase for member `id` of `M` (queue engine): INIT resets the
-// {distance, tag} words, TD relaxes the arcs of the input queue (64-entry
-// units distributed statically), HEAVY walks strips of heavy vertices, OUT
-// copies the distances to `dist`. `round` tags this round's queue entries.
+// One SSSP phase for member `id` of `M`: INIT sets the source's distances
+// to unreached and clears the bitmaps, TD relaxes the arcs of the vertices
+// in the current bitmap (one-word units) and clears the bitmap two rounds
+// ahead, HEAVY walks strips of heavy vertices. A workgroup that lowered any
+// distance raises the round's "next bitmap not empty" word.
 __device__ __forceinline__ void sssp_phase(const SsspArgs& p, BlockLds& sh, uint32_t ph, uint32_t flags,
-                                           uint32_t round, int32_t* dist, uint32_t id, uint32_t M) {
+                                           int32_t* dist_i, uint32_t id, uint32_t M) {
     const TraversalArgs& t = p.t;
     Work* wk = t.work;
     const uint32_t nw = num_waves();
-    const bool sel = (flags & kFlagSel) != 0;
-    uint32_t* in = t.frontier[sel ? 1 : 0];
-    uint32_t* out = t.frontier[sel ? 0 : 1];
+    uint32_t* dist = reinterpret_cast<uint32_t*>(dist_i);
+    const uint32_t rot = (flags & kRotMask) >> kRotShift;
+    uint32_t* cur = p.fb[rot];
+    uint32_t* nxt = p.fb[(rot + 1) % 3];
+    uint32_t* spare = p.fb[(rot + 2) % 3];
     const uint32_t gw = wave_slot(id, M, nw);
     const uint32_t W = M * nw;
     Stats st;
     if (ph == kPhInit) {
-        // distances to "unreached"; tags to 0 (no round uses tag 0)
         const uint32_t tid = id * blockDim.x + threadIdx.x, stride = M * blockDim.x;
-        for (uint32_t i = tid; i < t.n; i += stride) p.state[i] = 0x7FFFFFFFull << 32;
-    } else if (ph == kPhOut) {
-        const uint32_t tid = id * blockDim.x + threadIdx.x, stride = M * blockDim.x;
-        for (uint32_t i = tid; i < t.n; i += stride)
-            __builtin_nontemporal_store((int32_t)(p.state[i] >> 32), &dist[i]);
+        for (uint32_t i = tid; i < t.n; i += stride) dist[i] = 0x7FFFFFFFu;
+        for (uint32_t i = tid; i < p.words; i += stride) {
+            p.fb[0][i] = 0;
+            p.fb[1][i] = 0;
+            p.fb[2][i] = 0;
+        }
     } else if (ph == kPhTD || ph == kPhHeavy) {
-        if (threadIdx.x == 0) sh.in_size = wk->x.in_size;
-        __syncthreads();
-        const uint32_t size = sh.in_size;
-        SsspVisit vis{p.state, t.w, round + 2, t.ctx, &wk->out_tail, out};
+        SsspVisit vis{dist, t.w, nxt, t.ctx};
         WaveLds& w = sh.wave[wave_id()];
         if (ph == kPhTD) {
-            const uint32_t units = (size + kWave - 1) / kWave;
-            for (uint32_t u = gw; u < units; u += W) {
-                const uint32_t i = u * kWave + lane_id();
-                const bool act = i < size;
-                expand_batch(t, wk, w, act, act ? in[i] : 0u, vis, st);
-            }
+            clear_share(spare, p.words, gw, W);
+            expand_bitmap(t, wk, w, cur, p.words, gw, W, vis, st);
         } else {
-            heavy_phase(t, size, gw, W, w, vis, st);
+            heavy_phase(t, wk->x.in_size, gw, W, w, vis, st);
         }
-        wg_flush(sh, &wk->out_tail, out);
         stats_to_lds(sh, st);
         __syncthreads();
+        if (threadIdx.x == 0 && sh.acc[0])
+            __hip_atomic_store(&wk->out_tail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         acc_to_slot(sh, t.slots, id, false);
     }
 }
 
 // SSSP master step: place the next source, switch a round to its HEAVY
-// phase, turn the output queue into the next round's input, or finish the
-// source (OUT) and go to the next. Returns the release flags.
+// phase, or end the round: the next bitmap becomes the current one, or, if
+// no distance was lowered, the source is finished and the next one starts.
+// `roots` / `dist_base`: the sources and the distances (the launch's, or a
+// served query's). Returns the release flags.
 __device__ __forceinline__ uint32_t sssp_master(const SsspArgs& p, BlockLds& sh, CtxCore* c, uint32_t ph,
-                                                uint32_t cur_flags, const uint32_t* roots) {
+                                                uint32_t cur_flags, const uint32_t* roots, int32_t* dist_base) {
     const TraversalArgs& t = p.t;
     Work* wk = t.work;
     if (threadIdx.x == 0) {
         XferR x = wk->load_x();                 // one batch of loads
         const uint32_t hs = ld_relaxed(&wk->heavy_tail);
-        const uint32_t ot = ld_relaxed(&wk->out_tail);
+        const uint32_t lowered = ld_relaxed(&wk->out_tail);
+        const uint32_t r = (cur_flags & kRotMask) >> kRotShift;
         uint32_t res;
-        const uint32_t flags = cur_flags & kFlagSel;
         if (ph == kPhStart) {
             x.root() = 0;
             res = kPhInit;
-        } else if (ph == kPhOut) {
-            x.root() += 1;
-            res = x.root() >= t.nroots ? kFlagDone : kPhInit;
         } else if (ph == kPhInit) {
-            const uint32_t r = roots[x.root()];
-            p.state[r] = (uint64_t)(x.round() + 1);      // distance 0, queued for this round
-            t.frontier[0][0] = r;
-            x.in_size() = 1;
+            const uint32_t src = roots[x.root()];
+            int32_t* d = dist_base + (size_t)x.root() * t.out_stride;
+            d[src] = 0;
+            p.fb[0][src >> 5] = 1u << (src & 31);
+            x.level() = 0;
             wk->out_tail = 0;
             wk->heavy_tail = 0;
-            res = kPhTD;               // input = buffer 0
+            res = kPhTD;                        // rotation 0: current = fb[0]
         } else if (ph == kPhTD && hs > 0) {
             if (hs > t.heavy_cap) raise_error(c, kErrInternal);
             x.in_size() = hs;
             wk->heavy_tail = 0;
             x.heavy_phases() += 1;
-            res = flags | kPhHeavy;
+            res = (cur_flags & kRotMask) | kPhHeavy;
         } else {
-            // round done: the output queue becomes the input
-            wk->out_tail = 0;
             if (hs) wk->heavy_tail = 0;
-            x.in_size() = ot;
+            if (lowered) wk->out_tail = 0;
             x.level() += 1;
-            x.round() += 1;
             x.levels_total() += 1;
-            res = ot == 0 ? (kPhOut | kFlagAdv) : ((flags ^ kFlagSel) | kPhTD | kFlagAdv);
+            if (!lowered) {
+                x.root() += 1;
+                res = x.root() >= t.nroots ? kFlagDone : (kPhInit | kFlagAdv);
+            } else {
+                res = kPhTD | kFlagAdv | (((r + 1) % 3) << kRotShift);
+            }
         }
         wk->store_x(x);
         sh.bar.flags = res;
@@ -889,10 +894,10 @@ __device__ __forceinline__ uint32_t sssp_master(const SsspArgs& p, BlockLds& sh,
     return sh.bar.flags;
 }
 
-// Follow the transmitted SSSP state locally after a barrier.
-__device__ __forceinline__ void sssp_follow(uint32_t ph, uint32_t nflags, uint32_t& round, uint32_t& root) {
-    if (nflags & kFlagAdv) round += 1;
-    if ((nflags & kPhMask) == kPhInit && ph == kPhOut) root += 1;
+// Follow the transmitted SSSP state locally after a barrier: the source
+// index advances when a new source starts.
+__device__ __forceinline__ void sssp_follow(uint32_t ph, uint32_t nflags, uint32_t& root) {
+    if ((nflags & kPhMask) == kPhInit && ph != kPhStart) root += 1;
 }
 
 // ----------------------------------------------- colouring and MIS (JP DAG)
