@@ -38,6 +38,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace coop {
 
@@ -50,6 +51,7 @@ constexpr uint32_t kMaxGroups = 2048;        // launch limit N
 constexpr uint32_t kFlagDone = 1u;          // kernel finished: everybody leaves
 constexpr uint32_t kFlagAbort = 2u;         // watchdog fired or error: leave
 constexpr uint32_t kFlagRenum = 4u;         // kills chose their victims: read the new id
+constexpr uint32_t kFlagFlat = 8u;          // next arrival per workgroup (joiners' XCDs not yet known)
 constexpr uint32_t kFlagUser0 = 16u;        // algorithm-specific bits start here
 
 // Cfg::mode bits
@@ -97,6 +99,9 @@ __device__ __forceinline__ uint32_t engine_id(uint32_t ses) {
     return xcc * ses + se;
 }
 constexpr uint32_t kMaxEngines = 64;
+constexpr uint32_t kMaxXcds = 16;
+
+__device__ __forceinline__ uint32_t xcc_id() { return __builtin_amdgcn_s_getreg((3u << 11) | (0u << 6) | 20u) & 0xFu; }
 
 // Per-workgroup phase trace points (debugging and tuning only).
 enum WgTracePoint : uint32_t { kTrStart = 0, kTrWorkDone = 1, kTrArrive = 2, kTrReleased = 3 };
@@ -108,7 +113,8 @@ __device__ __forceinline__ void wg_trace(const Cfg cfg, uint32_t epoch, uint32_t
 // Barrier state: the lines every barrier touches. A team of workgroups
 // inside a batched launch uses one of these on its own (no joiners).
 struct alignas(256) CtxCore {
-    // ---- line: barrier arrival counter (one atomic per workgroup per barrier)
+    // ---- line: barrier arrival counter (per workgroup, or per group of
+    //      workgroups in a resizable launch)
     uint32_t arrive;
     uint32_t _pa[63];
     // ---- line: release word {epoch:32 (lo) | M:16 | flags:16 (hi)}
@@ -142,11 +148,37 @@ struct alignas(256) CtxCore {
 // (entries {slot:32 (lo) | epoch_lo:16 | id:16 (hi)}), the shader engine of
 // every logical id, and the new ids of a barrier that chose its kill victims
 // ({epoch_lo:16 (hi) | new id:16 (lo)}, new id 0xFFFF = killed).
+// Arrival by XCD. An agent-scope release on gfx950 writes back the XCD's
+// whole L2 and an acquire invalidates it; with every workgroup doing both
+// on one counter the arrival took about 6 us for 256 workgroups. Instead a
+// workgroup waits for its own memory operations (they then sit in its XCD's
+// L2), adds to its XCD's counter without a fence, and only the last of each
+// XCD releases (one L2 write-back per XCD) on the top counter; the last of
+// those is the master. The master keeps the per-XCD member counts of the
+// next interval (from engine_of) and sets kFlagFlat for an interval whose
+// joiners have not recorded their XCD yet; that interval arrives per
+// workgroup with release-acquire as before.
+struct alignas(256) ArriveLine {
+    uint32_t count;
+    uint32_t _p[63];
+};
+struct alignas(256) XcdCounts {
+    uint32_t members[kMaxXcds];   // members of this interval per XCD
+    uint32_t groups;              // XCDs with members
+    uint32_t _p[64 - kMaxXcds - 1];
+};
+
 struct alignas(256) Ctx : CtxCore {
     uint64_t join_entry[kJoinCap];
     uint32_t engine_of[kMaxGroups];
     uint32_t renum[kMaxGroups];
+    ArriveLine xcd_arrive[kMaxXcds];
+    XcdCounts xcd;
 };
+
+// Launch contexts (not the small per-team ones) arrive by XCD.
+template <class C>
+constexpr bool kGroupedArrival = std::is_same<C, Ctx>::value;
 
 // ------------------------------------------------------------- atomics
 
@@ -218,6 +250,7 @@ struct BarrierLds {
     uint32_t xcnt[kMaxEngines];        // placed kill: members per engine, then victims per engine
     uint32_t wsum[kMaxWaves + 1];      // placed kill: survivors per wave of ids
     uint8_t xcd[kMaxGroups];           // placed kill: shader engine of every logical id
+    uint8_t renum_alive[kMaxGroups];   // placed kill: 1 if the id survives
 };
 
 // Raise the abort flag so every spinning workgroup leaves.
@@ -320,6 +353,7 @@ __device__ inline Member register_member(Ctx* c, const Cfg cfg, bool plain, bool
         m.id = blockIdx.x;
         m.M = gridDim.x;
         m.alive = 1;
+        st_relaxed(&c->engine_of[m.id], engine_id(cfg.ses));
         return m;
     }
     if (!joiner_grid) {
@@ -481,6 +515,7 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
                     __hip_atomic_store(&c->renum[t], ((ne & 0xFFFFu) << 16) | (alive ? nid : 0xFFFFu),
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if (alive) st_relaxed(&c->engine_of[nid], b.xcd[t]);
+                    b.renum_alive[t] = alive ? 1u : 0u;
                 }
                 if (t == m.id) b.my_new = alive ? nid : 0xFFFFu;
                 for (uint32_t w = 0; w < blockDim.x / 64; ++w) carry += b.wsum[w];
@@ -491,9 +526,41 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
             __syncthreads();
         }
     }
+    // members per XCD for the next interval's arrival (launch contexts):
+    // recounted when the membership changed or the interval just ending
+    // could not arrive by XCD; joiners admitted now have not recorded their
+    // XCD yet, so the next interval arrives per workgroup (kFlagFlat)
+    if constexpr (kGroupedArrival<C>) {
+        const bool over = (b.flags & (kFlagDone | kFlagAbort)) != 0;
+        const uint32_t M2 = m.M + admitted;
+        const uint32_t Mn = renum ? Mn_sel : M2 - W;
+        if (!over && admitted == 0 && (m.epoch == 0 || (m.flags & kFlagFlat) || Mn != m.M || renum)) {
+            if (threadIdx.x < kMaxXcds) b.xcnt[threadIdx.x] = 0;
+            __syncthreads();
+            if (renum) {
+                // survivors' XCDs are in LDS (the new table is being written)
+                for (uint32_t t = threadIdx.x; t < M2; t += blockDim.x)
+                    if (t == 0 || b.renum_alive[t]) atomicAdd(&b.xcnt[(b.xcd[t] / cfg.ses) % kMaxXcds], 1u);
+            } else {
+                for (uint32_t t = threadIdx.x; t < Mn; t += blockDim.x)
+                    atomicAdd(&b.xcnt[(ld_relaxed(&c->engine_of[t]) / cfg.ses) % kMaxXcds], 1u);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                Ctx* cx = reinterpret_cast<Ctx*>(c);
+                uint32_t groups = 0;
+                for (uint32_t x = 0; x < kMaxXcds; ++x) {
+                    cx->xcd.members[x] = b.xcnt[x];
+                    groups += b.xcnt[x] ? 1u : 0u;
+                }
+                cx->xcd.groups = groups;
+            }
+        }
+    }
     if (threadIdx.x == 0) {
         flags = b.flags;
         uint32_t Mn = m.M;
+        if (kGroupedArrival<C> && !(flags & (kFlagDone | kFlagAbort)) && admitted) flags |= kFlagFlat;
         if (Coop && !(flags & (kFlagDone | kFlagAbort))) {
             const uint32_t M2 = m.M + admitted;
             const uint32_t Wk = renum ? M2 - Mn_sel : W;
@@ -542,6 +609,10 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
 // arrives.
 template <bool Coop, class C, class MasterFn>
 __device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, MasterFn&& master_fn) {
+    // by XCD: every wave's memory operations must have reached the L2 that
+    // its XCD's last arriver writes back
+    const bool by_xcd = kGroupedArrival<C> && m.epoch != 0 && !(m.flags & kFlagFlat);
+    if (by_xcd) __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     wg_trace(cfg, m.epoch, m.id, kTrArrive);
     if (threadIdx.x == 0) {
@@ -550,9 +621,27 @@ __device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, Ma
         if (Coop && cfg.host && m.id == 0)
             __hip_atomic_store(&c->T_seen, m.epoch == 0 ? ld_system(&cfg.host->target) : b.T_pre,
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t old = __hip_atomic_fetch_add(&c->arrive, 1u, __ATOMIC_ACQ_REL,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-        b.is_master = (old + 1 == m.M) ? 1u : 0u;
+        uint32_t last = 0;
+        if (by_xcd) {
+            Ctx* cx = reinterpret_cast<Ctx*>(c);
+            const uint32_t x = xcc_id();
+            const uint32_t members = ld_relaxed(&cx->xcd.members[x]);
+            const uint32_t groups = ld_relaxed(&cx->xcd.groups);
+            __builtin_amdgcn_s_waitcnt(0);       // our T_seen store is in the L2 too
+            const uint32_t o = __hip_atomic_fetch_add(&cx->xcd_arrive[x].count, 1u, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+            if (o + 1 == members) {
+                // last of this XCD: reset its counter, write back its L2
+                // and arrive for the XCD
+                __hip_atomic_store(&cx->xcd_arrive[x].count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t o2 = __hip_atomic_fetch_add(&c->arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                last = (o2 + 1 == groups) ? 1u : 0u;
+            }
+        } else {
+            const uint32_t old = __hip_atomic_fetch_add(&c->arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            last = (old + 1 == m.M) ? 1u : 0u;
+        }
+        b.is_master = last;
         if (b.is_master) __hip_atomic_store(&c->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();

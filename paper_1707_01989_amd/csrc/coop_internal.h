@@ -128,6 +128,7 @@ struct SsspArgs {
     uint32_t* fb[3];           // rotating frontier bitmaps: current / next / being cleared
     uint32_t words;            // bitmap words, multiple of 64
     int32_t* dist_out;         // nroots * out_stride (or n) distances, also the working state
+    uint32_t* lowered;         // kMaxXcds flags 64 words apart: a workgroup on that XCD lowered a distance
 };
 
 struct ColorArgs {

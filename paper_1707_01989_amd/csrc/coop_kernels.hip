@@ -230,6 +230,11 @@ __global__ void init_ctx_kernel(Ctx* c, Work* w) {
     const uint32_t head_words = sizeof(CtxCore) / 4;
     for (uint32_t i = tid; i < head_words; i += blockDim.x) cw[i] = 0;
     for (uint32_t i = tid; i < kJoinCap; i += blockDim.x) c->join_entry[i] = ~0ull;
+    for (uint32_t i = tid; i < kMaxXcds; i += blockDim.x) {
+        c->xcd_arrive[i].count = 0;
+        c->xcd.members[i] = 0;
+    }
+    if (tid == 0) c->xcd.groups = 0;
     uint32_t* ww = reinterpret_cast<uint32_t*>(w);
     for (uint32_t i = tid; i < sizeof(Work) / 4; i += blockDim.x) ww[i] = 0;
     __syncthreads();

@@ -614,8 +614,9 @@ int coop_sssp(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_
     }
     a.words = g->words;
     for (int i = 0; i < 3; ++i) a.fb[i] = static_cast<uint32_t*>(scratch(h, (size_t)a.words * 4));
+    a.lowered = static_cast<uint32_t*>(scratch(h, (size_t)coop::kMaxXcds * 256));
     a.dist_out = d_dist;
-    if (!a.fb[0] || !a.fb[1] || !a.fb[2]) { handle_free(h); return COOP_E_OOM; }
+    if (!a.fb[0] || !a.fb[1] || !a.fb[2] || !a.lowered) { handle_free(h); return COOP_E_OOM; }
     (void)hipEventRecord(h->ev_init, s);
     (void)hipEventRecord(h->ev_start, s);
     return finish_launch(rt, h, relaunch(h, false, h->grid, s), out);
@@ -1294,9 +1295,9 @@ int coop_server_create(coop_rt* rt, const coop_graph* const* graphs, uint32_t ng
         heavy_max = std::max(heavy_max, const_cast<coop_graph*>(g)->heavy_strips(heavy_th, strip));
     }
     // slot state: the BFS visited and frontier bitmaps (SSSP uses the three
-    // frontier bitmaps; its distances live in the query's output), plus the
-    // heavy-strip list and statistics slots
-    const size_t bfs_b = 4 * align_up((size_t)words_max * 4);
+    // frontier bitmaps; its distances live in the query's output), the SSSP
+    // per-XCD round flags, the heavy-strip list and statistics slots
+    const size_t bfs_b = 4 * align_up((size_t)words_max * 4) + (size_t)coop::kMaxXcds * 256;
     const size_t state_b = bfs_b + align_up(heavy_max * 16);
 
     coop_launch_opts o;
@@ -1415,6 +1416,7 @@ int coop_server_create(coop_rt* rt, const coop_graph* const* graphs, uint32_t ng
             D.bfs.total_arcs = g->arcs;
             D.sssp.t = t;
             for (int k = 0; k < 3; ++k) D.sssp.fb[k] = D.bfs.fb[k];
+            D.sssp.lowered = reinterpret_cast<uint32_t*>(st + 4 * wb);
             D.sssp.words = g->words;
             D.sssp.dist_out = nullptr;
         }

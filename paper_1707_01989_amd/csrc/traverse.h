@@ -836,8 +836,10 @@ __device__ __forceinline__ void sssp_phase(const SsspArgs& p, BlockLds& sh, uint
         }
         stats_to_lds(sh, st);
         __syncthreads();
+        // one flag per XCD: a single shared word took every workgroup's
+        // store in turn at the end of the round
         if (threadIdx.x == 0 && sh.acc[0])
-            __hip_atomic_store(&wk->out_tail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&p.lowered[xcc_id() * 64u], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         acc_to_slot(sh, t.slots, id, false);
     }
 }
@@ -854,7 +856,12 @@ __device__ __forceinline__ uint32_t sssp_master(const SsspArgs& p, BlockLds& sh,
     if (threadIdx.x == 0) {
         XferR x = wk->load_x();                 // one batch of loads
         const uint32_t hs = ld_relaxed(&wk->heavy_tail);
-        const uint32_t lowered = ld_relaxed(&wk->out_tail);
+        uint32_t lw[kMaxXcds];
+#pragma unroll
+        for (uint32_t i = 0; i < kMaxXcds; ++i) lw[i] = ld_relaxed(&p.lowered[i * 64u]);
+        uint32_t lowered = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < kMaxXcds; ++i) lowered |= lw[i];
         const uint32_t r = (cur_flags & kRotMask) >> kRotShift;
         uint32_t res;
         if (ph == kPhStart) {
@@ -866,7 +873,8 @@ __device__ __forceinline__ uint32_t sssp_master(const SsspArgs& p, BlockLds& sh,
             d[src] = 0;
             p.fb[0][src >> 5] = 1u << (src & 31);
             x.level() = 0;
-            wk->out_tail = 0;
+#pragma unroll
+            for (uint32_t i = 0; i < kMaxXcds; ++i) p.lowered[i * 64u] = 0;
             wk->heavy_tail = 0;
             res = kPhTD;                        // rotation 0: current = fb[0]
         } else if (ph == kPhTD && hs > 0) {
@@ -877,7 +885,9 @@ __device__ __forceinline__ uint32_t sssp_master(const SsspArgs& p, BlockLds& sh,
             res = (cur_flags & kRotMask) | kPhHeavy;
         } else {
             if (hs) wk->heavy_tail = 0;
-            if (lowered) wk->out_tail = 0;
+#pragma unroll
+            for (uint32_t i = 0; i < kMaxXcds; ++i)
+                if (lw[i]) p.lowered[i * 64u] = 0;
             x.level() += 1;
             x.levels_total() += 1;
             if (!lowered) {
