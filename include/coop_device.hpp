@@ -377,27 +377,54 @@ __device__ inline void startup_wait(Ctx* c, const Cfg cfg) {
         __builtin_amdgcn_s_sleep(2);
 }
 
+// Inputs of the scheduler part of the master step, loaded by thread 0 as
+// soon as its workgroup knows it is the master, so that their round trip
+// overlaps the algorithm's own master step. An error raised by another
+// workgroup after this load is caught at the next barrier (the error word
+// stays set); the algorithm's master step reports its own errors in the
+// flags it returns.
+struct MasterPre {
+    int32_t err;
+    uint32_t tail, T_seen, join_head, T_dev, nb, kills, forks, resizes, min_M, max_M;
+};
+
+template <bool Coop, class C>
+__device__ __forceinline__ MasterPre master_prefetch(C* c, const Cfg cfg) {
+    MasterPre p;
+    p.err = ld_relaxed_i(&c->error);
+    p.tail = Coop ? ld_relaxed(&c->join_tail) : 0u;
+    p.T_seen = (Coop && cfg.host) ? ld_relaxed(&c->T_seen) : 0u;
+    p.join_head = c->join_head;
+    p.T_dev = c->T_dev;
+    p.nb = c->barriers;
+    p.kills = c->kills;
+    p.forks = c->forks;
+    p.resizes = c->resizes;
+    p.min_M = c->min_M;
+    p.max_M = c->max_M;
+    return p;
+}
+
 // Scheduler part of the master step, run by every thread of the master
 // workgroup: fork (admit waiting joiners, in parallel), query (the target)
 // and kill (the top ids). Thread 0 then publishes the release word.
 template <bool Coop, class C>
 __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLds& b, uint32_t flags,
-                                       uint64_t t_in) {
+                                       uint64_t t_in, const MasterPre& pre) {
     const uint32_t ne = m.epoch + 1;
-    // one batch of independent loads
     uint32_t T_dev = 0, nb = 0, kills = 0, forks = 0, resizes = 0, min_M = 0, max_M = 0;
     if (threadIdx.x == 0) {
-        const int32_t err = ld_relaxed_i(&c->error);
-        const uint32_t tail = Coop ? ld_relaxed(&c->join_tail) : 0u;
-        const uint32_t T_seen = (Coop && cfg.host) ? ld_relaxed(&c->T_seen) : 0u;
-        const uint32_t join_head = c->join_head;
-        T_dev = c->T_dev;
-        nb = c->barriers;
-        kills = c->kills;
-        forks = c->forks;
-        resizes = c->resizes;
-        min_M = c->min_M;
-        max_M = c->max_M;
+        const int32_t err = pre.err;
+        const uint32_t tail = pre.tail;
+        const uint32_t T_seen = pre.T_seen;
+        const uint32_t join_head = pre.join_head;
+        T_dev = pre.T_dev;
+        nb = pre.nb;
+        kills = pre.kills;
+        forks = pre.forks;
+        resizes = pre.resizes;
+        min_M = pre.min_M;
+        max_M = pre.max_M;
         if (err) flags |= kFlagAbort;
         const bool live = Coop && !(flags & (kFlagDone | kFlagAbort));
         uint32_t T = cfg.N;
@@ -648,8 +675,10 @@ __device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, Ma
     if (b.is_master) {
         // master step: everybody else is parked in the barrier
         const uint64_t t_in = now_ticks();
+        MasterPre pre;                          // thread 0's
+        if (threadIdx.x == 0) pre = master_prefetch<Coop>(c, cfg);
         const uint32_t flags = master_fn(m.M, m.epoch + 1);
-        master_schedule<Coop, C>(c, cfg, m, b, flags, t_in);
+        master_schedule<Coop, C>(c, cfg, m, b, flags, t_in, pre);
     } else if (threadIdx.x == 0) {
         const uint64_t r = wait_release(c, cfg, m.epoch);
         fence_acquire();

@@ -655,11 +655,17 @@ __device__ __forceinline__ uint32_t bfs_master(const BfsArgs& p, BlockLds& sh, C
                                                uint32_t cur_flags, const uint32_t* roots, uint32_t* lvl_base) {
     const TraversalArgs& t = p.t;
     Work* wk = t.work;
+    // thread 0 loads the transmit block before the slot sums, so both round
+    // trips overlap (the values stay undefined in the other threads)
+    XferR x;
+    uint32_t hs;
+    if (threadIdx.x == 0) {
+        x = wk->load_x();
+        hs = ld_relaxed(&wk->heavy_tail);
+    }
     uint64_t tot[2];
     master_sum_slots(sh, t.slots, t.N, tot);
     if (threadIdx.x == 0) {
-        XferR x = wk->load_x();                 // one batch of loads
-        const uint32_t hs = ld_relaxed(&wk->heavy_tail);
         uint32_t res = 0;
         const uint32_t r = (cur_flags & kRotMask) >> kRotShift;
         if (ph == kPhStart) {
@@ -684,7 +690,6 @@ __device__ __forceinline__ uint32_t bfs_master(const BfsArgs& p, BlockLds& sh, C
             const uint64_t mf_lvl = join64(x.lvl_mf_lo(), x.lvl_mf_hi()) + tot[1];
             const uint32_t nf_lvl = x.lvl_found() + (uint32_t)tot[0];
             if (ph == kPhTD && hs > 0) {
-                if (hs > t.heavy_cap) raise_error(c, kErrInternal);
                 x.in_size() = hs;
                 wk->heavy_tail = 0;
                 x.lvl_found() = nf_lvl;
@@ -692,6 +697,10 @@ __device__ __forceinline__ uint32_t bfs_master(const BfsArgs& p, BlockLds& sh, C
                 x.lvl_mf_hi() = (uint32_t)(mf_lvl >> 32);
                 x.heavy_phases() += 1;
                 res = (cur_flags & kRotMask) | kPhHeavy;
+                if (hs > t.heavy_cap) {                 // the strip list overflowed
+                    raise_error(c, kErrInternal);
+                    res |= kFlagAbort;
+                }
             } else {
                 x.lvl_found() = 0;
                 x.lvl_mf_lo() = x.lvl_mf_hi() = 0;
@@ -878,11 +887,14 @@ __device__ __forceinline__ uint32_t sssp_master(const SsspArgs& p, BlockLds& sh,
             wk->heavy_tail = 0;
             res = kPhTD;                        // rotation 0: current = fb[0]
         } else if (ph == kPhTD && hs > 0) {
-            if (hs > t.heavy_cap) raise_error(c, kErrInternal);
             x.in_size() = hs;
             wk->heavy_tail = 0;
             x.heavy_phases() += 1;
             res = (cur_flags & kRotMask) | kPhHeavy;
+            if (hs > t.heavy_cap) {                     // the strip list overflowed
+                raise_error(c, kErrInternal);
+                res |= kFlagAbort;
+            }
         } else {
             if (hs) wk->heavy_tail = 0;
 #pragma unroll
