@@ -22,6 +22,9 @@ Printed JSON line (one):
   cotask         a co-task every 10 ms needing half the CUs for 1 ms while
                  a cooperative launch runs: p50/p99 latency, gather time,
                  slowdown of the traversal
+  gather_sweep   gather time against the workgroups a co-task claims (1, a
+                 quarter, half, all but one), query barrier vs the regular
+                 barrier that lets one workgroup go per barrier
   roofline       algorithmic bytes per launch / mean launch time (HIP events
                  on the launch stream) vs 8 TB/s; traffic from the committed
                  PMC summary when it was taken on the current kernel sources
@@ -80,6 +83,7 @@ def main():
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--roots-per-launch", type=int, default=8)
     ap.add_argument("--cotask-seconds", type=float, default=4.0)
+    ap.add_argument("--gather-seconds", type=float, default=0.5, help="per point of the gather-time sweep")
     ap.add_argument("--cpu-sample", type=int, default=32, help="sources for the oracle timing")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one int32 'x + 1' elementwise kernel over this many MiB (counter calibration)")
@@ -236,18 +240,22 @@ def main():
     if not args.skip_cotask:
         # co-task every 10 ms needing half the CUs for 1 ms during a long launch
         per_root_ms = ms_c / len(timed)
-        k = max(1, int(args.cotask_seconds * 1e3 / max(per_root_ms, 1e-3)))
-        k = min(k, 400000)
-        reps = np.resize(np.asarray(timed, dtype=np.uint32), k)
-        d_many = rt._roots(reps)
-        alone = run(coop_opts, d_many)
         cus = rt.info["compute_units"]
-        h = coop.coop_bfs(rt.rt, dg.handle, d_many, k, level, 0, coop_opts, stream)
-        coop.coop_injector_start(rt.rt, h, groups=cus // 2, busy_ns=1_000_000, period_ns=10_000_000)
-        rc, st_m = coop.coop_wait(h)
-        irc, cst = coop.coop_injector_stop(rt.rt)
-        if rc != 0 or irc != 0:
-            raise RuntimeError(f"co-task run failed: {coop.coop_strerror(rc)} / {coop.coop_strerror(irc)}")
+
+        def cotask_run(opts, groups, seconds):
+            k = max(1, int(seconds * 1e3 / max(per_root_ms, 1e-3)))
+            k = min(k, 400000)
+            d_many = rt._roots(np.resize(np.asarray(timed, dtype=np.uint32), k))
+            h = coop.coop_bfs(rt.rt, dg.handle, d_many, k, level, 0, opts, stream)
+            coop.coop_injector_start(rt.rt, h, groups=groups, busy_ns=1_000_000, period_ns=10_000_000)
+            rc, st = coop.coop_wait(h)
+            irc, cst = coop.coop_injector_stop(rt.rt)
+            if rc != 0 or irc != 0:
+                raise RuntimeError(f"co-task run failed: {coop.coop_strerror(rc)} / {coop.coop_strerror(irc)}")
+            return d_many, st, cst
+
+        d_many, st_m, cst = cotask_run(coop_opts, cus // 2, args.cotask_seconds)
+        alone = run(coop_opts, d_many)
         result["cotask"] = {
             "period_ms": 10, "busy_ms": 1, "groups": cus // 2, "count": cst["count"],
             "latency_p50_ms": round(cst["latency_p50_ms"], 4), "latency_p99_ms": round(cst["latency_p99_ms"], 4),
@@ -260,6 +268,24 @@ def main():
             "model_kernel_preemption": round(10 / 9, 4), "model_half_cu": round(10 / 9.5, 4),
         }
         log(f"cotask: {result['cotask']}")
+
+        # gather time against the number of workgroups the co-task claims,
+        # for the query barrier and the regular barrier (one kill per
+        # barrier), as in the paper's responsiveness experiment
+        regular_opts = coop.make_opts(coop.COOP_MODE_COOP,
+                                      flags=coop.COOP_F_HOST_SCHEDULE | coop.COOP_F_REGULAR_BARRIER)
+        sweep = []
+        for groups in (1, cus // 4, cus // 2, cus - 1):
+            for name, o in (("query", coop_opts), ("regular", regular_opts)):
+                _, st_g, c_g = cotask_run(o, groups, args.gather_seconds)
+                sweep.append({"groups": groups, "barrier": name, "count": c_g["count"],
+                              "gather_p50_ms": round(c_g["gather_p50_ms"], 4),
+                              "gather_p99_ms": round(c_g["gather_p99_ms"], 4),
+                              "latency_p50_ms": round(c_g["latency_p50_ms"], 4),
+                              "kills": st_g["kills"]})
+        result["gather_sweep"] = sweep
+        log("gather sweep: " + "; ".join(f"{e['barrier']} W={e['groups']}: {e['gather_p50_ms']}/{e['gather_p99_ms']} ms"
+                                         for e in sweep))
 
     # global-barrier latency (persistent launch doing barriers only)
     bar = {}

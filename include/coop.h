@@ -96,7 +96,10 @@ enum {
     COOP_F_PARK_KILLED = 1u,      /* killed workgroups queue again as joiners (test mode) */
     COOP_F_RANDOM_SCHEDULE = 2u,  /* seeded device-side kill/fork schedule */
     COOP_F_HOST_SCHEDULE = 4u,    /* barrier reads the host-written target (coop_set_target) */
-    COOP_F_TOP_DOWN_ONLY = 8u     /* BFS: never switch to bottom-up levels */
+    COOP_F_TOP_DOWN_ONLY = 8u,    /* BFS: never switch to bottom-up levels */
+    COOP_F_REGULAR_BARRIER = 16u  /* the paper's regular resizing barrier: at most one workgroup
+                                     (the top id) leaves per barrier, instead of the query
+                                     barrier's W at once (section 4.2); for gather-time comparisons */
 };
 
 typedef struct coop_launch_opts {
@@ -250,7 +253,10 @@ int coop_cotask_run(coop_rt* rt, const coop_cotask_cfg* cfg, coop_stream_t strea
 /* Start a host thread that, every period, asks the cooperative launch `h`
  * for cfg->groups workgroups (target = N - groups), runs the co-task on the
  * runtime's co-task stream, then restores the target and forks the
- * workgroups back. h may be NULL (co-tasks only). One injector per runtime. */
+ * workgroups back (groups + engines - 1 joiners: the engine-balanced kill
+ * can take up to engines - 1 more than asked; joiners beyond the target's
+ * room leave at once). h may be NULL (co-tasks only). One injector per
+ * runtime. */
 int coop_injector_start(coop_rt* rt, coop_handle* h, const coop_cotask_cfg* cfg);
 /* Stop the injector thread and return its statistics. */
 int coop_injector_stop(coop_rt* rt, coop_cotask_stats* out);

@@ -58,6 +58,7 @@ constexpr uint32_t kFlagUser0 = 16u;        // algorithm-specific bits start her
 constexpr uint32_t kModeCoop = 1u;          // cooperative (resizable) launch
 constexpr uint32_t kModePark = 2u;          // killed workgroups re-queue as joiners
 constexpr uint32_t kModeRandomSched = 4u;   // device-side seeded kill/fork schedule
+constexpr uint32_t kModeRegular = 8u;       // regular resizing barrier: at most one kill per barrier
 
 // error codes written to ctx->error (match COOP_E_* of coop.h)
 constexpr int32_t kErrTimeout = -4;
@@ -492,6 +493,9 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
             const uint32_t M2 = m.M + admitted;
             W = M2 > b.T ? M2 - b.T : 0u;
             if (W > M2 - 1) W = M2 - 1;
+            // the regular barrier (section 4.2): one offer_kill per arrival,
+            // which in the worst arrival order claims only the top id
+            if ((cfg.mode & kModeRegular) && W > 1) W = 1;
         }
     }
     // A host-driven target asks for compute units for another kernel, whose
@@ -511,13 +515,20 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
             __syncthreads();
             if (threadIdx.x == 0) {
                 const uint32_t need = (W + cfg.engines - 1) / cfg.engines;
+                uint32_t best = kMaxEngines, best_k = 0;
                 for (uint32_t x = 0; x < kMaxEngines; ++x) {
                     const uint32_t cnt = b.xcnt[x];
                     const uint32_t idle = x < cfg.engines && cfg.slots_per_engine > cnt ? cfg.slots_per_engine - cnt : 0u;
                     uint32_t k = need > idle ? need - idle : 0u;
                     const uint32_t cap = cnt - (x == b.xcd[0] ? 1u : 0u);     // workgroup 0 stays
                     b.xcnt[x] = k < cap ? k : cap;
+                    if (b.xcnt[x] > best_k) {
+                        best_k = b.xcnt[x];
+                        best = x;
+                    }
                 }
+                if (cfg.mode & kModeRegular)           // one victim: on the engine that owes most
+                    for (uint32_t x = 0; x < kMaxEngines; ++x) b.xcnt[x] = x == best ? 1u : 0u;
             }
             __syncthreads();
             // id t is a victim if fewer than xcnt[its XCD] higher ids share its XCD

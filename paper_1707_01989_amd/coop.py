@@ -31,6 +31,7 @@ COOP_F_PARK_KILLED = 1
 COOP_F_RANDOM_SCHEDULE = 2
 COOP_F_HOST_SCHEDULE = 4
 COOP_F_TOP_DOWN_ONLY = 8
+COOP_F_REGULAR_BARRIER = 16
 
 COOP_KERNEL_BFS = 1
 COOP_KERNEL_SSSP = 2

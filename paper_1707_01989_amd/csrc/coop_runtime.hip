@@ -267,6 +267,7 @@ int size_launch(coop_rt* rt, const coop_launch_opts* o, Sizing* s, uint32_t min_
         s->mode |= coop::kModeCoop;
         if (o->flags & COOP_F_PARK_KILLED) s->mode |= coop::kModePark;
         if (o->flags & COOP_F_RANDOM_SCHEDULE) s->mode |= coop::kModeRandomSched;
+        if (o->flags & COOP_F_REGULAR_BARRIER) s->mode |= coop::kModeRegular;
     }
     s->sched_p16 = (uint32_t)std::lround(std::min(1.0, std::max(0.0, o->sched_p)) * 65536.0);
     const uint64_t wd = o->watchdog_ns ? o->watchdog_ns : kDefaultWatchdogNs;
@@ -1670,7 +1671,13 @@ int coop_injector_start(coop_rt* rt, coop_handle* h, const coop_cotask_cfg* cfg)
             if (h && handle_done(h)) h = nullptr;
             double lat = 0, gat = 0, busy = 0, t_req = t, t_end = t;
             int rc = cotask_once(rt, &cfg, rt->cotask_stream, h, &lat, &gat, &busy, &t_req, &t_end);
-            if (rc == COOP_OK && h && !handle_done(h)) rc = coop_fork_groups(h, cfg.groups);
+            if (rc == COOP_OK && h && !handle_done(h)) {
+                // the engine-balanced kill may have taken up to engines - 1
+                // more than the co-task asked for; joiners beyond the room
+                // the target leaves give their compute unit back at once
+                const uint32_t extra = h->cfg.engines > 1 ? h->cfg.engines - 1 : 0u;
+                rc = coop_fork_groups(h, std::min<uint32_t>(cfg.groups + extra, h->grid));
+            }
             rt->inj_setup_max = std::max(rt->inj_setup_max, t_req - t);
             rt->inj_restore_max = std::max(rt->inj_restore_max, now_ms() - t_end);
             rt->inj_busy = 0;

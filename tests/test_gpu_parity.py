@@ -359,3 +359,35 @@ def test_cotask_injector_during_bfs(rt, coop_mod, gg):
     # no co-task waited for the whole traversal
     assert cst["latency_max_ms"] < 0.5 * st["kernel_ms"]
     dg.release()
+
+
+def test_regular_barrier_under_cotasks(rt, coop_mod, gg):
+    """The regular resizing barrier (one workgroup leaves per barrier) gives
+    the same levels under co-tasks; its gathers take more barriers than the
+    query barrier's."""
+    import torch
+    c = coop_mod
+    g = gg.rmat(18, 16, seed=3)
+    dg = rt.graph(g)
+    roots = np.resize(gg.sources(g, 3, 16), 300).astype(np.uint32)
+    d_roots = rt._roots(roots)
+    lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    cus = rt.info["compute_units"]
+    res = {}
+    for name, extra in (("query", 0), ("regular", c.COOP_F_REGULAR_BARRIER)):
+        o = c.make_opts(c.COOP_MODE_COOP, flags=c.COOP_F_HOST_SCHEDULE | extra)
+        say(f"bfs rmat18 x{len(roots)} under co-tasks, {name} barrier")
+        h = c.coop_bfs(rt.rt, dg.handle, d_roots, len(roots), lv, 0, o)
+        c.coop_injector_start(rt.rt, h, groups=cus // 4, busy_ns=300_000, period_ns=3_000_000)
+        rc, st = c.coop_wait(h)
+        irc, cst = c.coop_injector_stop(rt.rt)
+        assert rc == 0 and irc == 0, (c.coop_strerror(rc), c.coop_strerror(irc))
+        assert np.array_equal(as_u32(lv), oracle.bfs(g, int(roots[-1])))
+        say(f"  kernel {st['kernel_ms']:.1f} ms barriers={st['barriers']} kills={st['kills']} "
+            f"co-tasks={cst['count']} gather p50={cst['gather_p50_ms']:.3f} ms")
+        assert cst["count"] >= 1 and st["kills"] > 0
+        res[name] = st
+    # each co-task claims cus/4 workgroups: the regular barrier needs at
+    # least that many kill barriers per co-task, the query barrier one
+    assert res["regular"]["resizes"] >= res["query"]["resizes"]
+    dg.release()
