@@ -22,6 +22,9 @@ Printed JSON line (one):
   cotask         a co-task every 10 ms needing half the CUs for 1 ms while
                  a cooperative launch runs: p50/p99 latency, gather time,
                  slowdown of the traversal
+  shared         a long cooperative BFS and the SSSP grid launched together,
+                 the host sharer splitting the resident workgroups between
+                 them: each one's time alone and shared, wall time shared
   gather_sweep   gather time against the workgroups a co-task claims (1, a
                  quarter, half, all but one), query barrier vs the regular
                  barrier that lets one workgroup go per barrier
@@ -89,6 +92,7 @@ def main():
                     help="run one int32 'x + 1' elementwise kernel over this many MiB (counter calibration)")
     ap.add_argument("--skip-cotask", action="store_true")
     ap.add_argument("--skip-sssp", action="store_true")
+    ap.add_argument("--skip-share", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark measures one GPU; multi-GPU runs are not part of it",
@@ -235,7 +239,6 @@ def main():
                                 "same_as_never_resize": same},
         }
         log(f"sssp: {result['sssp']}")
-        del dgs
 
     if not args.skip_cotask:
         # co-task every 10 ms needing half the CUs for 1 ms during a long launch
@@ -286,6 +289,40 @@ def main():
         result["gather_sweep"] = sweep
         log("gather sweep: " + "; ".join(f"{e['barrier']} W={e['groups']}: {e['gather_p50_ms']}/{e['gather_p99_ms']} ms"
                                          for e in sweep))
+
+    if not args.skip_share and not args.skip_sssp:
+        # two cooperative launches at once: a long BFS (R-MAT, ~0.3 s) and the
+        # SSSP grid, equal weights; the sharer splits the resident workgroups
+        per_root_ms = ms_c / len(timed)
+        k = max(1, int(300.0 / max(per_root_ms, 1e-3)))
+        d_many = rt._roots(np.resize(np.asarray(timed, dtype=np.uint32), k))
+        st_a = run(coop_opts, d_many)
+        st_b = run_s(coop_opts)
+        s2 = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        coop.coop_share_start(rt.rt, 100)
+        try:
+            ha = coop.coop_bfs(rt.rt, dg.handle, d_many, k, level, 0, coop_opts, stream)
+            coop.coop_share_add(rt.rt, ha, 1)
+            hb = coop.coop_sssp(rt.rt, dgs.handle, d0, 1, dist, 0, coop_opts, s2)
+            coop.coop_share_add(rt.rt, hb, 1)
+            rcb, sh_b = coop.coop_wait(hb)
+            rca, sh_a = coop.coop_wait(ha)
+        finally:
+            rcs, sst = coop.coop_share_stop(rt.rt)
+        wall = (time.perf_counter() - t0) * 1e3
+        if rca or rcb or rcs:
+            raise RuntimeError(f"shared run failed: {rca} {rcb} {rcs}")
+        result["shared"] = {
+            "bfs_ms_alone": round(st_a["kernel_ms"], 2), "sssp_ms_alone": round(st_b["kernel_ms"], 2),
+            "bfs_ms_shared": round(sh_a["kernel_ms"], 2), "sssp_ms_shared": round(sh_b["kernel_ms"], 2),
+            "wall_ms_shared": round(wall, 2),
+            "sequential_ms": round(st_a["kernel_ms"] + st_b["kernel_ms"], 2),
+            "bfs_min_groups": sh_a["min_groups"], "sssp_max_groups": sh_b["max_groups"],
+            "target_updates": sst["target_updates"],
+        }
+        log(f"shared: {result['shared']}")
 
     # global-barrier latency (persistent launch doing barriers only)
     bar = {}

@@ -245,6 +245,30 @@ typedef struct coop_cotask_stats {
     uint32_t reserved;
 } coop_cotask_stats;
 
+/* Several cooperative launches at once (the paper's prototype ran one
+ * cooperative kernel at a time; its scheduler contexts were designed for
+ * several, section 4). coop_share_start starts a host thread that every
+ * period_us (0 = 200) gives each added launch its weighted share of the
+ * resident workgroups as its scheduler target (at least 1; the remainder
+ * goes to the oldest launch) and forks joiners for a launch whose share
+ * grew, e.g. when another one ended. A launch's workgroups that the
+ * hardware has not started yet start on the compute units the others free
+ * at their barriers. Launches must be cooperative with COOP_F_HOST_SCHEDULE;
+ * coop_wait detaches a launch. The sharer and the co-task injector exclude
+ * each other (COOP_E_BUSY). Errors: COOP_E_INVALID (bad handle or weight 0,
+ * launch added twice, sharer not running), COOP_E_BUSY; coop_share_stop
+ * returns the first error of a fork it issued. */
+typedef struct coop_share_stats {
+    uint32_t launches;        /* launches added since coop_share_start */
+    uint32_t target_updates;  /* target changes made */
+    uint32_t fork_calls;      /* joiner grids launched for grown shares */
+    uint32_t reserved;
+} coop_share_stats;
+
+int coop_share_start(coop_rt* rt, uint32_t period_us);
+int coop_share_add(coop_rt* rt, coop_handle* h, uint32_t weight);
+int coop_share_stop(coop_rt* rt, coop_share_stats* out);
+
 /* Run one co-task now on `stream` and wait for it (blocking). latency_ms /
  * gather_ms (nullable) get request->end and request->all-running times. */
 int coop_cotask_run(coop_rt* rt, const coop_cotask_cfg* cfg, coop_stream_t stream,

@@ -58,6 +58,7 @@ EXPORTS = [
     "coop_last_hip_error", "coop_graph_wrap", "coop_graph_release", "coop_bfs", "coop_sssp",
     "coop_color", "coop_mis", "coop_launch", "coop_wait", "coop_handle_groups", "coop_set_target",
     "coop_fork_groups", "coop_cotask_run", "coop_injector_start", "coop_injector_stop",
+    "coop_share_start", "coop_share_add", "coop_share_stop",
     "coop_barrier_bench", "coop_tune_default", "coop_batch_run", "coop_batch_autotune",
     "coop_server_cfg_default", "coop_server_create", "coop_server_submit", "coop_server_poll",
     "coop_server_wait", "coop_server_stats", "coop_server_handle", "coop_server_destroy",
@@ -122,6 +123,16 @@ class coop_cotask_cfg(ctypes.Structure):
         ("groups", ctypes.c_uint32), ("lds_bytes", ctypes.c_uint32), ("busy_ns", ctypes.c_uint64),
         ("period_ns", ctypes.c_uint64), ("max_tasks", ctypes.c_uint32),
     ]
+
+
+class coop_share_stats(ctypes.Structure):
+    _fields_ = [
+        ("launches", ctypes.c_uint32), ("target_updates", ctypes.c_uint32), ("fork_calls", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class coop_cotask_stats(ctypes.Structure):
@@ -225,6 +236,9 @@ def load_library():
                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
         "coop_injector_start": (i32, [VP, VP, ctypes.POINTER(coop_cotask_cfg)]),
         "coop_injector_stop": (i32, [VP, ctypes.POINTER(coop_cotask_stats)]),
+        "coop_share_start": (i32, [VP, u32]),
+        "coop_share_add": (i32, [VP, VP, u32]),
+        "coop_share_stop": (i32, [VP, ctypes.POINTER(coop_share_stats)]),
         "coop_barrier_bench": (i32, [VP, ctypes.POINTER(coop_launch_opts), u32, VP,
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(coop_stats)]),
         "coop_tune_default": (None, [ctypes.POINTER(coop_tune)]),
@@ -402,6 +416,20 @@ def coop_injector_start(rt, h, groups, busy_ns, period_ns, max_tasks=0, lds_byte
 def coop_injector_stop(rt) -> tuple[int, dict]:
     st = coop_cotask_stats()
     rc = load_library().coop_injector_stop(rt, ctypes.byref(st))
+    return rc, st.as_dict()
+
+
+def coop_share_start(rt, period_us=0) -> None:
+    _check(load_library().coop_share_start(rt, period_us), "coop_share_start")
+
+
+def coop_share_add(rt, h, weight=1) -> None:
+    _check(load_library().coop_share_add(rt, h, weight), "coop_share_add")
+
+
+def coop_share_stop(rt) -> tuple[int, dict]:
+    st = coop_share_stats()
+    rc = load_library().coop_share_stop(rt, ctypes.byref(st))
     return rc, st.as_dict()
 
 

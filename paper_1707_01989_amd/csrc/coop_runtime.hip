@@ -140,6 +140,20 @@ struct coop_rt {
     double inj_setup_max = 0, inj_restore_max = 0;
     uint32_t inj_late = 0;
     int inj_error = 0;
+    // sharing the GPU between cooperative launches
+    struct Shared {
+        coop_handle* h = nullptr;
+        uint32_t weight = 1, share = 0;
+        double t_add = 0, t_end = 0;
+        bool ended = false;
+    };
+    std::thread sharer;
+    std::atomic<bool> share_stop{false};
+    std::mutex share_mu;                       // guards `shared` and the handles in it
+    std::vector<Shared> shared;
+    uint32_t share_period_us = 200;
+    uint32_t share_updates = 0, share_forks = 0;
+    int share_error = 0;
 };
 
 namespace {
@@ -491,6 +505,10 @@ int coop_shutdown(coop_rt* rt) {
         rt->inj_stop = true;
         rt->injector.join();
     }
+    if (rt->sharer.joinable()) {
+        rt->share_stop = true;
+        rt->sharer.join();
+    }
     (void)hipDeviceSynchronize();
     for (coop_handle* h : rt->detached) handle_free(h);
     rt->detached.clear();
@@ -770,6 +788,16 @@ int coop_wait(coop_handle* h, coop_stats* stats) {
     if (rt->inj_handle.load() == h) {
         rt->inj_handle.store(nullptr);
         while (rt->inj_busy.load()) std::this_thread::yield();
+    }
+    {
+        // and from the GPU sharer (which holds share_mu while it uses handles)
+        std::lock_guard<std::mutex> sl(rt->share_mu);
+        for (auto& e2 : rt->shared)
+            if (e2.h == h) {
+                if (!e2.ended) e2.t_end = now_ms();
+                e2.ended = true;
+                e2.h = nullptr;
+            }
     }
     if (e == hipSuccess && h->joined) e = hipEventSynchronize(h->ev_join);
     if (h->kind == COOP_KERNEL_BATCH) {
@@ -1641,7 +1669,7 @@ int coop_cotask_run(coop_rt* rt, const coop_cotask_cfg* cfg, coop_stream_t strea
 int coop_injector_start(coop_rt* rt, coop_handle* h, const coop_cotask_cfg* cfg) {
     if (!rt || !cfg || cfg->groups == 0 || cfg->period_ns == 0) return COOP_E_INVALID;
     if (h && (!h->coop || h->rt != rt)) return COOP_E_INVALID;
-    if (rt->injector.joinable()) return COOP_E_BUSY;
+    if (rt->injector.joinable() || rt->sharer.joinable()) return COOP_E_BUSY;
     rt->inj_cfg = *cfg;
     rt->inj_stop = false;
     rt->inj_handle = h;
@@ -1713,6 +1741,110 @@ int coop_injector_stop(coop_rt* rt, coop_cotask_stats* out) {
         out->late_periods = rt->inj_late;
     }
     return rt->inj_error;
+}
+
+// ------------------------------------------------- several cooperative launches
+
+namespace {
+
+// One pass of the sharer (share_mu held): drop finished launches, give every
+// live one its weighted share of the resident workgroups as its target, and
+// fork joiners for a launch whose share grew (the engine-balanced kill of
+// another launch may also have freed up to engines - 1 more).
+void share_pass(coop_rt* rt) {
+    uint64_t wsum = 0;
+    uint32_t live = 0, N = 0;
+    for (auto& e : rt->shared) {
+        if (e.ended || !e.h) continue;
+        if (handle_done(e.h)) {
+            e.ended = true;
+            e.t_end = now_ms();
+            continue;
+        }
+        wsum += e.weight;
+        ++live;
+        N = std::max(N, e.h->grid);
+    }
+    if (!live) return;
+    uint32_t given = 0, first = ~0u;
+    std::vector<uint32_t> want(rt->shared.size(), 0);
+    for (size_t i = 0; i < rt->shared.size(); ++i) {
+        auto& e = rt->shared[i];
+        if (e.ended || !e.h) continue;
+        if (first == ~0u) first = (uint32_t)i;
+        want[i] = std::max<uint32_t>(1, (uint32_t)((uint64_t)N * e.weight / wsum));
+        given += want[i];
+    }
+    if (given < N) want[first] += N - given;        // the remainder goes to the oldest launch
+    for (size_t i = 0; i < rt->shared.size(); ++i) {
+        auto& e = rt->shared[i];
+        if (e.ended || !e.h || want[i] == e.share) continue;
+        (void)coop_set_target(e.h, want[i]);
+        if (e.share && want[i] > e.share) {
+            const uint32_t extra = e.h->cfg.engines > 1 ? e.h->cfg.engines - 1 : 0u;
+            const int rc = coop_fork_groups(e.h, std::min(want[i] - e.share + extra, e.h->grid));
+            if (rc && !rt->share_error) rt->share_error = rc;
+            ++rt->share_forks;
+        }
+        e.share = want[i];
+        ++rt->share_updates;
+    }
+}
+
+}  // namespace
+
+int coop_share_start(coop_rt* rt, uint32_t period_us) {
+    if (!rt) return COOP_E_INVALID;
+    if (rt->sharer.joinable() || rt->injector.joinable()) return COOP_E_BUSY;
+    {
+        std::lock_guard<std::mutex> sl(rt->share_mu);
+        rt->shared.clear();
+        rt->share_updates = rt->share_forks = 0;
+        rt->share_error = 0;
+        rt->share_period_us = period_us ? period_us : 200u;
+    }
+    rt->share_stop = false;
+    rt->sharer = std::thread([rt]() {
+        (void)hipSetDevice(rt->device);
+        while (!rt->share_stop.load()) {
+            {
+                std::lock_guard<std::mutex> sl(rt->share_mu);
+                share_pass(rt);
+            }
+            std::this_thread::sleep_for(std::chrono::microseconds(rt->share_period_us));
+        }
+    });
+    return COOP_OK;
+}
+
+int coop_share_add(coop_rt* rt, coop_handle* h, uint32_t weight) {
+    if (!rt || !h || h->rt != rt || !h->coop || !h->cfg.host || weight == 0) return COOP_E_INVALID;
+    if (!rt->sharer.joinable()) return COOP_E_INVALID;
+    std::lock_guard<std::mutex> sl(rt->share_mu);
+    for (const auto& e : rt->shared)
+        if (e.h == h) return COOP_E_INVALID;
+    coop_rt::Shared e;
+    e.h = h;
+    e.weight = weight;
+    e.t_add = now_ms();
+    rt->shared.push_back(e);
+    share_pass(rt);                                  // targets change now, not a period later
+    return COOP_OK;
+}
+
+int coop_share_stop(coop_rt* rt, coop_share_stats* out) {
+    if (!rt || !rt->sharer.joinable()) return COOP_E_INVALID;
+    rt->share_stop = true;
+    rt->sharer.join();
+    std::lock_guard<std::mutex> sl(rt->share_mu);
+    if (out) {
+        std::memset(out, 0, sizeof(*out));
+        out->launches = (uint32_t)rt->shared.size();
+        out->target_updates = rt->share_updates;
+        out->fork_calls = rt->share_forks;
+    }
+    rt->shared.clear();
+    return rt->share_error;
 }
 
 int coop_barrier_bench(coop_rt* rt, const coop_launch_opts* opts, uint32_t iters, coop_stream_t stream,
