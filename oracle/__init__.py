@@ -14,6 +14,8 @@ Functions (all results are integer and unique):
   color(g, prio_seed) -> uint32[n] greedy colours in decreasing key order
   mis(g, prio_seed)   -> uint8[n] greedy maximal independent set, same order
   priority_order(n, prio_seed) -> vertices by decreasing key
+  octree(x, y, z, cap) -> (uint32[n, 4] points in final order {x, y, z, index},
+                           uint32[k, 5] leaves {first, end, depth, code_lo, code_hi})
   splitmix64(x)       -> SplitMix64 output for state x
 
 The cooperative-scheduling semantics model lives in ``oracle.coop_model``.
@@ -57,6 +59,9 @@ def _load():
     lib.oracle_color.argtypes = [ctypes.c_uint32, u32p, u32p, ctypes.c_uint64, u32p]
     lib.oracle_mis.restype = ctypes.c_int
     lib.oracle_mis.argtypes = [ctypes.c_uint32, u32p, u32p, ctypes.c_uint64, u8p]
+    lib.oracle_octree.restype = ctypes.c_int
+    lib.oracle_octree.argtypes = [ctypes.c_uint32, u32p, u32p, u32p, ctypes.c_uint32, u32p, u32p,
+                                  ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
     lib.oracle_priority_order.restype = ctypes.c_int
     lib.oracle_priority_order.argtypes = [ctypes.c_uint32, ctypes.c_uint64, u32p]
     _lib = lib
@@ -128,3 +133,22 @@ def priority_order(n: int, prio_seed: int) -> np.ndarray:
     if rc != 0:
         raise OracleError("oracle_priority_order failed")
     return out
+
+
+def octree(x, y, z, cap: int) -> tuple[np.ndarray, np.ndarray]:
+    """Octree of integer points (see oracle_octree): the points in final
+    order as rows {x, y, z, original index}, and the leaves as rows
+    {first, end, depth, code_lo, code_hi} in order."""
+    x, px = _u32(x)
+    y, py = _u32(y)
+    z, pz = _u32(z)
+    n = len(x)
+    out = np.zeros((n, 4), dtype=np.uint32)
+    max_leaves = max(1, n)
+    leaves = np.zeros((max_leaves, 5), dtype=np.uint32)
+    nl = ctypes.c_uint64()
+    rc = _load().oracle_octree(n, px, py, pz, cap, _ptr(out, ctypes.c_uint32), _ptr(leaves, ctypes.c_uint32),
+                               max_leaves, ctypes.byref(nl))
+    if rc != 0:
+        raise OracleError(f"oracle_octree failed ({rc})")
+    return out, leaves[: nl.value].copy()

@@ -223,3 +223,72 @@ int oracle_mis(uint32_t n, const uint32_t* row_ptr, const uint32_t* col, uint64_
     free(order);
     return 0;
 }
+
+/* ------------------------------------------------------------- octree */
+
+/* Octree of points with integer coordinates in [0, 2^21) (the work-stealing
+ * workload; the paper names the octree build without giving its rules, so
+ * these are the readings used): a node at depth d is a cube of side
+ * 2^(21 - d); its points go to the 8 child cubes by bit (20 - d) of x, y
+ * and z (child = 4 bx + 2 by + bz), keeping their order (a stable split).
+ * A node with at most `cap` points, or at depth 21, is a leaf. The code of
+ * a node is its path of child indices, 3 bits per level.
+ *
+ * Output: `out` (4n words) = the points in final order as {x, y, z, index};
+ * `leaves` (5 words each, at most max_leaves) = {first, end, depth,
+ * code_lo, code_hi} in order of `first`. Returns 0, -1 (too many leaves)
+ * or -2 (out of memory). Depth-first with an explicit stack, children in
+ * index order, so the leaves come out ordered. */
+int oracle_octree(uint32_t n, const uint32_t* x, const uint32_t* y, const uint32_t* z, uint32_t cap,
+                  uint32_t* out, uint32_t* leaves, uint64_t max_leaves, uint64_t* nleaves) {
+    typedef struct { uint32_t first, end, depth; uint64_t code; } node;
+    uint32_t* tmp = (uint32_t*)malloc(sizeof(uint32_t) * 4 * (size_t)(n ? n : 1));
+    node* stack = (node*)malloc(sizeof(node) * (7 * 22 + 8));
+    if (!tmp || !stack) { free(tmp); free(stack); return -2; }
+    for (uint32_t i = 0; i < n; ++i) {
+        out[4 * i] = x[i];
+        out[4 * i + 1] = y[i];
+        out[4 * i + 2] = z[i];
+        out[4 * i + 3] = i;
+    }
+    uint64_t nl = 0;
+    int sp = 0;
+    stack[sp++] = (node){0, n, 0, 0};
+    while (sp > 0) {
+        node nd = stack[--sp];
+        const uint32_t count = nd.end - nd.first;
+        if (count <= cap || nd.depth == 21) {
+            if (count == 0) continue;
+            if (nl >= max_leaves) { free(tmp); free(stack); return -1; }
+            uint32_t* L = leaves + 5 * nl++;
+            L[0] = nd.first; L[1] = nd.end; L[2] = nd.depth;
+            L[3] = (uint32_t)nd.code; L[4] = (uint32_t)(nd.code >> 32);
+            continue;
+        }
+        /* stable split by the child index at this depth */
+        const uint32_t bit = 20 - nd.depth;
+        uint32_t cnt[8] = {0}, start[8];
+        for (uint32_t i = nd.first; i < nd.end; ++i) {
+            const uint32_t* p = out + 4 * (size_t)i;
+            const uint32_t c = (((p[0] >> bit) & 1u) << 2) | (((p[1] >> bit) & 1u) << 1) | ((p[2] >> bit) & 1u);
+            ++cnt[c];
+        }
+        uint32_t acc = nd.first;
+        for (int c = 0; c < 8; ++c) { start[c] = acc; acc += cnt[c]; }
+        uint32_t pos[8];
+        for (int c = 0; c < 8; ++c) pos[c] = start[c];
+        for (uint32_t i = nd.first; i < nd.end; ++i) {
+            const uint32_t* p = out + 4 * (size_t)i;
+            const uint32_t c = (((p[0] >> bit) & 1u) << 2) | (((p[1] >> bit) & 1u) << 1) | ((p[2] >> bit) & 1u);
+            memcpy(tmp + 4 * (size_t)pos[c]++, p, 16);
+        }
+        memcpy(out + 4 * (size_t)nd.first, tmp + 4 * (size_t)nd.first, 16 * (size_t)count);
+        /* children pushed last-first so child 0 is handled next */
+        for (int c = 7; c >= 0; --c)
+            if (cnt[c]) stack[sp++] = (node){start[c], start[c] + cnt[c], nd.depth + 1, (nd.code << 3) | (uint64_t)c};
+    }
+    *nleaves = nl;
+    free(tmp);
+    free(stack);
+    return 0;
+}

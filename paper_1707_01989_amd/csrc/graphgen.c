@@ -39,7 +39,7 @@
 #define GG_GAMMA 0x9E3779B97F4A7C15ull
 
 enum { GG_STREAM_ER = 1, GG_STREAM_RMAT = 2, GG_STREAM_PERM = 3, GG_STREAM_W = 4,
-       GG_STREAM_MISC = 5 };
+       GG_STREAM_MISC = 5, GG_STREAM_PTS = 6, GG_STREAM_CENTRES = 7 };
 
 uint64_t gg_splitmix64(uint64_t x) {
     uint64_t z = x + GG_GAMMA;
@@ -285,4 +285,42 @@ int64_t gg_sources(uint32_t n, const uint32_t* row_ptr, uint64_t seed, uint32_t 
         }
     }
     return k;
+}
+
+/* Seeded points with integer coordinates in [0, 2^21) per axis.
+ * kind 0: uniform. kind 1: clustered -- each point picks one of 16 seeded
+ * centres and adds, per axis, the sum of three uniform draws in [0, 2^14)
+ * minus 3 * 2^13 (a bell-shaped spread of about +-24K), clamped to the
+ * cube. Point i uses draws 4i .. 4i+3 of its stream. */
+int gg_points(uint32_t n, uint64_t seed, uint32_t kind, uint32_t* x, uint32_t* y, uint32_t* z) {
+    const uint64_t side = 1ull << 21;
+    if (kind > 1) return -1;
+    uint32_t cx[16], cy[16], cz[16];
+    for (uint32_t c = 0; c < 16; ++c) {
+        cx[c] = (uint32_t)gg_uniform(seed, GG_STREAM_CENTRES, 3 * c, 0, side - 1);
+        cy[c] = (uint32_t)gg_uniform(seed, GG_STREAM_CENTRES, 3 * c + 1, 0, side - 1);
+        cz[c] = (uint32_t)gg_uniform(seed, GG_STREAM_CENTRES, 3 * c + 2, 0, side - 1);
+    }
+    for (uint32_t i = 0; i < n; ++i) {
+        if (kind == 0) {
+            x[i] = (uint32_t)gg_uniform(seed, GG_STREAM_PTS, 4ull * i, 0, side - 1);
+            y[i] = (uint32_t)gg_uniform(seed, GG_STREAM_PTS, 4ull * i + 1, 0, side - 1);
+            z[i] = (uint32_t)gg_uniform(seed, GG_STREAM_PTS, 4ull * i + 2, 0, side - 1);
+        } else {
+            const uint32_t c = (uint32_t)gg_uniform(seed, GG_STREAM_PTS, 4ull * i + 3, 0, 15);
+            const uint32_t ctr[3] = {cx[c], cy[c], cz[c]};
+            uint32_t* out[3] = {x, y, z};
+            for (int a = 0; a < 3; ++a) {
+                int64_t off = 0;
+                /* three disjoint 14-bit fields of one draw */
+                const uint64_t r = gg_rand(seed, GG_STREAM_PTS, 4ull * i + a);
+                for (int k = 0; k < 3; ++k) off += (int64_t)((r >> (64 - 14 * (k + 1))) & 0x3FFF);
+                int64_t v = (int64_t)ctr[a] + off - 3 * 8192;
+                if (v < 0) v = 0;
+                if (v > (int64_t)side - 1) v = (int64_t)side - 1;
+                out[a][i] = (uint32_t)v;
+            }
+        }
+    }
+    return 0;
 }

@@ -57,6 +57,8 @@ def _load():
     lib.gg_weights.restype = ctypes.c_int
     lib.gg_weights.argtypes = [ctypes.c_uint32, u32p, u32p, ctypes.c_uint64,
                                ctypes.c_uint32, ctypes.c_uint32, u32p]
+    lib.gg_points.restype = ctypes.c_int
+    lib.gg_points.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, u32p, u32p, u32p]
     lib.gg_sources.restype = ctypes.c_int64
     lib.gg_sources.argtypes = [ctypes.c_uint32, u32p, ctypes.c_uint64, ctypes.c_uint32, u32p]
     _lib = lib
@@ -257,3 +259,23 @@ def disjoint_union(g1: Graph, g2: Graph) -> Graph:
     if g1.w is not None and g2.w is not None:
         w = np.concatenate([g1.w, g2.w]).astype(np.uint32)
     return Graph(n=g1.n + g2.n, row_ptr=rp, col=col, w=w, name=f"{g1.name}+{g2.name}")
+
+
+# ----------------------------------------------------------------- points
+
+POINT_BITS = 21          # coordinates in [0, 2^21) per axis
+
+
+def points(n: int, seed: int, kind: str = "uniform") -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """n seeded points (x, y, z uint32 arrays in [0, 2^21)): "uniform", or
+    "clustered" (16 seeded centres, bell-shaped spread of about 1% of the
+    side), for the work-stealing octree."""
+    k = {"uniform": 0, "clustered": 1}[kind]
+    x = np.zeros(n, dtype=np.uint32)
+    y = np.zeros(n, dtype=np.uint32)
+    z = np.zeros(n, dtype=np.uint32)
+    if n:
+        rc = _load().gg_points(n, seed & (2**64 - 1), k, _p(x), _p(y), _p(z))
+        if rc != 0:
+            raise ValueError("gg_points failed")
+    return x, y, z
