@@ -187,7 +187,8 @@ int coop_mis(coop_rt* rt, const coop_graph* g, uint64_t prio_seed, uint8_t* d_in
 /* Generic launch by kernel id with a parameter block (immutable, copied). */
 enum { COOP_KERNEL_BFS = 1, COOP_KERNEL_SSSP = 2, COOP_KERNEL_COLOR = 3, COOP_KERNEL_MIS = 4,
        COOP_KERNEL_BARRIER = 5, COOP_KERNEL_BATCH = 6 /* handles of coop_batch_run only */,
-       COOP_KERNEL_SERVE = 7 /* the launch inside a coop_server */ };
+       COOP_KERNEL_SERVE = 7 /* the launch inside a coop_server */,
+       COOP_KERNEL_OCTREE = 8 /* handles of coop_octree only */ };
 typedef struct coop_params {
     const coop_graph* graph;
     const uint32_t* d_roots;
@@ -244,6 +245,30 @@ typedef struct coop_cotask_stats {
     uint32_t late_periods;    /* injector: periods that started more than one period late */
     uint32_t reserved;
 } coop_cotask_stats;
+
+/* Work-stealing octree build (the paper's work-stealing class of cooperative
+ * kernels, section 3.2 "Adapting Work Stealing"; the octree of Table 1).
+ * Points: n coordinates per axis in d_x, d_y, d_z (device, each < 2^21).
+ * A cube at depth d has side 2^(21 - d); its points are split stably into
+ * its 8 child cubes (child = 4 bx + 2 by + bz for bit 20 - d) until a cube
+ * holds at most `cap` points or reaches depth 21 (a leaf). Tasks are cubes
+ * to split, kept in one queue per workgroup slot (mutex per queue); idle
+ * workgroups steal. In a cooperative launch a workgroup offers itself to
+ * the scheduler before each task and may leave with tasks queued (they are
+ * stolen); joiner grids (coop_fork_groups) take free slots.
+ * Outputs: d_out (4n words, 16-byte aligned) = the points in final order as
+ * {x, y, z, input index}; d_leaves (8 words per leaf, room for leaf_cap) =
+ * {first, end, depth, code_lo, code_hi, -, -, -} in no particular order
+ * (sort by first), code = the child indices from the root, 3 bits per
+ * level. Both are the same under any schedule. coop_wait's stats: rows =
+ * leaves written (COOP_E_INVALID if more than leaf_cap were needed),
+ * levels = cubes split, arcs = tasks stolen, found = n, kills / forks /
+ * min_groups / max_groups = workgroups that left / joined and the range of
+ * active workgroups. Errors: COOP_E_INVALID, COOP_E_OOM, COOP_E_TIMEOUT
+ * (watchdog), COOP_E_HIP. */
+int coop_octree(coop_rt* rt, const uint32_t* d_x, const uint32_t* d_y, const uint32_t* d_z, uint32_t n,
+                uint32_t cap, uint32_t* d_out, uint32_t* d_leaves, uint32_t leaf_cap,
+                const coop_launch_opts* opts, coop_stream_t stream, coop_handle** out);
 
 /* Several cooperative launches at once (the paper's prototype ran one
  * cooperative kernel at a time; its scheduler contexts were designed for

@@ -24,7 +24,8 @@ INCLUDE_DIR = os.path.join(REPO_DIR, "include")
 GRAPHGEN_SO = os.path.join(LIB_DIR, "libgraphgen.so")
 COOP_SO = os.path.join(LIB_DIR, "libcoop.so")
 
-HIP_SOURCES = ["coop_kernels.hip", "batch_kernels.hip", "serve_kernels.hip", "coop_runtime.hip"]
+HIP_SOURCES = ["coop_kernels.hip", "batch_kernels.hip", "serve_kernels.hip", "octree_kernels.hip",
+               "coop_runtime.hip"]
 HIP_ARCH = "gfx950"
 
 

@@ -32,6 +32,7 @@ COOP_F_RANDOM_SCHEDULE = 2
 COOP_F_HOST_SCHEDULE = 4
 COOP_F_TOP_DOWN_ONLY = 8
 COOP_F_REGULAR_BARRIER = 16
+COOP_KERNEL_OCTREE = 8
 
 COOP_KERNEL_BFS = 1
 COOP_KERNEL_SSSP = 2
@@ -58,7 +59,7 @@ EXPORTS = [
     "coop_last_hip_error", "coop_graph_wrap", "coop_graph_release", "coop_bfs", "coop_sssp",
     "coop_color", "coop_mis", "coop_launch", "coop_wait", "coop_handle_groups", "coop_set_target",
     "coop_fork_groups", "coop_cotask_run", "coop_injector_start", "coop_injector_stop",
-    "coop_share_start", "coop_share_add", "coop_share_stop",
+    "coop_share_start", "coop_share_add", "coop_share_stop", "coop_octree",
     "coop_barrier_bench", "coop_tune_default", "coop_batch_run", "coop_batch_autotune",
     "coop_server_cfg_default", "coop_server_create", "coop_server_submit", "coop_server_poll",
     "coop_server_wait", "coop_server_stats", "coop_server_handle", "coop_server_destroy",
@@ -237,6 +238,7 @@ def load_library():
         "coop_injector_start": (i32, [VP, VP, ctypes.POINTER(coop_cotask_cfg)]),
         "coop_injector_stop": (i32, [VP, ctypes.POINTER(coop_cotask_stats)]),
         "coop_share_start": (i32, [VP, u32]),
+        "coop_octree": (i32, [VP, VP, VP, VP, u32, u32, VP, VP, u32, ctypes.POINTER(coop_launch_opts), VP, VPP]),
         "coop_share_add": (i32, [VP, VP, u32]),
         "coop_share_stop": (i32, [VP, ctypes.POINTER(coop_share_stats)]),
         "coop_barrier_bench": (i32, [VP, ctypes.POINTER(coop_launch_opts), u32, VP,
@@ -419,6 +421,16 @@ def coop_injector_stop(rt) -> tuple[int, dict]:
     return rc, st.as_dict()
 
 
+def coop_octree(rt, x, y, z, n, cap, out, leaves, leaf_cap, opts=None, stream=None, keep=True):
+    """Work-stealing octree build; x, y, z, out (n x 4), leaves (leaf_cap x 8)
+    are device tensors. Returns the launch handle (wait with coop_wait)."""
+    h = ctypes.c_void_p()
+    _check(load_library().coop_octree(rt, _ptr(x), _ptr(y), _ptr(z), n, cap, _ptr(out), _ptr(leaves), leaf_cap,
+                                      ctypes.byref(opts) if opts is not None else None, _stream(stream),
+                                      ctypes.byref(h) if keep else None), "coop_octree")
+    return h.value
+
+
 def coop_share_start(rt, period_us=0) -> None:
     _check(load_library().coop_share_start(rt, period_us), "coop_share_start")
 
@@ -578,6 +590,25 @@ class Runtime:
         import torch
         r = np.ascontiguousarray(np.asarray(roots, dtype=np.uint32).reshape(-1))
         return torch.from_numpy(r.view("int32")).cuda()
+
+    def octree(self, x, y, z, cap: int, opts=None, stream=None):
+        """Work-stealing octree of host (numpy) points: returns (rc, points
+        uint32[n, 4] in final order {x, y, z, index}, leaves uint32[k, 5]
+        {first, end, depth, code_lo, code_hi} sorted by first, stats)."""
+        import numpy as np
+        import torch
+        n = len(x)
+        dx, dy, dz = (torch.from_numpy(np.ascontiguousarray(v, dtype=np.uint32).view(np.int32)).cuda()
+                      for v in (x, y, z))
+        out = torch.empty((max(n, 1), 4), dtype=torch.int32, device="cuda")
+        leaf_cap = max(1, n)
+        leaves = torch.empty((leaf_cap, 8), dtype=torch.int32, device="cuda")
+        h = coop_octree(self.rt, dx, dy, dz, n, cap, out, leaves, leaf_cap, opts, stream)
+        rc, st = coop_wait(h)
+        pts = out.cpu().numpy().view(np.uint32)[:n]
+        lv = leaves.cpu().numpy().view(np.uint32)[: min(st["rows"], leaf_cap), :5]
+        lv = lv[np.argsort(lv[:, 0], kind="stable")]
+        return rc, pts, lv, st
 
     def bfs(self, dg: DeviceGraph, roots, opts=None, stream=None, out=None):
         import torch

@@ -284,6 +284,59 @@ struct ServeArgs {
     uint32_t team_max;         // the kill rule keeps at least this many workgroups
 };
 
+// ------------------------------------------------ work-stealing octree
+
+constexpr uint32_t kOctQueueCap = 1024;   // node ids per queue (depth-first use keeps it short)
+constexpr uint32_t kOctMaxDepth = 21;     // coordinates have 21 bits
+
+// One task queue (ring of node ids) per slot; a workgroup owns one slot at
+// a time. Guarded by `lock` (compare-and-swap mutex): the owner pushes and
+// pops at the tail, thieves take from the head.
+struct alignas(256) OctQueue {
+    uint32_t lock;
+    uint32_t head;
+    uint32_t tail;
+    uint32_t _p[61];
+    uint32_t ring[kOctQueueCap];
+};
+
+struct alignas(256) OctCtl {
+    uint32_t outstanding;      // tasks created and not finished
+    uint32_t _p0[63];
+    uint32_t node_count;       // nodes allocated (node 0 = root)
+    uint32_t leaf_count;
+    uint32_t _p1[62];
+    uint32_t active;           // workgroups inside the loop
+    uint32_t kills;            // workgroups that left for the scheduler
+    uint32_t forks;            // joiner workgroups that entered
+    uint32_t min_active;
+    uint32_t max_active;
+    int32_t error;
+    uint32_t _p2[58];
+    uint32_t tasks;            // cubes split
+    uint32_t steals;           // tasks taken from another slot's queue
+    uint32_t _p3[62];
+    uint32_t active_x[kMaxEngines];
+};
+
+struct OctreeArgs {
+    Cfg cfg;                   // N = slots, mode, host target, watchdog
+    uint4* buf[2];             // points {x, y, z, index}; depth d reads buf[d & 1]; buf[0] is the result
+    uint32_t n, cap;
+    uint32_t* nodes;           // 8 words per node {first, end, depth, code_lo, code_hi, -, -, -}
+    uint32_t node_cap;
+    uint32_t* leaves;          // 8 words per leaf {first, end, depth, code_lo, code_hi, -, -, -}
+    uint32_t leaf_cap;
+    OctCtl* ctl;
+    OctQueue* q;               // N queues
+    uint32_t* slot_owner;      // N words: 1 while a workgroup owns the slot
+};
+
+hipError_t launch_octree_init(const OctreeArgs& a, const uint32_t* x, const uint32_t* y, const uint32_t* z,
+                              hipStream_t s);
+hipError_t launch_octree(const OctreeArgs& a, bool coop, bool joiner_grid, uint32_t grid, uint32_t block,
+                         uint32_t lds_bytes, hipStream_t s);
+
 hipError_t launch_serve_init(TeamState* teams, uint32_t slots, ServeCtl* ctl, hipStream_t s);
 hipError_t launch_serve(const ServeArgs& a, bool coop, bool joiner_grid, uint32_t grid, uint32_t block,
                         uint32_t lds_bytes, hipStream_t s);

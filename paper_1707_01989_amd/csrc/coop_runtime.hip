@@ -112,6 +112,8 @@ struct coop_handle {
     size_t bslot_words = 0;
     // serving launch
     coop::ServeArgs serve{};
+    // work-stealing octree
+    coop::OctreeArgs octree{};
 };
 
 struct coop_rt {
@@ -361,6 +363,8 @@ hipError_t relaunch(coop_handle* h, bool joiner, uint32_t grid, hipStream_t s) {
             return coop::launch_barrier_bench(h->bb, h->coop, joiner, grid, h->block, h->lds, s);
         case COOP_KERNEL_BATCH: return coop::launch_batch(h->batch, h->coop, joiner, grid, h->block, h->lds, s);
         case COOP_KERNEL_SERVE: return coop::launch_serve(h->serve, h->coop, joiner, grid, h->block, h->lds, s);
+        case COOP_KERNEL_OCTREE:
+            return coop::launch_octree(h->octree, h->coop, joiner, grid, h->block, h->lds, s);
     }
     return hipErrorInvalidValue;
 }
@@ -802,6 +806,31 @@ int coop_wait(coop_handle* h, coop_stats* stats) {
     if (e == hipSuccess && h->joined) e = hipEventSynchronize(h->ev_join);
     if (h->kind == COOP_KERNEL_BATCH) {
         int rc = e == hipSuccess ? batch_stats(h, stats) : hip_fail(rt, e);
+        std::lock_guard<std::recursive_mutex> lk(rt->mu);
+        handle_free(h);
+        return rc;
+    }
+    if (h->kind == COOP_KERNEL_OCTREE) {
+        coop::OctCtl ctl{};
+        if (e == hipSuccess) e = hipMemcpy(&ctl, h->octree.ctl, sizeof(ctl), hipMemcpyDeviceToHost);
+        float ms = 0.f;
+        if (e == hipSuccess) (void)hipEventElapsedTime(&ms, h->ev_start, h->ev_end);
+        int rc = e == hipSuccess ? ctl.error : hip_fail(rt, e);
+        if (rc == COOP_OK && ctl.leaf_count > h->octree.leaf_cap) rc = COOP_E_INVALID;
+        if (stats) {
+            std::memset(stats, 0, sizeof(*stats));
+            stats->error = rc;
+            stats->grid = h->grid;
+            stats->kills = ctl.kills;
+            stats->forks = ctl.forks;
+            stats->min_groups = ctl.min_active == 0xFFFFFFFFu ? ctl.max_active : ctl.min_active;
+            stats->max_groups = ctl.max_active;
+            stats->levels = ctl.tasks;
+            stats->rows = ctl.leaf_count;
+            stats->arcs = ctl.steals;
+            stats->found = h->octree.n;
+            stats->kernel_ms = ms;
+        }
         std::lock_guard<std::recursive_mutex> lk(rt->mu);
         handle_free(h);
         return rc;
@@ -1741,6 +1770,45 @@ int coop_injector_stop(coop_rt* rt, coop_cotask_stats* out) {
         out->late_periods = rt->inj_late;
     }
     return rt->inj_error;
+}
+
+// ---------------------------------------------------- work-stealing octree
+
+int coop_octree(coop_rt* rt, const uint32_t* d_x, const uint32_t* d_y, const uint32_t* d_z, uint32_t n,
+                uint32_t cap, uint32_t* d_out, uint32_t* d_leaves, uint32_t leaf_cap, const coop_launch_opts* opts,
+                coop_stream_t stream, coop_handle** out) {
+    if (!rt || (n && (!d_x || !d_y || !d_z || !d_out || !d_leaves)) || cap == 0 || leaf_cap == 0) return COOP_E_INVALID;
+    if ((reinterpret_cast<uintptr_t>(d_out) & 15) != 0) return COOP_E_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(rt->mu);
+    reap(rt);
+    Sizing sz{};
+    int rc = size_launch(rt, opts, &sz);
+    if (rc) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    coop_handle* h = nullptr;
+    if ((rc = begin_launch(rt, opts, sz, COOP_KERNEL_OCTREE, s, &h))) return rc;
+    coop::OctreeArgs& a = h->octree;
+    a.cfg = h->cfg;
+    a.n = n;
+    a.cap = cap;
+    // a cube that is split holds more than cap points and the cubes of one
+    // depth are disjoint: at most n / (cap + 1) splits per depth
+    const uint64_t nodes = (uint64_t)(coop::kOctMaxDepth + 1) * ((uint64_t)n / ((uint64_t)cap + 1) + 1);
+    a.node_cap = (uint32_t)std::min<uint64_t>(nodes, 0xFFFFFFF0ull);
+    a.leaf_cap = leaf_cap;
+    a.buf[0] = reinterpret_cast<uint4*>(d_out);
+    a.buf[1] = static_cast<uint4*>(scratch(h, (size_t)std::max<uint32_t>(n, 1) * 16));
+    a.nodes = static_cast<uint32_t*>(scratch(h, (size_t)a.node_cap * 32));
+    a.leaves = d_leaves;
+    a.ctl = static_cast<coop::OctCtl*>(scratch(h, sizeof(coop::OctCtl)));
+    a.q = static_cast<coop::OctQueue*>(scratch(h, (size_t)h->grid * sizeof(coop::OctQueue)));
+    a.slot_owner = static_cast<uint32_t*>(scratch(h, (size_t)h->grid * 4));
+    if (!a.buf[1] || !a.nodes || !a.ctl || !a.q || !a.slot_owner) { handle_free(h); return COOP_E_OOM; }
+    hipError_t e = coop::launch_octree_init(a, d_x, d_y, d_z, s);
+    if (e != hipSuccess) { handle_free(h); return hip_fail(rt, e); }
+    (void)hipEventRecord(h->ev_init, s);
+    (void)hipEventRecord(h->ev_start, s);
+    return finish_launch(rt, h, relaunch(h, false, h->grid, s), out);
 }
 
 // ------------------------------------------------- several cooperative launches
