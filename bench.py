@@ -25,6 +25,8 @@ Printed JSON line (one):
   shared         a long cooperative BFS and the SSSP grid launched together,
                  the host sharer splitting the resident workgroups between
                  them: each one's time alone and shared, wall time shared
+  octree         work-stealing octree build (4M clustered points): coop vs
+                 plain, and co-task latency during one build
   gather_sweep   gather time against the workgroups a co-task claims (1, a
                  quarter, half, all but one), query barrier vs the regular
                  barrier that lets one workgroup go per barrier
@@ -93,6 +95,7 @@ def main():
     ap.add_argument("--skip-cotask", action="store_true")
     ap.add_argument("--skip-sssp", action="store_true")
     ap.add_argument("--skip-share", action="store_true")
+    ap.add_argument("--skip-octree", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark measures one GPU; multi-GPU runs are not part of it",
@@ -323,6 +326,47 @@ def main():
             "target_updates": sst["target_updates"],
         }
         log(f"shared: {result['shared']}")
+
+    if not args.skip_octree:
+        # work-stealing octree: 4M clustered points, leaves of at most 8
+        xo, yo, zo = gg.points(4_000_000, 9, "clustered")
+        no = len(xo)
+        dxo, dyo, dzo = (torch.from_numpy(v.view(np.int32)).cuda() for v in (xo, yo, zo))
+        o_out = torch.empty((no, 4), dtype=torch.int32, device="cuda")
+        o_leaves = torch.empty((no, 8), dtype=torch.int32, device="cuda")
+
+        def run_o(opts):
+            h = coop.coop_octree(rt.rt, dxo, dyo, dzo, no, 8, o_out, o_leaves, no, opts, stream)
+            rc, st = coop.coop_wait(h)
+            if rc != 0:
+                raise RuntimeError(coop.coop_strerror(rc))
+            return st
+
+        run_o(coop_opts)
+        run_o(plain_opts)
+        oc = [run_o(coop_opts) for _ in range(5)]
+        op = [run_o(plain_opts) for _ in range(5)]
+        ms_oc = float(np.median([s["kernel_ms"] for s in oc]))
+        ms_op = float(np.median([s["kernel_ms"] for s in op]))
+        # co-tasks needing half the CUs every 2 ms during one build
+        h = coop.coop_octree(rt.rt, dxo, dyo, dzo, no, 8, o_out, o_leaves, no, coop_opts, stream)
+        coop.coop_injector_start(rt.rt, h, groups=rt.info["compute_units"] // 2, busy_ns=200_000,
+                                 period_ns=2_000_000)
+        rc, st_oi = coop.coop_wait(h)
+        irc, c_oi = coop.coop_injector_stop(rt.rt)
+        if rc or irc:
+            raise RuntimeError(f"octree co-task run failed: {rc} {irc}")
+        result["octree"] = {
+            "workload": "work-stealing octree, 4M clustered points (seed 9), leaves of at most 8 points",
+            "ms_coop": round(ms_oc, 3), "ms_plain": round(ms_op, 3), "coop_overhead": round(ms_oc / ms_op, 4),
+            "mpoints_per_s_coop": round(no / (ms_oc * 1e-3) / 1e6, 1),
+            "splits": oc[0]["levels"], "leaves": oc[0]["rows"], "steals": oc[0]["arcs"],
+            "cotask": {"period_ms": 2, "busy_ms": 0.2, "count": c_oi["count"],
+                       "latency_p50_ms": round(c_oi["latency_p50_ms"], 4),
+                       "latency_p99_ms": round(c_oi["latency_p99_ms"], 4),
+                       "build_ms": round(st_oi["kernel_ms"], 3), "kills": st_oi["kills"]},
+        }
+        log(f"octree: {result['octree']}")
 
     # global-barrier latency (persistent launch doing barriers only)
     bar = {}

@@ -1092,23 +1092,36 @@ struct LeaveCounters {
 // offer_kill between instances (thread 0): leave if the launch holds more
 // workgroups than max(T, floor) and this workgroup's shader engine holds
 // more than its share ceil(T / engines) (a competing kernel is dealt over
-// every engine, so it needs free compute units on each of them).
+// every engine, so it needs free compute units on each of them). The
+// engine's count is claimed first with compare-and-swap, so workgroups of
+// one engine that decide together cannot all leave it; if the launch-wide
+// count is already at its floor the engine's count is given back.
 __device__ inline bool leave_for_target(const LeaveCounters& lc, uint32_t T, uint32_t floor, uint32_t engines,
                                         uint32_t x) {
     const uint32_t lo = T > floor ? T : floor;
     const bool placed = engines > 1 && engines <= kMaxEngines;
     const uint32_t share = placed ? (T + engines - 1) / engines : T;
-    if (placed && ld_relaxed(&lc.active_x[x % kMaxEngines]) <= share) return false;
+    uint32_t* ax = &lc.active_x[x % kMaxEngines];
+    if (placed) {
+        uint32_t e = ld_relaxed(ax);
+        for (;;) {
+            if (e <= share) return false;
+            if (__hip_atomic_compare_exchange_strong(ax, &e, e - 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT))
+                break;
+        }
+    }
     uint32_t a = ld_relaxed(lc.active);
     while (a > lo) {
         if (__hip_atomic_compare_exchange_strong(lc.active, &a, a - 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT)) {
-            add_relaxed(&lc.active_x[x % kMaxEngines], 0xFFFFFFFFu);
+            if (!placed) add_relaxed(ax, 0xFFFFFFFFu);
             add_relaxed(lc.kills, 1u);
             atomicMin(lc.min_active, a - 1);
             return true;
         }
     }
+    if (placed) add_relaxed(ax, 1u);          // the launch is at its floor: stay
     return false;
 }
 
