@@ -270,7 +270,7 @@ def main():
             "busy_mean_ms": round(cst["busy_mean_ms"], 4),
             "traversal_ms_alone": round(alone["kernel_ms"], 2), "traversal_ms_with_cotask": round(st_m["kernel_ms"], 2),
             "slowdown": round(st_m["kernel_ms"] / alone["kernel_ms"], 4),
-            "kills": st_m["kills"], "forks": st_m["forks"],
+            "kills": st_m["kills"], "forks": st_m["forks"], "join_full": st_m["join_full"],
             "model_kernel_preemption": round(10 / 9, 4), "model_half_cu": round(10 / 9.5, 4),
         }
         log(f"cotask: {result['cotask']}")
@@ -288,10 +288,10 @@ def main():
                               "gather_p50_ms": round(c_g["gather_p50_ms"], 4),
                               "gather_p99_ms": round(c_g["gather_p99_ms"], 4),
                               "latency_p50_ms": round(c_g["latency_p50_ms"], 4),
-                              "kills": st_g["kills"]})
+                              "kills": st_g["kills"], "forks": st_g["forks"], "join_full": st_g["join_full"]})
         result["gather_sweep"] = sweep
-        log("gather sweep: " + "; ".join(f"{e['barrier']} W={e['groups']}: {e['gather_p50_ms']}/{e['gather_p99_ms']} ms"
-                                         for e in sweep))
+        log("gather sweep: " + "; ".join(f"{e['barrier']} W={e['groups']}: {e['gather_p50_ms']}/{e['gather_p99_ms']} ms "
+                                         f"({e['count']} co-tasks, {e['kills']} kills)" for e in sweep))
 
     if not args.skip_share and not args.skip_sssp:
         # two cooperative launches at once: a long BFS (R-MAT, ~0.3 s) and the

@@ -68,6 +68,8 @@ typedef struct coop_device_info {
     uint32_t wall_clock_khz;       /* rate of the device wall clock */
     uint64_t hbm_bytes;            /* global memory size */
     char arch[64];                 /* gcnArchName, e.g. "gfx950:sramecc+:xnack-" */
+    uint32_t xcds;                 /* XCDs workgroups are dealt over (from where a probe grid lands) */
+    uint32_t shader_engines;       /* shader engines per XCD (same probe) */
 } coop_device_info;
 
 /* Create a runtime on `device` (HIP ordinal). The runtime owns its streams,
@@ -98,8 +100,8 @@ enum {
     COOP_F_HOST_SCHEDULE = 4u,    /* barrier reads the host-written target (coop_set_target) */
     COOP_F_TOP_DOWN_ONLY = 8u,    /* BFS: never switch to bottom-up levels */
     COOP_F_REGULAR_BARRIER = 16u  /* the paper's regular resizing barrier: at most one workgroup
-                                     (the top id) leaves per barrier, instead of the query
-                                     barrier's W at once (section 4.2); for gather-time comparisons */
+                                     leaves per barrier, instead of the query barrier's W at
+                                     once (section 4.2); for gather-time comparisons */
 };
 
 typedef struct coop_launch_opts {
@@ -119,7 +121,11 @@ typedef struct coop_launch_opts {
                                  when it published, with the published flags in the top
                                  16 bits; NULL = no trace */
     uint32_t trace_cap;       /* barriers d_trace (and d_wgtrace) can hold */
-    uint32_t reserved0;
+    uint32_t join_window;     /* joiners that may wait for admission at once (at least N,
+                                 so that the launch's own late workgroups fit); a joiner
+                                 that finds more ahead of it leaves (counted in
+                                 coop_stats.join_full); 0 = the ring's 8192 entries
+                                 minus the launch's N */
     uint64_t* d_wgtrace;      /* optional device buffer: per barrier e and logical workgroup id,
                                  four device wall-clock stamps at [(e * N + id) * 4 + k]: work
                                  start, work done, barrier arrival, release seen; NULL = off */
@@ -148,7 +154,7 @@ typedef struct coop_stats {
     uint32_t td_levels;       /* BFS levels run top-down */
     uint32_t bu_levels;       /* BFS levels run bottom-up */
     uint32_t heavy_phases;    /* extra phases that walked heavy-vertex strips */
-    uint32_t reserved;
+    uint32_t join_full;       /* joiners that found the admission ring full and left */
 } coop_stats;
 
 /* BFS (the cooperative graph-traversal kernel of the paper's programming
@@ -213,7 +219,12 @@ uint32_t coop_handle_groups(const coop_handle* h);
 /* Scheduler target for a COOP_F_HOST_SCHEDULE launch: at its next resizing
  * barrier the kernel keeps min(max(1, target), N) workgroups (the paper's
  * `query`): surplus workgroups leave (their CUs become free), and waiting
- * joiners are admitted while M < target. Non-blocking host store. */
+ * joiners are admitted while M < target. The leavers are chosen by shader
+ * engine: every engine keeps at most (its share of the resident slots) -
+ * ceil((N - target) / engines) workgroups, because the other kernel's
+ * workgroups are dealt over the engines round-robin; the regular barrier
+ * (COOP_F_REGULAR_BARRIER) lets one leave per barrier, from the engine that
+ * owes most. Non-blocking host store. */
 int coop_set_target(coop_handle* h, uint32_t target);
 
 /* Give workgroups back: launch `count` joiner workgroups for this handle on
@@ -302,10 +313,12 @@ int coop_cotask_run(coop_rt* rt, const coop_cotask_cfg* cfg, coop_stream_t strea
 /* Start a host thread that, every period, asks the cooperative launch `h`
  * for cfg->groups workgroups (target = N - groups), runs the co-task on the
  * runtime's co-task stream, then restores the target and forks the
- * workgroups back (groups + engines - 1 joiners: the engine-balanced kill
- * can take up to engines - 1 more than asked; joiners beyond the target's
- * room leave at once). h may be NULL (co-tasks only). One injector per
- * runtime. */
+ * workgroups back. For BFS, SSSP, colouring, MIS and barrier launches the
+ * co-task's last workgroup reports the launch's M, and the injector forks
+ * N - M joiners less those of earlier forks not yet started; for the other
+ * kinds it forks groups + engines - 1 (the engine-balanced kill can take up
+ * to engines - 1 more than asked; joiners beyond the target's room leave at
+ * once). h may be NULL (co-tasks only). One injector per runtime. */
 int coop_injector_start(coop_rt* rt, coop_handle* h, const coop_cotask_cfg* cfg);
 /* Stop the injector thread and return its statistics. */
 int coop_injector_stop(coop_rt* rt, coop_cotask_stats* out);

@@ -88,6 +88,7 @@ struct Cfg {
     uint32_t engines;         // shader engines workgroups are dealt over (XCDs x engines per XCD)
     uint32_t ses;             // shader engines per XCD
     uint32_t slots_per_engine;  // workgroups of this kernel one shader engine holds at once
+    uint32_t join_window;     // joiners that may wait in the admission ring at once (<= kJoinCap - N)
 };
 
 // The shader engine this workgroup runs on, numbered XCD-major: the XCD
@@ -124,7 +125,9 @@ struct alignas(256) CtxCore {
     // ---- line: registration
     uint32_t ticket;          // start-up tickets
     uint32_t join_tail;       // next joiner slot
-    uint32_t _pj[62];
+    uint32_t join_full;       // joiners that found the admission ring full and left
+    uint32_t joined_grid;     // workgroups of joiner grids that started
+    uint32_t _pj[60];
     // ---- line: error and the host target as read by workgroup 0
     int32_t error;
     uint32_t T_seen;
@@ -246,6 +249,8 @@ struct BarrierLds {
     uint32_t flags;         // master step result (broadcast inside the master)
     uint32_t head, kmax, T;
     uint32_t my_new;                   // placed kill: the master's new id
+    uint32_t top_kill;                 // placed kill: no engine owes, the top W ids leave
+    uint32_t drain_span, drained;      // ring slots checked for given-up joiners, and how many lead
     uint32_t T_pre;                    // workgroup 0: host target read during the phase
     uint32_t valid[kMaxGroups / 32];   // admission: ring slots whose joiner was still waiting
     uint32_t xcnt[kMaxEngines];        // placed kill: members per engine, then victims per engine
@@ -261,16 +266,53 @@ __device__ inline void raise_error(CtxCore* c, int32_t err) {
                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Joiner admission entries: {slot:32 (lo) | epoch_lo:16 | id:16 (hi)}.
-// A joiner that gives up writes a "withdrawn" entry for its slot with a
-// compare-and-swap; the master admits with an exchange and skips a slot
-// whose previous value was that joiner's withdrawal. Both sides therefore
-// agree on whether the slot was admitted.
-__device__ __forceinline__ uint64_t withdrawn_entry(uint32_t slot) {
-    return (uint64_t)slot | (0xFFFFFFFFull << 32);
+// Joiner admission ring. Slot s (taken in arrival order from join_tail)
+// lives in entry s % kJoinCap as {slot:32 (lo) | tag:32 (hi)}; the tag is
+// an admission {epoch_lo:16 | id:16 (hi)} or one of the states below. A
+// joiner announces itself (waiting) with a compare-and-swap, and gives up by
+// turning its own waiting entry into withdrawn; the master turns a waiting
+// entry into an admission with a compare-and-swap and closes any other slot
+// it passes (consumed), so a slot counts as a member only if its joiner was
+// still waiting, and a joiner that announces too late sees that it was
+// passed. Nothing else bounds how many joiners take slots between two
+// admissions (under a co-task, surplus joiner workgroups the hardware starts
+// late take slots and withdraw while the target leaves no room), so a joiner
+// whose slot lies more than the ring's window ahead of the master's head
+// leaves at once without touching the ring: its entry may still belong to
+// an older slot. The window keeps one barrier's worth of slots (at most N)
+// back, so the entries of joiners admitted at the last barrier, whose final
+// ids they read after the release, are not reused under them; for the same
+// reason the master passes given-up slots without admitting (a drain) only
+// at barriers that admit nobody.
+constexpr uint32_t kTagWithdrawn = 0xFFFFFFFFu;
+constexpr uint32_t kTagWaiting = 0xFFFFFFFEu;
+constexpr uint32_t kTagConsumed = 0xFFFFFFFDu;
+constexpr uint32_t kDrainMin = 64;           // queued slots before the master drains given-up ones
+__device__ __forceinline__ uint64_t ring_entry(uint32_t slot, uint32_t tag) {
+    return (uint64_t)slot | ((uint64_t)tag << 32);
 }
 __device__ __forceinline__ uint64_t admit_entry(uint32_t slot, uint32_t epoch, uint32_t id) {
     return (uint64_t)slot | ((uint64_t)(epoch & 0xFFFFu) << 32) | ((uint64_t)id << 48);
+}
+__device__ __forceinline__ bool cas64(uint64_t* p, uint64_t& expected, uint64_t desired) {
+    return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Master side of one slot: admit its joiner as `id` if it is waiting, else
+// close the slot. Returns true if admitted. Terminates: every failed
+// compare-and-swap means the joiner moved its entry on (announced, or
+// withdrew), which it does at most twice.
+__device__ inline bool ring_admit(uint64_t* ent, uint32_t slot, uint32_t epoch, uint32_t id) {
+    uint64_t cur = __hip_atomic_load(ent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        if (cur == ring_entry(slot, kTagWithdrawn) || cur == ring_entry(slot, kTagConsumed)) return false;
+        if (cur == ring_entry(slot, kTagWaiting)) {
+            if (cas64(ent, cur, admit_entry(slot, epoch, id))) return true;
+        } else if (cas64(ent, cur, ring_entry(slot, kTagConsumed))) {
+            return false;   // not announced (yet, or ever): passed
+        }
+    }
 }
 
 // Wait for the release word to move past `epoch` (or abort/done). Returns
@@ -296,18 +338,29 @@ __device__ inline uint64_t wait_release(CtxCore* c, const Cfg cfg, uint32_t epoc
 
 // Joiner queue (thread 0 only): wait until admitted at a barrier, until
 // the kernel is done, or until giving the compute unit back because the
-// scheduler target leaves no room (host-driven schedule only) or the
-// watchdog expires.
+// scheduler target leaves no room (host-driven schedule only), the
+// admission ring is full or the watchdog expires.
 __device__ inline Member join_queue(Ctx* c, const Cfg cfg) {
     Member m{};
     m.alive = 0;
     const uint32_t slot = add_relaxed(&c->join_tail, 1u);
     uint64_t* ent = &c->join_entry[slot % kJoinCap];
+    if (slot - __hip_atomic_load(&c->join_head, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= cfg.join_window) {
+        add_relaxed(&c->join_full, 1u);
+        return m;
+    }
+    {
+        // announce (unless the master has passed the slot already)
+        uint64_t cur = __hip_atomic_load(ent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        while (!cas64(ent, cur, ring_entry(slot, kTagWaiting)))
+            if ((uint32_t)cur == slot) return m;
+    }
     const uint64_t t0 = now_ticks();
     for (uint32_t it = 0;; ++it) {
         const uint64_t e = __hip_atomic_load(ent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         uint64_t r = ld_relaxed64(&c->release);
-        if ((uint32_t)e == slot && (e >> 32) != 0xFFFFFFFFull) {
+        if (e != ring_entry(slot, kTagWaiting)) {
+            if ((e >> 32) >= kTagConsumed) return m;     // not ours to take (cannot happen after announcing)
             // admitted at epoch (e >> 32) & 0xFFFF: wait until that epoch's
             // release is visible, then read the final id (the master may
             // renumber before it publishes) and start after the fork point
@@ -334,8 +387,7 @@ __device__ inline Member join_queue(Ctx* c, const Cfg cfg) {
         if (!leave && now_ticks() - t0 > cfg.watchdog_ticks) leave = true;
         if (leave) {
             uint64_t expected = e;
-            if (__hip_atomic_compare_exchange_strong(ent, &expected, withdrawn_entry(slot), __ATOMIC_RELAXED,
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            if (cas64(ent, expected, ring_entry(slot, kTagWithdrawn)))
                 return m;            // withdrawn: the master will skip this slot
             continue;                // the master admitted us meanwhile: re-read
         }
@@ -366,6 +418,8 @@ __device__ inline Member register_member(Ctx* c, const Cfg cfg, bool plain, bool
             st_relaxed(&c->engine_of[0], engine_id(cfg.ses));
             return m;
         }
+    } else {
+        add_relaxed(&c->joined_grid, 1u);
     }
     return join_queue(c, cfg);
 }
@@ -395,7 +449,7 @@ __device__ __forceinline__ MasterPre master_prefetch(C* c, const Cfg cfg) {
     p.err = ld_relaxed_i(&c->error);
     p.tail = Coop ? ld_relaxed(&c->join_tail) : 0u;
     p.T_seen = (Coop && cfg.host) ? ld_relaxed(&c->T_seen) : 0u;
-    p.join_head = c->join_head;
+    p.join_head = ld_relaxed(&c->join_head);
     p.T_dev = c->T_dev;
     p.nb = c->barriers;
     p.kills = c->kills;
@@ -450,11 +504,27 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
         b.kmax = kmax;
         b.T = T;
         b.flags = flags;
+        // with no room, pass the slots at the head whose joiners have given
+        // up already, so that they do not fill the ring's window (never at
+        // a barrier that admits: see the ring's comment)
+        const uint32_t span = ready < blockDim.x ? ready : blockDim.x;
+        b.drain_span = (live && kmax == 0 && span >= kDrainMin) ? span : 0u;
     }
     uint32_t admitted = 0;
     if constexpr (Coop) {
         __syncthreads();
         const uint32_t kmax = b.kmax, head = b.head;
+        if (b.drain_span) {
+            if (threadIdx.x == 0) b.drained = b.drain_span;
+            __syncthreads();
+            if (threadIdx.x < b.drain_span) {
+                const uint32_t slot = head + threadIdx.x;
+                const uint64_t e = __hip_atomic_load(&c->join_entry[slot % kJoinCap], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                if (e != ring_entry(slot, kTagWithdrawn)) atomicMin(&b.drained, threadIdx.x);
+            }
+            __syncthreads();
+        }
         if (kmax) {
             const uint32_t nwords = (kmax + 31) / 32;
             for (uint32_t w = threadIdx.x; w < nwords; w += blockDim.x) b.valid[w] = 0;
@@ -462,13 +532,11 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
             // fork: admit ring slots head .. head+kmax-1 as ids M .. M+kmax-1
             for (uint32_t j = threadIdx.x; j < kmax; j += blockDim.x) {
                 const uint32_t slot = head + j;
-                const uint64_t prev = __hip_atomic_exchange(&c->join_entry[slot % kJoinCap],
-                                                            admit_entry(slot, ne, m.M + j), __ATOMIC_RELAXED,
-                                                            __HIP_MEMORY_SCOPE_AGENT);
-                if (prev != withdrawn_entry(slot)) atomicOr(&b.valid[j / 32], 1u << (j % 32));
+                if (ring_admit(&c->join_entry[slot % kJoinCap], slot, ne, m.M + j))
+                    atomicOr(&b.valid[j / 32], 1u << (j % 32));
             }
             __syncthreads();
-            // withdrawn slots leave holes: renumber the admitted ones densely
+            // passed slots leave holes: renumber the admitted ones densely
             // (a joiner reads its final id after the release is published)
             for (uint32_t j = threadIdx.x; j < kmax; j += blockDim.x) {
                 const uint32_t wj = j / 32, bj = j % 32;
@@ -501,7 +569,13 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
     // A host-driven target asks for compute units for another kernel, whose
     // workgroups the hardware deals round-robin over the XCDs and their
     // shader engines: choose the victims so that every engine frees its
-    // share (then renumber the rest densely).
+    // share (then renumber the rest densely). The share is that of all
+    // N - T units the other kernel needs, not of this barrier's surplus:
+    // units already idle have usually been taken by the other kernel's
+    // first workgroups, so an engine keeps at most slots - ceil((N - T) /
+    // engines) of ours. The regular barrier takes one victim, on the engine
+    // that owes most. If no engine owes (a launch smaller than the device),
+    // the top ids leave as in the plain kill.
     bool renum = false;
     uint32_t Mn_sel = 0, my_new = m.id;
     if constexpr (Coop) {
@@ -514,7 +588,8 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
             for (uint32_t t = threadIdx.x; t < M2; t += blockDim.x) atomicAdd(&b.xcnt[b.xcd[t] % kMaxEngines], 1u);
             __syncthreads();
             if (threadIdx.x == 0) {
-                const uint32_t need = (W + cfg.engines - 1) / cfg.engines;
+                const uint32_t want_free = cfg.N > b.T ? cfg.N - b.T : 0u;
+                const uint32_t need = (want_free + cfg.engines - 1) / cfg.engines;
                 uint32_t best = kMaxEngines, best_k = 0;
                 for (uint32_t x = 0; x < kMaxEngines; ++x) {
                     const uint32_t cnt = b.xcnt[x];
@@ -529,6 +604,7 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
                 }
                 if (cfg.mode & kModeRegular)           // one victim: on the engine that owes most
                     for (uint32_t x = 0; x < kMaxEngines; ++x) b.xcnt[x] = x == best ? 1u : 0u;
+                b.top_kill = best_k == 0 ? 1u : 0u;
             }
             __syncthreads();
             // id t is a victim if fewer than xcnt[its XCD] higher ids share its XCD
@@ -540,7 +616,7 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
                     const uint32_t x = b.xcd[t];
                     uint32_t above = 0;
                     for (uint32_t u = t + 1; u < M2; ++u) above += b.xcd[u] == x ? 1u : 0u;
-                    alive = t == 0 || above >= b.xcnt[x % kMaxEngines];
+                    alive = b.top_kill ? t < M2 - W : (t == 0 || above >= b.xcnt[x % kMaxEngines]);
                 }
                 const uint64_t bal = __ballot(alive);
                 if ((threadIdx.x & 63) == 0) b.wsum[threadIdx.x / 64] = (uint32_t)__popcll(bal);
@@ -604,7 +680,8 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
             const uint32_t Wk = renum ? M2 - Mn_sel : W;
             Mn = M2 - Wk;
             if (renum) flags |= kFlagRenum;
-            if (b.kmax) c->join_head = b.head + b.kmax;
+            if (b.kmax) st_relaxed(&c->join_head, b.head + b.kmax);
+            else if (b.drain_span && b.drained) st_relaxed(&c->join_head, b.head + b.drained);
             if (cfg.mode & kModeRandomSched) c->T_dev = T_dev;
             if (admitted) c->forks = forks + admitted;
             if (Wk) c->kills = kills + Wk;

@@ -83,7 +83,7 @@ class coop_launch_opts(ctypes.Structure):
         ("lds_bytes", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("heavy_threshold", ctypes.c_uint32),
         ("strip", ctypes.c_uint32), ("startup_wait_ns", ctypes.c_uint32), ("sched_seed", ctypes.c_uint64),
         ("sched_p", ctypes.c_double), ("watchdog_ns", ctypes.c_uint64),
-        ("d_trace", ctypes.c_void_p), ("trace_cap", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
+        ("d_trace", ctypes.c_void_p), ("trace_cap", ctypes.c_uint32), ("join_window", ctypes.c_uint32),
         ("d_wgtrace", ctypes.c_void_p),
     ]
 
@@ -96,7 +96,7 @@ class coop_stats(ctypes.Structure):
         ("levels", ctypes.c_uint32), ("kernel_ms", ctypes.c_double), ("device_ms", ctypes.c_double),
         ("arcs", ctypes.c_uint64), ("rows", ctypes.c_uint64), ("found", ctypes.c_uint64),
         ("bitmap_words", ctypes.c_uint64), ("td_levels", ctypes.c_uint32), ("bu_levels", ctypes.c_uint32),
-        ("heavy_phases", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+        ("heavy_phases", ctypes.c_uint32), ("join_full", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:
@@ -107,7 +107,8 @@ class coop_device_info(ctypes.Structure):
     _fields_ = [
         ("device", ctypes.c_int), ("compute_units", ctypes.c_uint32), ("lds_per_cu", ctypes.c_uint32),
         ("max_lds_per_group", ctypes.c_uint32), ("wall_clock_khz", ctypes.c_uint32),
-        ("hbm_bytes", ctypes.c_uint64), ("arch", ctypes.c_char * 64),
+        ("hbm_bytes", ctypes.c_uint64), ("arch", ctypes.c_char * 64), ("xcds", ctypes.c_uint32),
+        ("shader_engines", ctypes.c_uint32),
     ]
 
 

@@ -144,7 +144,10 @@ struct CotaskArgs {
     uint64_t busy_ticks;       // how long each workgroup holds its compute unit
     uint32_t* started;         // device counter of started workgroups
     uint32_t* finished;        // device counter of finished workgroups
-    uint64_t* host_stamp;      // pinned host words: [0] all started, [1] all done (wall clock)
+    uint64_t* host_stamp;      // pinned host words: [0] all started, [1] all done (wall clock),
+                               // [2] the resizable launch's M and joiner-grid starts when done
+    const uint64_t* release;   // that launch's release word, or null
+    const uint32_t* joined;    // that launch's count of started joiner-grid workgroups
     uint32_t nwg;
 };
 

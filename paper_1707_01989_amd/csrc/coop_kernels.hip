@@ -284,8 +284,18 @@ __global__ void __launch_bounds__(256) cotask_kernel(CotaskArgs a) {
             __hip_atomic_store(&a.host_stamp[0], t0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         while (now_ticks() - t0 < a.busy_ticks) __builtin_amdgcn_s_sleep(8);
         const uint32_t f = add_relaxed(a.finished, 1u);
-        if (f + 1 == a.nwg && a.host_stamp)
+        if (f + 1 == a.nwg && a.host_stamp) {
+            if (a.release) {
+                // what the resizable launch looks like while the co-task
+                // still holds its compute units: the host forks joiners
+                // for exactly the units it gives back
+                const uint64_t r = ld_relaxed64(a.release);
+                const uint32_t j = ld_relaxed(a.joined);
+                __hip_atomic_store(&a.host_stamp[2], (uint64_t)rel_M(r) | ((uint64_t)j << 32), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
+            }
             __hip_atomic_store(&a.host_stamp[1], now_ticks(), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
     }
     __syncthreads();
 }

@@ -98,6 +98,7 @@ struct coop_handle {
     hipStream_t stream = nullptr;
     hipEvent_t ev_init = nullptr, ev_start = nullptr, ev_end = nullptr, ev_join = nullptr;
     bool joined = false;
+    uint32_t forked = 0;                 // joiner-grid workgroups launched
     coop::BfsArgs bfs{};
     coop::SsspArgs sssp{};
     coop::ColorArgs color{};
@@ -335,6 +336,8 @@ int begin_launch(coop_rt* rt, const coop_launch_opts* o, const Sizing& sz, int k
     cfg.ses = rt->ses;
     cfg.engines = rt->xcds * rt->ses;
     cfg.slots_per_engine = std::max<uint32_t>(1, sz.resident / std::max<uint32_t>(1, cfg.engines));
+    cfg.join_window = coop::kJoinCap - sz.grid;
+    if (o && o->join_window) cfg.join_window = std::min(cfg.join_window, std::max(o->join_window, sz.grid));
     hipError_t e = coop::launch_init_ctx(h->ctx, h->work, stream);
     if (e != hipSuccess) { handle_free(h); return hip_fail(rt, e); }
     *hout = h;
@@ -538,6 +541,8 @@ int coop_device_query(coop_rt* rt, coop_device_info* out) {
     out->wall_clock_khz = rt->wall_khz;
     out->hbm_bytes = (uint64_t)rt->props.totalGlobalMem;
     std::snprintf(out->arch, sizeof(out->arch), "%s", rt->props.gcnArchName);
+    out->xcds = rt->xcds;
+    out->shader_engines = rt->ses;
     return COOP_OK;
 }
 
@@ -879,7 +884,7 @@ int coop_wait(coop_handle* h, coop_stats* stats) {
             stats->td_levels = w.x.td_levels;
             stats->bu_levels = w.x.bu_levels;
             stats->heavy_phases = w.x.heavy_phases;
-            stats->reserved = 0;
+            stats->join_full = c.join_full;
         }
     }
     std::lock_guard<std::recursive_mutex> lk(rt->mu);
@@ -906,6 +911,7 @@ int coop_fork_groups(coop_handle* h, uint32_t count) {
     HIP_TRY(rt, relaunch(h, true, count, rt->joiner_stream));
     HIP_TRY(rt, hipEventRecord(h->ev_join, rt->joiner_stream));
     h->joined = true;
+    h->forked += count;
     return COOP_OK;
 }
 
@@ -1660,8 +1666,13 @@ static int cotask_once(coop_rt* rt, const coop_cotask_cfg* cfg, hipStream_t s, c
     a.finished = rt->d_cot + 1;
     a.host_stamp = rt->h_stamp;
     a.nwg = cfg->groups;
+    if (h && h->kind >= COOP_KERNEL_BFS && h->kind <= COOP_KERNEL_BARRIER) {
+        a.release = &h->ctx->release;
+        a.joined = &h->ctx->joined_grid;
+    }
     __atomic_store_n(&rt->h_stamp[0], 0ull, __ATOMIC_RELEASE);
     __atomic_store_n(&rt->h_stamp[1], 0ull, __ATOMIC_RELEASE);
+    __atomic_store_n(&rt->h_stamp[2], ~0ull, __ATOMIC_RELEASE);
     HIP_TRY(rt, hipMemsetAsync(rt->d_cot, 0, 8, s));
     const double t_req = now_ms();
     if (h) coop_set_target(h, h->grid > cfg->groups ? h->grid - cfg->groups : 1);
@@ -1729,11 +1740,23 @@ int coop_injector_start(coop_rt* rt, coop_handle* h, const coop_cotask_cfg* cfg)
             double lat = 0, gat = 0, busy = 0, t_req = t, t_end = t;
             int rc = cotask_once(rt, &cfg, rt->cotask_stream, h, &lat, &gat, &busy, &t_req, &t_end);
             if (rc == COOP_OK && h && !handle_done(h)) {
-                // the engine-balanced kill may have taken up to engines - 1
-                // more than the co-task asked for; joiners beyond the room
-                // the target leaves give their compute unit back at once
-                const uint32_t extra = h->cfg.engines > 1 ? h->cfg.engines - 1 : 0u;
-                rc = coop_fork_groups(h, std::min<uint32_t>(cfg.groups + extra, h->grid));
+                // fork joiners for the compute units the launch gave up:
+                // N - M as the co-task saw it when done, less joiner
+                // workgroups of earlier forks that have not started yet
+                // (they take those units first). Launches that do not
+                // report M: the co-task's groups plus what the engine-
+                // balanced kill may have taken beyond them; joiners beyond
+                // the room the target leaves give their unit back at once.
+                const uint64_t seen = __atomic_load_n(&rt->h_stamp[2], __ATOMIC_ACQUIRE);
+                uint32_t n;
+                if (seen != ~0ull) {
+                    const uint32_t M = (uint32_t)seen, started = (uint32_t)(seen >> 32);
+                    const uint32_t pending = h->forked > started ? h->forked - started : 0u;
+                    n = h->grid > M + pending ? h->grid - M - pending : 0u;
+                } else {
+                    n = cfg.groups + (h->cfg.engines > 1 ? h->cfg.engines - 1 : 0u);
+                }
+                rc = coop_fork_groups(h, std::min<uint32_t>(n, h->grid));
             }
             rt->inj_setup_max = std::max(rt->inj_setup_max, t_req - t);
             rt->inj_restore_max = std::max(rt->inj_restore_max, now_ms() - t_end);

@@ -391,3 +391,42 @@ def test_regular_barrier_under_cotasks(rt, coop_mod, gg):
     # least that many kill barriers per co-task, the query barrier one
     assert res["regular"]["resizes"] >= res["query"]["resizes"]
     dg.release()
+
+
+@pytest.mark.parametrize("window", [0, 300])
+def test_admission_ring_flood(rt, coop_mod, gg, window):
+    """Far more joiner workgroups than the admission ring holds (12000
+    against 8192 entries) take slots and give up while the target leaves no
+    room, the state surplus joiners reach under co-tasks. A joiner whose
+    slot lies beyond the ring's window leaves without touching it, the
+    master admits only joiners still waiting, and the levels match the
+    oracle. window=300 (just above N) makes a full ring the common case; 0
+    is the default window (8192 - N)."""
+    import time
+    import torch
+    c = coop_mod
+    g = gg.rmat(18, 16, seed=3)
+    dg = rt.graph(g)
+    roots = np.resize(gg.sources(g, 3, 16), 2000).astype(np.uint32)
+    d_roots = rt._roots(roots)
+    lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    cus = rt.info["compute_units"]
+    o = c.make_opts(c.COOP_MODE_COOP, flags=c.COOP_F_HOST_SCHEDULE, join_window=window)
+    say(f"bfs rmat18 x{len(roots)}: 12000 joiners at half target, join_window={window}")
+    h = c.coop_bfs(rt.rt, dg.handle, d_roots, len(roots), lv, 0, o)
+    time.sleep(0.01)
+    c.coop_set_target(h, cus // 2)
+    time.sleep(0.01)
+    c.coop_fork_groups(h, 12000)
+    time.sleep(0.06)
+    c.coop_set_target(h, cus)
+    c.coop_fork_groups(h, cus // 2)
+    rc, st = c.coop_wait(h)
+    say(f"  kernel {st['kernel_ms']:.1f} ms kills={st['kills']} forks={st['forks']} "
+        f"join_full={st['join_full']} min_groups={st['min_groups']}")
+    assert rc == 0, c.coop_strerror(rc)
+    assert np.array_equal(as_u32(lv), oracle.bfs(g, int(roots[-1])))
+    assert st["kills"] > 0 and st["min_groups"] <= cus // 2
+    if window:
+        assert st["join_full"] > 0
+    dg.release()
