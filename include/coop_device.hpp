@@ -94,11 +94,15 @@ struct Cfg {
 // The shader engine this workgroup runs on, numbered XCD-major: the XCD
 // from hardware register XCC_ID (bits 3:0) and the engine inside it from
 // HW_ID (bits 15:13). The hardware deals a kernel's workgroups round-robin
-// over the XCDs and, inside each XCD, over its shader engines.
+// over the XCDs and, inside each XCD, over its shader engines. `ses` is the
+// engine count per XCD the runtime observed; an engine index beyond it is
+// folded onto the last one, so that id / ses is always the XCD (the arrival
+// by XCD counts members with it).
 __device__ __forceinline__ uint32_t engine_id(uint32_t ses) {
     const uint32_t xcc = __builtin_amdgcn_s_getreg((3u << 11) | (0u << 6) | 20u) & 0xFu;
     const uint32_t se = (__builtin_amdgcn_s_getreg((31u << 11) | (0u << 6) | 4u) >> 13) & 7u;
-    return xcc * ses + se;
+    const uint32_t n = ses ? ses : 1u;
+    return xcc * n + (se < n ? se : n - 1u);
 }
 constexpr uint32_t kMaxEngines = 64;
 constexpr uint32_t kMaxXcds = 16;

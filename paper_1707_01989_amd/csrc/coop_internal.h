@@ -366,7 +366,8 @@ hipError_t launch_cotask(const CotaskArgs& a, uint32_t block, uint32_t lds_bytes
 uint32_t kernel_lds_bytes();   // LDS the traversal kernels need at least
 // out[2g] = XCD, out[2g+1] = shader engine of workgroup g, for `groups`
 // one-wave workgroups
-hipError_t launch_place_probe(uint32_t* out, uint32_t groups, hipStream_t s);
+hipError_t launch_place_probe(uint32_t* out, uint32_t groups, uint32_t lds_bytes, uint64_t hold_ticks,
+                              hipStream_t s);
 uint32_t kernel_lds_bytes_for(uint32_t block);   // ... with `block` threads per workgroup
 
 }  // namespace coop

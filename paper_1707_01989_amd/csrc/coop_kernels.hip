@@ -244,11 +244,19 @@ __global__ void init_ctx_kernel(Ctx* c, Work* w) {
     }
 }
 
-// Every workgroup records its XCD and shader engine (the runtime counts them).
-__global__ void place_probe_kernel(uint32_t* out) {
+// Every workgroup records its XCD and shader engine (the runtime counts
+// them). The launch asks for more than half a CU's LDS, so a CU holds one
+// probe workgroup, and each holds its CU for `hold` wall-clock ticks: the
+// first grid-full lands on every CU, hence on every shader engine, instead
+// of a few fast CUs taking all of them.
+__global__ void place_probe_kernel(uint32_t* out, uint64_t hold) {
+    extern __shared__ uint32_t probe_lds[];
     if (threadIdx.x == 0) {
+        const uint64_t t0 = now_ticks();
+        probe_lds[0] = blockIdx.x;
         out[2 * blockIdx.x] = __builtin_amdgcn_s_getreg((3u << 11) | (0u << 6) | 20u) & 0xFu;
         out[2 * blockIdx.x + 1] = (__builtin_amdgcn_s_getreg((31u << 11) | (0u << 6) | 4u) >> 13) & 7u;
+        while (now_ticks() - t0 < hold) __builtin_amdgcn_s_sleep(8);
     }
 }
 
@@ -304,8 +312,11 @@ namespace coop {
 
 uint32_t kernel_lds_bytes() { return (uint32_t)sizeof(BlockLds); }
 
-hipError_t launch_place_probe(uint32_t* out, uint32_t groups, hipStream_t s) {
-    hipLaunchKernelGGL(place_probe_kernel, dim3(groups), dim3(64), 0, s, out);
+hipError_t launch_place_probe(uint32_t* out, uint32_t groups, uint32_t lds_bytes, uint64_t hold_ticks,
+                              hipStream_t s) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(place_probe_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    hipLaunchKernelGGL(place_probe_kernel, dim3(groups), dim3(64), lds_bytes, s, out, hold_ticks);
     return hipGetLastError();
 }
 

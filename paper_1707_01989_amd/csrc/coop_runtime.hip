@@ -481,11 +481,14 @@ int coop_init(int device, coop_rt** out) {
                                            hipHostMallocCoherent | hipHostMallocMapped);
     if (e == hipSuccess) {
         // count the XCDs and the shader engines per XCD from where the
-        // workgroups of a 4x oversubscribed grid land
-        const uint32_t groups = 4u * (uint32_t)std::max(1, rt->props.multiProcessorCount);
+        // workgroups of a 2x oversubscribed grid land, one per CU at a time,
+        // each holding its CU for 50 us
+        const uint32_t groups = 2u * (uint32_t)std::max(1, rt->props.multiProcessorCount);
+        const uint32_t lds = (uint32_t)rt->props.maxSharedMemoryPerMultiProcessor / 2 + 1024;
         uint32_t* d = nullptr;
         e = hipMalloc(&d, (size_t)groups * 8);
-        if (e == hipSuccess) e = coop::launch_place_probe(d, groups, nullptr);
+        if (e == hipSuccess)
+            e = coop::launch_place_probe(d, groups, lds, 50ull * rt->wall_khz / 1000ull + 1, nullptr);
         std::vector<uint32_t> h((size_t)groups * 2, 0);
         if (e == hipSuccess) e = hipMemcpy(h.data(), d, (size_t)groups * 8, hipMemcpyDeviceToHost);
         if (d) (void)hipFree(d);
