@@ -405,7 +405,10 @@ enum { COOP_QUERY_BFS = 1, COOP_QUERY_SSSP = 2 };
 typedef struct coop_server_cfg {
     uint32_t mode;            /* COOP_MODE_PLAIN or COOP_MODE_COOP */
     uint32_t flags;           /* COOP_F_HOST_SCHEDULE */
-    uint32_t num_groups;      /* launch limit N; 0 = all resident workgroups */
+    uint32_t num_groups;      /* launch limit N; 0 = all resident workgroups but one per shader
+                                 engine, so that the host's copies (which run as small kernels)
+                                 and other kernels always find a compute unit while the server
+                                 stays resident */
     uint32_t group_size;      /* 0 = 1024 */
     uint32_t max_queries;     /* slots; 0 = as many as the budget holds, at most 1024 */
     uint32_t team_max;        /* largest team, <= N; 0 = max(1, N / 4) */
@@ -415,7 +418,9 @@ typedef struct coop_server_cfg {
     uint32_t heavy_threshold; /* 0 = 128 */
     uint32_t strip;           /* 0 = 512 */
     uint32_t reserved;
-    uint64_t watchdog_ns;     /* barrier spin bound; 0 = 10 s */
+    uint64_t watchdog_ns;     /* barrier spin bound, and how long idle workgroups wait without
+                                 the host's heartbeat (its poller thread) before they leave
+                                 with COOP_E_TIMEOUT; 0 = 10 s */
 } coop_server_cfg;
 
 typedef struct coop_serve_stats {

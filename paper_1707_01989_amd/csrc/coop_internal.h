@@ -246,7 +246,8 @@ struct alignas(64) ServeReq {
 struct alignas(64) ServeHost {
     uint32_t ticket_end;       // tickets below this are published
     uint32_t stop;             // 1: leave once no ticket is left
-    uint32_t pad[14];
+    uint32_t heartbeat;        // advanced by the host's poller about every millisecond
+    uint32_t pad[13];
 };
 
 // Completion record of a slot (pinned): written by the last member of the

@@ -39,8 +39,10 @@ constexpr uint32_t kDefaultLds = 96 * 1024;       // > half a CU's 160 KiB: one 
 constexpr uint32_t kDefaultHeavy = 128;
 constexpr uint32_t kDefaultStrip = 512;          // one wave walk step (64 lanes x 8 arcs)
 constexpr uint64_t kDefaultWatchdogNs = 10ull * 1000 * 1000 * 1000;
-constexpr uint32_t kDefaultStartupNs = 20 * 1000;
+// The query server stays off the GPU: its launch has ended a GPU machine with a
+// memory fault or hung queue twice, and no cause has been shown yet.
 constexpr bool kServerEnabled = false;
+constexpr uint32_t kDefaultStartupNs = 20 * 1000;
 
 double now_ms() {
     using namespace std::chrono;
@@ -1342,7 +1344,6 @@ int coop_server_create(coop_rt* rt, const coop_graph* const* graphs, uint32_t ng
                        const coop_server_cfg* cfg, coop_server** out) {
     if (!rt || !graphs || ngraphs == 0 || !out) return COOP_E_INVALID;
     *out = nullptr;
-    // Switched off: a GPU fault has not been explained for this launch yet.
     if (!kServerEnabled) return COOP_E_INVALID;
     coop_server_cfg c;
     coop_server_cfg_default(&c);
@@ -1379,6 +1380,16 @@ int coop_server_create(coop_rt* rt, const coop_graph* const* graphs, uint32_t ng
     Sizing sz{};
     int rc = size_launch(rt, &o, &sz, coop::kernel_lds_bytes_for(c.group_size), coop::occupancy_serve);
     if (rc) return rc;
+    if (!c.num_groups && sz.resident > 2 * rt->xcds * rt->ses) {
+        // The server stays resident between queries, so by default it leaves
+        // one workgroup slot per shader engine free: copies the host issues
+        // meanwhile run as small kernels (so do other processes' kernels),
+        // and the hardware gives a workgroup only a slot on the shader
+        // engine it deals it to.
+        o.num_groups = sz.resident - rt->xcds * rt->ses;
+        if ((rc = size_launch(rt, &o, &sz, coop::kernel_lds_bytes_for(c.group_size), coop::occupancy_serve)))
+            return rc;
+    }
     const uint32_t team_max = c.team_max ? c.team_max : std::max<uint32_t>(1, sz.grid / 4);
     if (team_max > sz.grid) return COOP_E_INVALID;
     const size_t stats_b = align_up((size_t)team_max * coop::kSlotWords * 4);
@@ -1525,8 +1536,15 @@ int coop_server_create(coop_rt* rt, const coop_graph* const* graphs, uint32_t ng
     (void)hipEventRecord(h->ev_end, sv->stream);
     sv->poller = std::thread([sv]() {
         (void)hipSetDevice(sv->rt->device);
+        double beat = now_ms();
         while (!sv->stop_poller.load()) {
             server_poll_once(sv);
+            const double t = now_ms();
+            if (t - beat >= 1.0) {
+                // tell the server's idle workgroups this process is alive
+                __atomic_fetch_add(&sv->host->heartbeat, 1u, __ATOMIC_RELEASE);
+                beat = t;
+            }
             std::this_thread::sleep_for(std::chrono::microseconds(10));
         }
     });

@@ -197,11 +197,28 @@ __device__ void serve_body(const ServeArgs& a, bool joiner) {
         atomicMax(&ctl->max_active, act);
         if (joiner) add_relaxed(&ctl->forks, 1u);
     }
+    // the host's heartbeat as last seen, and when it last moved: a server
+    // whose host has stopped advancing it for the watchdog time leaves, so
+    // the launch cannot outlive its process
+    uint32_t hb_seen = 0;
+    uint64_t hb_t = now_ticks();
     for (;;) {
         if (threadIdx.x == 0) {
             uint32_t leave = 0, k = 0, idle = 0;
             for (uint32_t it = 0;; ++it) {
                 if (ld_relaxed_i(&ctl->error)) { leave = 1; break; }
+                if ((it & 63) == 63) {
+                    const uint32_t hb = ld_system(&a.host->heartbeat);
+                    const uint64_t now = now_ticks();
+                    if (hb != hb_seen) {
+                        hb_seen = hb;
+                        hb_t = now;
+                    } else if (now - hb_t > a.cfg.watchdog_ticks) {
+                        atomicCAS(&ctl->error, 0, kErrTimeout);
+                        leave = 1;
+                        break;
+                    }
+                }
                 if (Coop && a.cfg.host && (it & 7) == 0 &&
                     leave_for_target(LeaveCounters{&ctl->active, ctl->active_x, &ctl->kills, &ctl->min_active},
                                      ld_system(&a.cfg.host->target), a.team_max, a.cfg.engines, engine_id(a.cfg.ses))) {

@@ -11,11 +11,15 @@ import pytest
 import oracle
 from tests.conftest import gpu_available
 
+# every wait below is bounded well inside the test's own time limit, so a
+# stuck query fails the test and coop_server_destroy still stops the launch
 pytestmark = [
     pytest.mark.gpu,
-    pytest.mark.skip(reason="the first GPU run of a suite containing these tests ended the box with a GPU "
-                            "fault or hung queue; the cause is not yet shown, so the server stays off the GPU "
-                            "(coop_server_create refuses to start) until it is"),
+    pytest.mark.timeout(400),
+    pytest.mark.skip(reason="two GPU runs of these tests ended the box with a GPU memory fault or hung queue "
+                            "(the second after a host copy that could not find a free CU was ruled out); the "
+                            "cause is not shown yet, so the server stays off the GPU (coop_server_create "
+                            "refuses to start) until it is"),
 ]
 
 
@@ -82,7 +86,7 @@ def run_queries(c, srv, dgs, qs, spacing_s=0.0):
             time.sleep(spacing_s)
     lats = []
     for t in tickets:
-        rc, lat = c.coop_server_wait(srv, t, 60000.0)
+        rc, lat = c.coop_server_wait(srv, t, 20000.0)
         assert rc == 0, c.coop_strerror(rc)
         lats.append(lat)
     return [o.cpu().numpy().view(np.uint32) for o in outs], lats
@@ -153,7 +157,7 @@ def test_serve_poisson_with_target_changes(rt, coop_mod, graphs):
                 outs.append(out)
                 time.sleep(float(rng.exponential(0.0005)))
             for t in tickets:
-                rc, _ = c.coop_server_wait(srv, t, 60000.0)
+                rc, _ = c.coop_server_wait(srv, t, 20000.0)
                 assert rc == 0, c.coop_strerror(rc)
         finally:
             stop.set()
@@ -209,7 +213,7 @@ def test_serve_rejects_bad_queries(rt, coop_mod, graphs, gg):
         with pytest.raises(c.CoopError):
             c.coop_server_submit(srv, dgs[0].handle, 9, 0, out)
         t = c.coop_server_submit(srv, unweighted.handle, c.COOP_QUERY_BFS, 3, out)
-        rc, _ = c.coop_server_wait(srv, t)
+        rc, _ = c.coop_server_wait(srv, t, 20000.0)
         assert rc == 0
         assert np.array_equal(out.cpu().numpy().view(np.uint32)[:100], oracle.bfs(gg.er(100, 4, 1), 3))
     finally:
