@@ -105,6 +105,7 @@ __device__ __forceinline__ uint32_t engine_id(uint32_t ses) {
     return xcc * n + (se < n ? se : n - 1u);
 }
 constexpr uint32_t kMaxEngines = 64;
+constexpr uint32_t kRelayThread = 64;        // first lane of the second wave
 constexpr uint32_t kMaxXcds = 16;
 
 __device__ __forceinline__ uint32_t xcc_id() { return __builtin_amdgcn_s_getreg((3u << 11) | (0u << 6) | 20u) & 0xFu; }
@@ -146,7 +147,7 @@ struct alignas(256) CtxCore {
     uint32_t min_M;
     uint32_t max_M;
     uint32_t final_M;
-    uint32_t _pm0;
+    uint32_t tail_prev;       // join_tail as the previous barrier's master read it
     uint64_t t_start;
     uint64_t t_end;
     uint32_t _pm[50];
@@ -255,7 +256,7 @@ struct BarrierLds {
     uint32_t my_new;                   // placed kill: the master's new id
     uint32_t top_kill;                 // placed kill: no engine owes, the top W ids leave
     uint32_t drain_span, drained;      // ring slots checked for given-up joiners, and how many lead
-    uint32_t T_pre;                    // workgroup 0: host target read during the phase
+    uint32_t cut, tail_prev;           // admission: slots taken before the first new unannounced one
     uint32_t valid[kMaxGroups / 32];   // admission: ring slots whose joiner was still waiting
     uint32_t xcnt[kMaxEngines];        // placed kill: members per engine, then victims per engine
     uint32_t wsum[kMaxWaves + 1];      // placed kill: survivors per wave of ids
@@ -444,15 +445,19 @@ __device__ inline void startup_wait(Ctx* c, const Cfg cfg) {
 // flags it returns.
 struct MasterPre {
     int32_t err;
-    uint32_t tail, T_seen, join_head, T_dev, nb, kills, forks, resizes, min_M, max_M;
+    uint32_t tail, T_seen, join_head, T_dev, nb, kills, forks, resizes, min_M, max_M, tail_prev;
 };
 
 template <bool Coop, class C>
-__device__ __forceinline__ MasterPre master_prefetch(C* c, const Cfg cfg) {
+__device__ __forceinline__ MasterPre master_prefetch(C* c, const Cfg cfg, bool relay_self) {
     MasterPre p;
     p.err = ld_relaxed_i(&c->error);
     p.tail = Coop ? ld_relaxed(&c->join_tail) : 0u;
-    p.T_seen = (Coop && cfg.host) ? ld_relaxed(&c->T_seen) : 0u;
+    // the target workgroup 0 relayed while it waited; when it has nobody
+    // to wait for (M = 1) it reads the host word here, the PCIe round trip
+    // overlapping the algorithm's master step (with M > 1 a barrier that
+    // workgroup 0 masters uses the value of the one before)
+    p.T_seen = (Coop && cfg.host) ? (relay_self ? ld_system(&cfg.host->target) : ld_relaxed(&c->T_seen)) : 0u;
     p.join_head = ld_relaxed(&c->join_head);
     p.T_dev = c->T_dev;
     p.nb = c->barriers;
@@ -461,6 +466,7 @@ __device__ __forceinline__ MasterPre master_prefetch(C* c, const Cfg cfg) {
     p.resizes = c->resizes;
     p.min_M = c->min_M;
     p.max_M = c->max_M;
+    p.tail_prev = c->tail_prev;
     return p;
 }
 
@@ -508,6 +514,7 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
         b.kmax = kmax;
         b.T = T;
         b.flags = flags;
+        b.tail_prev = pre.tail_prev;
         // with no room, pass the slots at the head whose joiners have given
         // up already, so that they do not fill the ring's window (never at
         // a barrier that admits: see the ring's comment)
@@ -530,11 +537,27 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
             __syncthreads();
         }
         if (kmax) {
-            const uint32_t nwords = (kmax + 31) / 32;
-            for (uint32_t w = threadIdx.x; w < nwords; w += blockDim.x) b.valid[w] = 0;
+            // a slot taken since the previous barrier whose joiner has not
+            // announced itself yet ends this barrier's admissions (it will
+            // announce within moments); an older unannounced slot belongs to
+            // a joiner that left beyond the window and is closed
+            if (threadIdx.x == 0) b.cut = kmax;
+            const uint32_t nwords0 = (kmax + 31) / 32;
+            for (uint32_t w = threadIdx.x; w < nwords0; w += blockDim.x) b.valid[w] = 0;
             __syncthreads();
-            // fork: admit ring slots head .. head+kmax-1 as ids M .. M+kmax-1
             for (uint32_t j = threadIdx.x; j < kmax; j += blockDim.x) {
+                const uint32_t slot = head + j;
+                const uint64_t e = __hip_atomic_load(&c->join_entry[slot % kJoinCap], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                const bool known = e == ring_entry(slot, kTagWaiting) || e == ring_entry(slot, kTagWithdrawn) ||
+                                   e == ring_entry(slot, kTagConsumed);
+                if (!known && (int32_t)(slot - b.tail_prev) >= 0) atomicMin(&b.cut, j);
+            }
+            __syncthreads();
+            const uint32_t kcut = b.cut;
+            const uint32_t nwords = (kcut + 31) / 32;
+            // fork: admit ring slots head .. head+kcut-1 as ids M .. M+kcut-1
+            for (uint32_t j = threadIdx.x; j < kcut; j += blockDim.x) {
                 const uint32_t slot = head + j;
                 if (ring_admit(&c->join_entry[slot % kJoinCap], slot, ne, m.M + j))
                     atomicOr(&b.valid[j / 32], 1u << (j % 32));
@@ -542,7 +565,7 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
             __syncthreads();
             // passed slots leave holes: renumber the admitted ones densely
             // (a joiner reads its final id after the release is published)
-            for (uint32_t j = threadIdx.x; j < kmax; j += blockDim.x) {
+            for (uint32_t j = threadIdx.x; j < kcut; j += blockDim.x) {
                 const uint32_t wj = j / 32, bj = j % 32;
                 if (!((b.valid[wj] >> bj) & 1u)) continue;
                 uint32_t rank = __popc(b.valid[wj] & ((1u << bj) - 1u));
@@ -684,7 +707,7 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
             const uint32_t Wk = renum ? M2 - Mn_sel : W;
             Mn = M2 - Wk;
             if (renum) flags |= kFlagRenum;
-            if (b.kmax) st_relaxed(&c->join_head, b.head + b.kmax);
+            if (b.kmax) st_relaxed(&c->join_head, b.head + b.cut);
             else if (b.drain_span && b.drained) st_relaxed(&c->join_head, b.head + b.drained);
             if (cfg.mode & kModeRandomSched) c->T_dev = T_dev;
             if (admitted) c->forks = forks + admitted;
@@ -694,6 +717,7 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
             if (Mn > max_M) c->max_M = Mn;
         }
         c->barriers = nb + 1;
+        if (Coop) c->tail_prev = pre.tail;
         if (nb == 0) c->t_start = t_in;
         if (flags & kFlagDone) {
             c->final_M = m.M;
@@ -735,11 +759,12 @@ __device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, Ma
     __syncthreads();
     wg_trace(cfg, m.epoch, m.id, kTrArrive);
     if (threadIdx.x == 0) {
-        // workgroup 0 passes the host target to the master; after the first
-        // barrier the value was read over PCIe while the phase ran
-        if (Coop && cfg.host && m.id == 0)
-            __hip_atomic_store(&c->T_seen, m.epoch == 0 ? ld_system(&cfg.host->target) : b.T_pre,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // workgroup 0 passes the host target to the master: at the first
+        // barrier (and in one-wave workgroups) here, later while it waits
+        // for a release (below)
+        if (Coop && cfg.host && m.id == 0 && (m.epoch == 0 || blockDim.x <= kRelayThread))
+            __hip_atomic_store(&c->T_seen, ld_system(&cfg.host->target), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         uint32_t last = 0;
         if (by_xcd) {
             Ctx* cx = reinterpret_cast<Ctx*>(c);
@@ -768,9 +793,16 @@ __device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, Ma
         // master step: everybody else is parked in the barrier
         const uint64_t t_in = now_ticks();
         MasterPre pre;                          // thread 0's
-        if (threadIdx.x == 0) pre = master_prefetch<Coop>(c, cfg);
+        if (threadIdx.x == 0) pre = master_prefetch<Coop>(c, cfg, m.M == 1);
         const uint32_t flags = master_fn(m.M, m.epoch + 1);
         master_schedule<Coop, C>(c, cfg, m, b, flags, t_in, pre);
+    } else if (Coop && cfg.host && m.id == 0 && threadIdx.x == kRelayThread) {
+        // workgroup 0 reads the host target over PCIe while it waits, in a
+        // wave other than the waiting one: the read (about 2 us) then sits
+        // neither in a phase's loads nor on the master's path; the master of
+        // the next barrier finds the value (one barrier late if workgroup 0
+        // is this barrier's master and skips the read)
+        __hip_atomic_store(&c->T_seen, ld_system(&cfg.host->target), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else if (threadIdx.x == 0) {
         const uint64_t r = wait_release(c, cfg, m.epoch);
         fence_acquire();
@@ -799,12 +831,6 @@ __device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, Ma
     __syncthreads();
     wg_trace(cfg, m.epoch, m.id, kTrReleased);
     m = b.member;
-    // workgroup 0 (never killed, never renumbered) reads the host target for
-    // the next barrier now, in its last wave, so the PCIe round trip overlaps
-    // the phase instead of delaying its arrival (it often holds the work of
-    // a small frontier and arrives last)
-    if (Coop && cfg.host && m.id == 0 && m.alive && threadIdx.x == blockDim.x - 64)
-        b.T_pre = ld_system(&cfg.host->target);
 }
 
 // Barrier of a team: a fixed set of `m.M` workgroups that work on one

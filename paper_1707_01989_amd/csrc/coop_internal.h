@@ -142,8 +142,10 @@ struct ColorArgs {
 
 struct CotaskArgs {
     uint64_t busy_ticks;       // how long each workgroup holds its compute unit
-    uint32_t* started;         // device counter of started workgroups
-    uint32_t* finished;        // device counter of finished workgroups
+    uint32_t* started;         // device counter of started co-task workgroups (never reset)
+    uint32_t* finished;        // device counter of finished co-task workgroups (never reset)
+    uint32_t base;             // workgroups of all earlier co-tasks: both counters reach
+                               // base + nwg when this one has started / finished
     uint64_t* host_stamp;      // pinned host words: [0] all started, [1] all done (wall clock),
                                // [2] the resizable launch's M and joiner-grid starts when done
     const uint64_t* release;   // that launch's release word, or null

@@ -288,11 +288,11 @@ __global__ void __launch_bounds__(256) cotask_kernel(CotaskArgs a) {
         const uint64_t t0 = now_ticks();
         lds_raw[0] = 1;
         const uint32_t s = add_relaxed(a.started, 1u);
-        if (s + 1 == a.nwg && a.host_stamp)
+        if (s + 1 == a.base + a.nwg && a.host_stamp)
             __hip_atomic_store(&a.host_stamp[0], t0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         while (now_ticks() - t0 < a.busy_ticks) __builtin_amdgcn_s_sleep(8);
         const uint32_t f = add_relaxed(a.finished, 1u);
-        if (f + 1 == a.nwg && a.host_stamp) {
+        if (f + 1 == a.base + a.nwg && a.host_stamp) {
             if (a.release) {
                 // what the resizable launch looks like while the co-task
                 // still holds its compute units: the host forks joiners

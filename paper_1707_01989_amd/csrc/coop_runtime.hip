@@ -133,7 +133,8 @@ struct coop_rt {
     std::vector<HostCtl*> host_pool;           // free pinned control blocks
     std::vector<coop_handle*> detached;        // handles the caller did not keep
     // co-task state (counters on the device, stamps in pinned host memory)
-    uint32_t* d_cot = nullptr;                 // [0] started, [1] finished
+    uint32_t* d_cot = nullptr;                 // [0] started, [1] finished (cumulative)
+    uint32_t cot_launched = 0;                 // co-task workgroups launched so far
     uint64_t* h_stamp = nullptr;               // [0] all started, [1] all finished
     // injector
     std::thread injector;
@@ -479,6 +480,7 @@ int coop_init(int device, coop_rt** out) {
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&rt->joiner_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&rt->cotask_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(&rt->d_cot, 256);
+    if (e == hipSuccess) e = hipMemset(rt->d_cot, 0, 256);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&rt->h_stamp), 64,
                                            hipHostMallocCoherent | hipHostMallocMapped);
     if (e == hipSuccess) {
@@ -1694,10 +1696,13 @@ static int cotask_once(coop_rt* rt, const coop_cotask_cfg* cfg, hipStream_t s, c
     __atomic_store_n(&rt->h_stamp[0], 0ull, __ATOMIC_RELEASE);
     __atomic_store_n(&rt->h_stamp[1], 0ull, __ATOMIC_RELEASE);
     __atomic_store_n(&rt->h_stamp[2], ~0ull, __ATOMIC_RELEASE);
-    HIP_TRY(rt, hipMemsetAsync(rt->d_cot, 0, 8, s));
+    // the counters are cumulative, so no clearing kernel has to find a
+    // compute unit before the co-task can start
+    a.base = rt->cot_launched;
     const double t_req = now_ms();
     if (h) coop_set_target(h, h->grid > cfg->groups ? h->grid - cfg->groups : 1);
     HIP_TRY(rt, coop::launch_cotask(a, 256, lds, s));
+    rt->cot_launched += cfg->groups;        // every launched workgroup counts once, even if we stop waiting
     double t_gather = -1, t_end = -1;
     const double deadline = t_req + 60000.0;
     while (now_ms() < deadline) {

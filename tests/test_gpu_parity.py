@@ -398,6 +398,39 @@ def test_regular_barrier_under_cotasks(rt, coop_mod, gg):
     dg.release()
 
 
+def test_host_target_down_to_one_and_back(rt, coop_mod, gg):
+    """The target drops to one workgroup (workgroup 0 alone, the master at
+    every barrier, must still see the host's target) and comes back: the
+    joiners are admitted and the launch ends at (nearly) full size with the
+    oracle's levels."""
+    import time
+    import torch
+    c = coop_mod
+    g = gg.rmat(18, 16, seed=3)
+    dg = rt.graph(g)
+    roots = np.resize(gg.sources(g, 3, 16), 2000).astype(np.uint32)
+    d_roots = rt._roots(roots)
+    lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    o = c.make_opts(c.COOP_MODE_COOP, flags=c.COOP_F_HOST_SCHEDULE)
+    say(f"bfs rmat18 x{len(roots)}: target 1, then back to N")
+    h = c.coop_bfs(rt.rt, dg.handle, d_roots, len(roots), lv, 0, o)
+    n = c.coop_handle_groups(h)
+    time.sleep(0.01)
+    c.coop_set_target(h, 1)
+    time.sleep(0.02)
+    c.coop_set_target(h, n)
+    c.coop_fork_groups(h, n)
+    rc, st = c.coop_wait(h)
+    say(f"  kernel {st['kernel_ms']:.1f} ms kills={st['kills']} forks={st['forks']} "
+        f"min={st['min_groups']} final={st['final_groups']}")
+    assert rc == 0, c.coop_strerror(rc)
+    assert np.array_equal(as_u32(lv), oracle.bfs(g, int(roots[-1])))
+    # the hardware deals joiners over the shader engines, so one may wait for
+    # a unit on its own engine while another engine has one idle: nearly N
+    assert st["min_groups"] == 1 and st["final_groups"] >= n - 8
+    dg.release()
+
+
 @pytest.mark.parametrize("window", [0, 300])
 def test_admission_ring_flood(rt, coop_mod, gg, window):
     """Far more joiner workgroups than the admission ring holds (12000
