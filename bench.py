@@ -96,9 +96,10 @@ def main():
     ap.add_argument("--skip-sssp", action="store_true")
     ap.add_argument("--skip-share", action="store_true")
     ap.add_argument("--skip-octree", action="store_true")
-    ap.add_argument("--barrier-bench", action="store_true",
-                    help="also time 2000 barriers of an empty persistent launch, plain and cooperative "
-                         "(off by default: a plain run once waited out its watchdog under the profiler)")
+    ap.add_argument("--barrier-bench-plain", action="store_true",
+                    help="also time 2000 barriers of an empty plain persistent launch (off by default: "
+                         "one such run waited out its watchdog under the profiler)")
+    ap.add_argument("--skip-barrier", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark measures one GPU; multi-GPU runs are not part of it",
@@ -371,10 +372,11 @@ def main():
         }
         log(f"octree: {result['octree']}")
 
-    if args.barrier_bench:
+    if not args.skip_barrier:
         # global-barrier latency (persistent launch doing barriers only)
         bar = {}
-        for name, o in (("plain", plain_opts), ("coop", coop_opts)):
+        modes = (("plain", plain_opts),) if args.barrier_bench_plain else ()
+        for name, o in modes + (("coop", coop_opts),):
             ns, _ = coop.coop_barrier_bench(rt.rt, 2000, o, stream)
             bar[name] = round(ns, 1)
         result["barrier_ns"] = bar
