@@ -244,7 +244,17 @@ struct Member {
     uint32_t epoch;     // last release epoch observed
     uint32_t flags;     // flags of that release
     uint32_t alive;     // 1 while this workgroup is an active member
+    uint32_t xm, xg;    // arrival by XCD: this XCD's members and the XCDs with members,
+                        // as last loaded (xg = 0: not loaded since the master recounted)
 };
+
+// Whether the master that published `n` (after the interval described by
+// `m`) recounted the members per XCD: exactly when the next interval arrives
+// by XCD and the membership may have changed.
+__device__ __forceinline__ bool counts_changed(const Member& m, const Member& n) {
+    if (n.flags & (kFlagDone | kFlagAbort | kFlagFlat)) return false;
+    return m.epoch == 0 || (m.flags & kFlagFlat) || n.M != m.M || (n.flags & kFlagRenum);
+}
 
 // Workgroup-shared state of the barrier.
 struct BarrierLds {
@@ -458,6 +468,8 @@ __device__ __forceinline__ MasterPre master_prefetch(C* c, const Cfg cfg, bool r
     // overlapping the algorithm's master step (with M > 1 a barrier that
     // workgroup 0 masters uses the value of the one before)
     p.T_seen = (Coop && cfg.host) ? (relay_self ? ld_system(&cfg.host->target) : ld_relaxed(&c->T_seen)) : 0u;
+    // and leaves it for the masters after it (nobody relayed while M was 1)
+    if (Coop && cfg.host && relay_self) st_relaxed(&c->T_seen, p.T_seen);
     p.join_head = ld_relaxed(&c->join_head);
     p.T_dev = c->T_dev;
     p.nb = c->barriers;
@@ -737,6 +749,7 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
         if (Coop && !over) gone = renum ? my_new == 0xFFFFu : n.id >= Mn;
         if (renum && !gone) n.id = my_new;
         n.alive = (over || gone) ? 0u : 1u;
+        if (counts_changed(m, n)) n.xm = n.xg = 0;
         b.member = n;
         b.killed = gone ? 1u : 0u;
     }
@@ -769,8 +782,12 @@ __device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, Ma
         if (by_xcd) {
             Ctx* cx = reinterpret_cast<Ctx*>(c);
             const uint32_t x = xcc_id();
-            const uint32_t members = ld_relaxed(&cx->xcd.members[x]);
-            const uint32_t groups = ld_relaxed(&cx->xcd.groups);
+            if (m.xg == 0) {
+                // the counts changed at the last release: load them once
+                m.xm = ld_relaxed(&cx->xcd.members[x]);
+                m.xg = ld_relaxed(&cx->xcd.groups);
+            }
+            const uint32_t members = m.xm, groups = m.xg;
             __builtin_amdgcn_s_waitcnt(0);       // our T_seen store is in the L2 too
             const uint32_t o = __hip_atomic_fetch_add(&cx->xcd_arrive[x].count, 1u, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
@@ -825,6 +842,7 @@ __device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, Ma
         if (Coop && !(n.flags & kFlagRenum) && n.id >= n.M) k = 1;
         if (n.flags & (kFlagDone | kFlagAbort)) k = 0;
         n.alive = (!k && !(n.flags & (kFlagDone | kFlagAbort))) ? 1u : 0u;
+        if (counts_changed(m, n)) n.xm = n.xg = 0;
         b.member = n;
         b.killed = k;
     }
