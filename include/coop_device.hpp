@@ -365,10 +365,15 @@ __device__ inline Member join_queue(Ctx* c, const Cfg cfg) {
         return m;
     }
     {
-        // announce (unless the master has passed the slot already)
+        // announce over the entry of an older slot only: our own slot's
+        // value means the master passed it, a newer slot's that the ring
+        // went a whole lap round while this joiner stood still (slots are
+        // compared modulo 2^32, so a launch sees at most 2^31 joiners)
         uint64_t cur = __hip_atomic_load(ent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        while (!cas64(ent, cur, ring_entry(slot, kTagWaiting)))
-            if ((uint32_t)cur == slot) return m;
+        for (;;) {
+            if (cur != ~0ull && (int32_t)((uint32_t)cur - slot) >= 0) return m;
+            if (cas64(ent, cur, ring_entry(slot, kTagWaiting))) break;
+        }
     }
     const uint64_t t0 = now_ticks();
     for (uint32_t it = 0;; ++it) {
