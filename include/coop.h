@@ -85,7 +85,10 @@ int coop_last_hip_error(coop_rt* rt);
 
 /* Wrap caller-owned device CSR arrays (no copy). d_w may be NULL (no
  * weights; SSSP then fails with COOP_E_INVALID). The runtime reads row_ptr
- * once (device to host copy) to size its work queues. */
+ * once (device to host copy) to size its work queues, and checks the CSR:
+ * row_ptr[0] = 0, row_ptr[n] = arcs, row_ptr non-decreasing and every
+ * column index < n (one pass over d_col on the device); otherwise
+ * COOP_E_INVALID and no graph. */
 int coop_graph_wrap(coop_rt* rt, const uint32_t* d_row_ptr, const uint32_t* d_col,
                     const uint32_t* d_w, uint32_t n, uint64_t arcs, coop_graph** out);
 int coop_graph_release(coop_graph* g);
@@ -165,7 +168,10 @@ typedef struct coop_stats {
  * COOP_F_TOP_DOWN_ONLY is set; the result is the same either way. d_roots holds nroots source
  * vertices (device memory). d_level receives, for source r, n levels at
  * d_level + r * out_stride (out_stride = 0: every source overwrites the same
- * n entries). Unreached vertices get 0xFFFFFFFF. */
+ * n entries). Unreached vertices get 0xFFFFFFFF. The kernel checks each source
+ * when it starts it: a source >= n fails the launch with COOP_E_INVALID before
+ * anything is written for that source (the outputs of the sources before it
+ * are complete). */
 int coop_bfs(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_t nroots,
              uint32_t* d_level, uint64_t out_stride, const coop_launch_opts* opts,
              coop_stream_t stream, coop_handle** out);
@@ -173,7 +179,8 @@ int coop_bfs(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_t
 /* SSSP by frontier Bellman-Ford (relaxations with atomicMin; a vertex whose
  * distance dropped is queued once for the next round). Distances int32;
  * unreached INT32_MAX; a distance >= INT32_MAX fails with COOP_E_OVERFLOW.
- * Weights are uint32 and must be present in the graph. */
+ * Weights are uint32 and must be present in the graph. A source >= n fails
+ * the launch with COOP_E_INVALID as in coop_bfs. */
 int coop_sssp(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_t nroots,
               int32_t* d_dist, uint64_t out_stride, const coop_launch_opts* opts,
               coop_stream_t stream, coop_handle** out);

@@ -61,6 +61,7 @@ constexpr uint32_t kModeRandomSched = 4u;   // device-side seeded kill/fork sche
 constexpr uint32_t kModeRegular = 8u;       // regular resizing barrier: at most one kill per barrier
 
 // error codes written to ctx->error (match COOP_E_* of coop.h)
+constexpr int32_t kErrInvalid = -1;
 constexpr int32_t kErrTimeout = -4;
 constexpr int32_t kErrOverflow = -6;
 constexpr int32_t kErrInternal = -7;

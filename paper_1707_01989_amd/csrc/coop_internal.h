@@ -357,6 +357,8 @@ hipError_t launch_init_ctx(Ctx* c, Work* w, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s);
 // Bitmap of vertices without arcs (words: multiple of 64, padding bits set).
 hipError_t launch_deg0_bitmap(const uint32_t* row_ptr, uint32_t n, uint32_t* bits, uint32_t words, hipStream_t s);
+// Count (into *bad, cleared first) the column indices that are >= n.
+hipError_t launch_check_cols(const uint32_t* col, uint64_t arcs, uint32_t n, uint32_t* bad, hipStream_t s);
 hipError_t launch_bfs(const BfsArgs& a, bool coop, bool joiner_grid, uint32_t grid, uint32_t block,
                       uint32_t lds_bytes, hipStream_t s);
 hipError_t launch_sssp(const SsspArgs& a, bool coop, bool joiner_grid, uint32_t grid, uint32_t block,

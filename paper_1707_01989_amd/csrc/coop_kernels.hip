@@ -279,6 +279,14 @@ __global__ void deg0_bitmap_kernel(const uint32_t* row_ptr, uint32_t n, uint32_t
     }
 }
 
+// Column indices outside [0, n), counted into *bad (graph check).
+__global__ void check_cols_kernel(const uint32_t* col, uint64_t arcs, uint32_t n, uint32_t* bad) {
+    uint32_t b = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < arcs; i += (uint64_t)gridDim.x * blockDim.x)
+        b += col[i] >= n ? 1u : 0u;
+    if (b) atomicAdd(bad, b);
+}
+
 // A non-cooperative co-task: every workgroup holds its compute unit for a
 // fixed wall-clock time (the stand-in for the paper's graphics workload).
 // Its LDS request makes it exclusive with a traversal workgroup per CU.
@@ -374,6 +382,16 @@ hipError_t launch_deg0_bitmap(const uint32_t* row_ptr, uint32_t n, uint32_t* bit
     if (blocks > 65536) blocks = 65536;
     if (blocks == 0) blocks = 1;
     hipLaunchKernelGGL(deg0_bitmap_kernel, dim3(blocks), dim3(256), 0, s, row_ptr, n, bits, words);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_cols(const uint32_t* col, uint64_t arcs, uint32_t n, uint32_t* bad, hipStream_t s) {
+    hipError_t e = launch_fill_u32(bad, 1, 0u, s);
+    if (e != hipSuccess) return e;
+    uint64_t blocks = (arcs + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(check_cols_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, col, arcs, n, bad);
     return hipGetLastError();
 }
 

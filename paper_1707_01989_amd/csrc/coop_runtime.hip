@@ -134,6 +134,7 @@ struct coop_rt {
     std::vector<coop_handle*> detached;        // handles the caller did not keep
     // co-task state (counters on the device, stamps in pinned host memory)
     uint32_t* d_cot = nullptr;                 // [0] started, [1] finished (cumulative)
+    uint32_t* d_check = nullptr;               // graph check: column indices outside [0, n)
     uint32_t cot_launched = 0;                 // co-task workgroups launched so far
     uint64_t* h_stamp = nullptr;               // [0] all started, [1] all finished
     // injector
@@ -481,6 +482,7 @@ int coop_init(int device, coop_rt** out) {
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&rt->cotask_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(&rt->d_cot, 256);
     if (e == hipSuccess) e = hipMemset(rt->d_cot, 0, 256);
+    if (e == hipSuccess) e = hipMalloc(&rt->d_check, 256);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&rt->h_stamp), 64,
                                            hipHostMallocCoherent | hipHostMallocMapped);
     if (e == hipSuccess) {
@@ -531,6 +533,7 @@ int coop_shutdown(coop_rt* rt) {
     for (HostCtl* h : rt->host_pool) (void)hipHostFree(h);
     rt->host_pool.clear();
     if (rt->d_cot) (void)hipFree(rt->d_cot);
+    if (rt->d_check) (void)hipFree(rt->d_check);
     if (rt->h_stamp) (void)hipHostFree(rt->h_stamp);
     if (rt->joiner_stream) (void)hipStreamDestroy(rt->joiner_stream);
     if (rt->cotask_stream) (void)hipStreamDestroy(rt->cotask_stream);
@@ -564,6 +567,19 @@ int coop_graph_wrap(coop_rt* rt, const uint32_t* d_row_ptr, const uint32_t* d_co
     std::vector<uint32_t> rp((size_t)n + 1);
     HIP_TRY(rt, hipMemcpy(rp.data(), d_row_ptr, ((size_t)n + 1) * 4, hipMemcpyDeviceToHost));
     if (rp[0] != 0 || rp[n] != arcs) return COOP_E_INVALID;
+    for (uint32_t v = 0; v < n; ++v)
+        if (rp[v + 1] < rp[v]) return COOP_E_INVALID;
+    if (arcs > 0) {
+        // every column index must name a vertex: the kernels index their
+        // per-vertex arrays with it unchecked
+        std::lock_guard<std::recursive_mutex> lk(rt->mu);
+        uint32_t bad = 0;
+        hipError_t e = coop::launch_check_cols(d_col, arcs, n, rt->d_check, rt->cotask_stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(&bad, rt->d_check, 4, hipMemcpyDeviceToHost, rt->cotask_stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(rt->cotask_stream);
+        if (e != hipSuccess) return hip_fail(rt, e);
+        if (bad) return COOP_E_INVALID;
+    }
     coop_graph* g = new (std::nothrow) coop_graph();
     if (!g) return COOP_E_OOM;
     g->rt = rt;
@@ -576,7 +592,6 @@ int coop_graph_wrap(coop_rt* rt, const uint32_t* d_row_ptr, const uint32_t* d_co
     g->max_deg = 0;
     g->words = (uint32_t)((((uint64_t)n + 31) / 32 + 63) / 64 * 64);
     for (uint32_t v = 0; v < n; ++v) {
-        if (rp[v + 1] < rp[v]) { delete g; return COOP_E_INVALID; }
         g->deg[v] = rp[v + 1] - rp[v];
         g->max_deg = std::max(g->max_deg, g->deg[v]);
     }

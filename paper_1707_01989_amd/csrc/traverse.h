@@ -673,18 +673,25 @@ __device__ __forceinline__ uint32_t bfs_master(const BfsArgs& p, BlockLds& sh, C
             res = kPhInit;
         } else if (ph == kPhInit) {
             const uint32_t src = roots[x.root()];
-            uint32_t* lv = lvl_base + (size_t)x.root() * t.out_stride;
-            __builtin_nontemporal_store(0u, &lv[src]);
-            p.vis[src >> 5] |= 1u << (src & 31);
-            p.fb[0][src >> 5] |= 1u << (src & 31);
-            x.level() = 0;
-            x.nf_prev() = 1;
-            x.m_visited_lo() = t.row_ptr[src + 1] - t.row_ptr[src];
-            x.m_visited_hi() = 0;
-            x.lvl_found() = 0;
-            x.lvl_mf_lo() = x.lvl_mf_hi() = 0;
-            wk->heavy_tail = 0;
-            res = kPhTD;                        // rotation 0: current = fb[0]
+            if (src >= t.n) {
+                // a source outside the graph ends the launch before anything
+                // is written for it (earlier sources are complete)
+                raise_error(c, kErrInvalid);
+                res = kFlagAbort;
+            } else {
+                uint32_t* lv = lvl_base + (size_t)x.root() * t.out_stride;
+                __builtin_nontemporal_store(0u, &lv[src]);
+                p.vis[src >> 5] |= 1u << (src & 31);
+                p.fb[0][src >> 5] |= 1u << (src & 31);
+                x.level() = 0;
+                x.nf_prev() = 1;
+                x.m_visited_lo() = t.row_ptr[src + 1] - t.row_ptr[src];
+                x.m_visited_hi() = 0;
+                x.lvl_found() = 0;
+                x.lvl_mf_lo() = x.lvl_mf_hi() = 0;
+                wk->heavy_tail = 0;
+                res = kPhTD;                    // rotation 0: current = fb[0]
+            }
         } else {
             // level partials (a TD level may be followed by a HEAVY phase)
             const uint64_t mf_lvl = join64(x.lvl_mf_lo(), x.lvl_mf_hi()) + tot[1];
@@ -878,14 +885,19 @@ __device__ __forceinline__ uint32_t sssp_master(const SsspArgs& p, BlockLds& sh,
             res = kPhInit;
         } else if (ph == kPhInit) {
             const uint32_t src = roots[x.root()];
-            int32_t* d = dist_base + (size_t)x.root() * t.out_stride;
-            d[src] = 0;
-            p.fb[0][src >> 5] = 1u << (src & 31);
-            x.level() = 0;
+            if (src >= t.n) {                   // as in BFS: fail before any write
+                raise_error(c, kErrInvalid);
+                res = kFlagAbort;
+            } else {
+                int32_t* d = dist_base + (size_t)x.root() * t.out_stride;
+                d[src] = 0;
+                p.fb[0][src >> 5] = 1u << (src & 31);
+                x.level() = 0;
 #pragma unroll
-            for (uint32_t i = 0; i < kMaxXcds; ++i) p.lowered[i * 64u] = 0;
-            wk->heavy_tail = 0;
-            res = kPhTD;                        // rotation 0: current = fb[0]
+                for (uint32_t i = 0; i < kMaxXcds; ++i) p.lowered[i * 64u] = 0;
+                wk->heavy_tail = 0;
+                res = kPhTD;                    // rotation 0: current = fb[0]
+            }
         } else if (ph == kPhTD && hs > 0) {
             x.in_size() = hs;
             wk->heavy_tail = 0;

@@ -134,6 +134,55 @@ def test_bfs_small_groups(rt, coop_mod, gg):
     dg.release()
 
 
+@pytest.mark.parametrize("mode", ["plain", "coop"])
+def test_source_outside_graph_fails_cleanly(rt, coop_mod, gg, mode):
+    """A source >= n ends the launch with COOP_E_INVALID before anything is
+    written for it (the kernel checks it before any access it indexes);
+    the sources before it are complete and the runtime stays usable."""
+    c = coop_mod
+    g = gg.add_weights(gg.er(3000, 6, 4), 3, 1, 100)
+    dg = rt.graph(g)
+    o = modes(c)[mode]
+    say(f"source outside the graph, {mode}: n={g.n}")
+    for bad in (g.n, g.n + 40, 0xFFFFFFFF):
+        rc, lv, _ = rt.bfs(dg, [5, bad], o)
+        assert rc == c.COOP_E_INVALID, (bad, c.coop_strerror(rc))
+        assert np.array_equal(lv[0].cpu().numpy().view(np.uint32), oracle.bfs(g, 5)), bad
+        rc, d, _ = rt.sssp(dg, [7, bad], o)
+        assert rc == c.COOP_E_INVALID, (bad, c.coop_strerror(rc))
+        assert np.array_equal(d[0].cpu().numpy(), oracle.sssp(g, 7)), bad
+    rc, lv, _ = rt.bfs(dg, [g.n - 1], o)
+    assert rc == 0 and np.array_equal(as_u32(lv), oracle.bfs(g, g.n - 1))
+    dg.release()
+
+
+def test_graph_wrap_rejects_bad_csr(rt, coop_mod, gg):
+    """coop_graph_wrap checks the CSR before any kernel indexes with it: a
+    column index >= n (found by a device pass over the columns) or a bad
+    row_ptr gives COOP_E_INVALID and no graph; the exact array is accepted."""
+    import torch
+    c = coop_mod
+    g = gg.er(2000, 5, 6)
+    rp = torch.from_numpy(g.row_ptr.view("int32")).cuda()
+    col = g.col.copy()
+    say(f"graph wrap checks: n={g.n} arcs={g.arcs}")
+    h = c.coop_graph_wrap(rt.rt, rp, torch.from_numpy(col.view("int32")).cuda(), None, g.n, g.arcs)
+    c.coop_graph_release(h)
+    for pos, val in ((0, g.n), (g.arcs - 1, g.n + 7), (g.arcs // 2, 0xFFFFFFFF)):
+        bad = col.copy()
+        bad[pos] = val
+        with pytest.raises(c.CoopError) as ei:
+            c.coop_graph_wrap(rt.rt, rp, torch.from_numpy(bad.view("int32")).cuda(), None, g.n, g.arcs)
+        assert ei.value.code == c.COOP_E_INVALID, (pos, val)
+    dcol = torch.from_numpy(col.view("int32")).cuda()
+    rp_bad = g.row_ptr.copy()
+    rp_bad[10] = rp_bad[11] + 1                   # row 10 ends before it starts
+    for r, arcs in ((rp_bad, g.arcs), (g.row_ptr, g.arcs - 1)):
+        with pytest.raises(c.CoopError) as ei:
+            c.coop_graph_wrap(rt.rt, torch.from_numpy(r.view("int32")).cuda(), dcol, None, g.n, arcs)
+        assert ei.value.code == c.COOP_E_INVALID
+
+
 # ----------------------------------------------------------------- SSSP
 
 @pytest.mark.parametrize("name", ["grid64", "er5000", "rmat12"])
