@@ -109,7 +109,8 @@ enum {
 
 typedef struct coop_launch_opts {
     uint32_t mode;            /* COOP_MODE_PLAIN (fixed M = grid, all resident) or COOP_MODE_COOP */
-    uint32_t num_groups;      /* N requested; 0 = one per compute unit x residency */
+    uint32_t num_groups;      /* N requested, at most 2048 (else COOP_E_INVALID); 0 = one per
+                                 compute unit x residency, capped at 2048 */
     uint32_t group_size;      /* threads per workgroup: multiple of 64, <= 1024; 0 = 1024 */
     uint32_t lds_bytes;       /* LDS per workgroup; 0 = 96 KiB (one workgroup per CU) */
     uint32_t flags;           /* COOP_F_* */

@@ -278,8 +278,9 @@ int size_launch(coop_rt* rt, const coop_launch_opts* o, Sizing* s, uint32_t min_
     if (occupancy) per_cu = std::max<uint32_t>(1, std::min(per_cu, occupancy(s->coop, s->block, s->lds)));
     const uint32_t resident = cus * per_cu;
     s->resident = resident;
-    s->grid = o->num_groups ? o->num_groups : resident;
-    if (s->grid == 0 || s->grid > 0xFFFF) return COOP_E_INVALID;
+    // the launch context holds per-id tables of kMaxGroups entries
+    s->grid = o->num_groups ? o->num_groups : std::min<uint32_t>(resident, coop::kMaxGroups);
+    if (s->grid == 0 || s->grid > coop::kMaxGroups) return COOP_E_INVALID;
     if (!s->coop && s->grid > resident) return COOP_E_INVALID;   // a plain barrier needs residency
     if (s->coop && (o->flags & COOP_F_RANDOM_SCHEDULE) && (o->sched_p < 0 || o->sched_p > 1))
         return COOP_E_INVALID;

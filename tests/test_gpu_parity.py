@@ -183,6 +183,31 @@ def test_graph_wrap_rejects_bad_csr(rt, coop_mod, gg):
         assert ei.value.code == c.COOP_E_INVALID
 
 
+def test_launch_limit(rt, coop_mod, gg):
+    """N is at most 2048 (the launch context's per-id tables): 2049 is refused
+    before any launch; a cooperative launch of exactly 2048 workgroups (far
+    more than are resident at once: the rest start later as joiners or
+    after the end) gives the oracle's levels."""
+    c = coop_mod
+    g = gg.er(3000, 5, 12)
+    dg = rt.graph(g)
+    say("launch limit: 2049 refused, 2048 coop")
+    for mode in (c.COOP_MODE_PLAIN, c.COOP_MODE_COOP):
+        o = c.make_opts(mode)
+        o.num_groups = 2049
+        with pytest.raises(c.CoopError) as ei:
+            rt.bfs(dg, [1], o)
+        assert ei.value.code == c.COOP_E_INVALID
+    o = c.make_opts(c.COOP_MODE_COOP)
+    o.num_groups = 2048
+    o.group_size = 64
+    rc, lv, st = rt.bfs(dg, [1], o)
+    assert rc == 0, c.coop_strerror(rc)
+    assert np.array_equal(as_u32(lv), oracle.bfs(g, 1))
+    assert st["max_groups"] <= 2048
+    dg.release()
+
+
 # ----------------------------------------------------------------- SSSP
 
 @pytest.mark.parametrize("name", ["grid64", "er5000", "rmat12"])
