@@ -50,8 +50,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bfs_kernel_rmat22_traffic.txt")
+# the kernel and the runtime that sizes and parameterises its launches
 KERNEL_SOURCES = ("paper_1707_01989_amd/csrc/coop_kernels.hip", "paper_1707_01989_amd/csrc/traverse.h",
-                  "paper_1707_01989_amd/csrc/coop_internal.h", "include/coop_device.hpp")
+                  "paper_1707_01989_amd/csrc/coop_internal.h", "include/coop_device.hpp",
+                  "paper_1707_01989_amd/csrc/coop_runtime.hip")
 
 
 def log(msg):

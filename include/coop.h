@@ -114,7 +114,7 @@ typedef struct coop_launch_opts {
     uint32_t group_size;      /* threads per workgroup: multiple of 64, <= 1024; 0 = 1024 */
     uint32_t lds_bytes;       /* LDS per workgroup; 0 = 96 KiB (one workgroup per CU) */
     uint32_t flags;           /* COOP_F_* */
-    uint32_t heavy_threshold; /* degree above which a vertex is split into strips; 0 = 128 */
+    uint32_t heavy_threshold; /* degree above which a vertex is split into strips; 0 = 512 */
     uint32_t strip;           /* arcs per strip; 0 = 512 */
     uint32_t startup_wait_ns; /* how long workgroup 0 waits for the grid to register; 0 = 20 us */
     uint64_t sched_seed;      /* COOP_F_RANDOM_SCHEDULE: seed */
@@ -364,7 +364,7 @@ typedef struct coop_tune {
     uint64_t team_arcs;       /* work (arcs + vertices) per team member; 0 = 2^20 */
     uint32_t team_max;        /* largest team; 0 = max(1, N / 8); must be <= N */
     uint32_t direction_opt;   /* BFS: 1 = direction-optimising, 0 = top-down only */
-    uint32_t heavy_threshold; /* as coop_launch_opts; 0 = 128 */
+    uint32_t heavy_threshold; /* as coop_launch_opts; 0 = 512 */
     uint32_t strip;           /* as coop_launch_opts; 0 = 512 */
 } coop_tune;
 
@@ -423,7 +423,7 @@ typedef struct coop_server_cfg {
     uint64_t team_arcs_bfs;   /* team = clamp(ceil((arcs + n) / team_arcs), 1, team_max); 0 = 2^22 */
     uint64_t team_arcs_sssp;  /* likewise for SSSP queries; 0 = 2^22 */
     uint32_t direction_opt;   /* BFS: 1 = direction-optimising, 0 = top-down only */
-    uint32_t heavy_threshold; /* 0 = 128 */
+    uint32_t heavy_threshold; /* 0 = 512 */
     uint32_t strip;           /* 0 = 512 */
     uint32_t reserved;
     uint64_t watchdog_ns;     /* barrier spin bound, and how long idle workgroups wait without
