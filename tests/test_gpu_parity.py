@@ -208,6 +208,18 @@ def test_launch_limit(rt, coop_mod, gg):
     dg.release()
 
 
+def test_server_refuses_while_switched_off(rt, coop_mod, gg):
+    """The query server is switched off until the cause of its GPU fault is
+    shown: coop_server_create must refuse (COOP_E_INVALID) before it
+    allocates or launches anything, not start a launch."""
+    c = coop_mod
+    dg = rt.graph(gg.add_weights(gg.er(500, 4, 3), 1, 1, 10))
+    with pytest.raises(c.CoopError) as ei:
+        c.coop_server_create(rt.rt, [dg.handle], 1 << 26, c.make_server_cfg())
+    assert ei.value.code == c.COOP_E_INVALID
+    dg.release()
+
+
 # ----------------------------------------------------------------- SSSP
 
 @pytest.mark.parametrize("name", ["grid64", "er5000", "rmat12"])
