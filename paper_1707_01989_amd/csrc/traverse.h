@@ -779,9 +779,12 @@ struct SsspVisit {
     __device__ __forceinline__ void maybe_flush(WaveLds&) {}
 
     // The arcs that would lower their target (by a plain probe) are decided
-    // for the whole step first, so the atomic minimums are issued back to
-    // back and their round trips overlap; the ones that lowered the value
-    // mark the target in the next bitmap (fire-and-forget OR).
+    // for the whole step first; each issues its atomic minimum and marks its
+    // target in the next bitmap without waiting for either. Marking on the
+    // probe is exact: the probe read this round's value or a later (lower)
+    // one, so a candidate below it means the target's distance dropped in
+    // this round, by this relaxation or by one that marked it as well; a
+    // candidate not below it cannot lower the target.
     __device__ __forceinline__ void step(const bool* ok, const uint32_t* arc, const uint32_t* u,
                                          const uint32_t* pay, WaveLds&, Stats& st) {
         uint32_t wt[kUnroll];
@@ -801,14 +804,12 @@ struct SsspVisit {
             tr[j] = ok[j] && !big && nd[j] < du[j];
         }
         if (ovf) raise_error(ctx, kErrOverflow);
-        uint32_t old[kUnroll];              // read only where tr[] is set
-#pragma unroll
-        for (uint32_t j = 0; j < kUnroll; ++j)
-            if (tr[j]) old[j] = __hip_atomic_fetch_min(&dist[u[j]], nd[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
         for (uint32_t j = 0; j < kUnroll; ++j) {
-            if (tr[j] && nd[j] < old[j]) {
-                __hip_atomic_fetch_or(&nxt[u[j] >> 5], 1u << (u[j] & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (tr[j]) {
+                (void)__hip_atomic_fetch_min(&dist[u[j]], nd[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                (void)__hip_atomic_fetch_or(&nxt[u[j] >> 5], 1u << (u[j] & 31), __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
                 st.found += 1;
             }
         }
