@@ -496,6 +496,7 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
                                        uint64_t t_in, const MasterPre& pre) {
     const uint32_t ne = m.epoch + 1;
     uint32_t T_dev = 0, nb = 0, kills = 0, forks = 0, resizes = 0, min_M = 0, max_M = 0;
+    uint32_t kmax0 = 0, head0 = 0, drain0 = 0;     // thread 0's copies of what it shares in LDS
     if (threadIdx.x == 0) {
         const int32_t err = pre.err;
         const uint32_t tail = pre.tail;
@@ -528,6 +529,8 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
         uint32_t kmax = live ? ready : 0u;
         kmax = kmax < room ? kmax : room;
         kmax = kmax < want ? kmax : want;
+        kmax0 = kmax;
+        head0 = join_head;
         b.head = join_head;
         b.kmax = kmax;
         b.T = T;
@@ -537,7 +540,8 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
         // up already, so that they do not fill the ring's window (never at
         // a barrier that admits: see the ring's comment)
         const uint32_t span = ready < blockDim.x ? ready : blockDim.x;
-        b.drain_span = (live && kmax == 0 && span >= kDrainMin) ? span : 0u;
+        drain0 = (live && kmax == 0 && span >= kDrainMin) ? span : 0u;
+        b.drain_span = drain0;
     }
     uint32_t admitted = 0;
     if constexpr (Coop) {
@@ -717,7 +721,7 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
         }
     }
     if (threadIdx.x == 0) {
-        flags = b.flags;
+        // `flags` is still the value thread 0 shared as b.flags
         uint32_t Mn = m.M;
         if (kGroupedArrival<C> && !(flags & (kFlagDone | kFlagAbort)) && admitted) flags |= kFlagFlat;
         if (Coop && !(flags & (kFlagDone | kFlagAbort))) {
@@ -725,8 +729,8 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
             const uint32_t Wk = renum ? M2 - Mn_sel : W;
             Mn = M2 - Wk;
             if (renum) flags |= kFlagRenum;
-            if (b.kmax) st_relaxed(&c->join_head, b.head + b.cut);
-            else if (b.drain_span && b.drained) st_relaxed(&c->join_head, b.head + b.drained);
+            if (kmax0) st_relaxed(&c->join_head, head0 + b.cut);
+            else if (drain0 && b.drained) st_relaxed(&c->join_head, head0 + b.drained);
             if (cfg.mode & kModeRandomSched) c->T_dev = T_dev;
             if (admitted) c->forks = forks + admitted;
             if (Wk) c->kills = kills + Wk;
@@ -778,10 +782,11 @@ __device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, Ma
     __syncthreads();
     wg_trace(cfg, m.epoch, m.id, kTrArrive);
     if (threadIdx.x == 0) {
-        // workgroup 0 passes the host target to the master: at the first
-        // barrier (and in one-wave workgroups) here, later while it waits
-        // for a release (below)
-        if (Coop && cfg.host && m.id == 0 && (m.epoch == 0 || blockDim.x <= kRelayThread))
+        // workgroup 0 passes the host target to the master: here in
+        // one-wave workgroups (and at a first barrier it does not master
+        // alone), otherwise while it waits for a release (below); alone
+        // (M = 1, as at the first barrier) it reads it in its master step
+        if (Coop && cfg.host && m.id == 0 && m.M > 1 && (m.epoch == 0 || blockDim.x <= kRelayThread))
             __hip_atomic_store(&c->T_seen, ld_system(&cfg.host->target), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         uint32_t last = 0;
