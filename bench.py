@@ -1,39 +1,46 @@
 #!/usr/bin/env python3
-"""Benchmark: cooperative vs plain persistent BFS on R-MAT scale 22, with the
-co-task preemption measurement and an SSSP grid side line.
+"""Benchmark: cooperative vs plain persistent BFS on R-MAT scale 22 (the
+headline), with the other measured configurations as side lines.
 
-Workload (one GPU): R-MAT scale 22, edge factor 16 (a=0.57, b=0.19,
-c=0.19, d=0.05), seeded, permuted, symmetrised, loops/duplicates removed,
-uint32 CSR resident in HBM. A *step* is one BFS traversal from the next
-seeded source (degree >= 1). Steps run inside persistent cooperative
-launches of ``--roots-per-launch`` sources each (the scheduler target word
-is polled at every resizing barrier and kept at N), so every launch of the
-kernel does the same kind of work and the per-launch event time can be
-compared with a profiler's per-dispatch average.
+Headline workload (one GPU, the timed region and nothing else): R-MAT scale
+22, edge factor 16 (a=0.57, b=0.19, c=0.19, d=0.05), seeded, permuted,
+symmetrised, loops/duplicates removed, uint32 CSR resident in HBM. A *step*
+is one BFS traversal from the next seeded source (degree >= 1). The K timed
+steps run in ceil(K / L) persistent cooperative launches of L sources each
+(the last one holds the remainder); at every resizing barrier the launch
+queries the host-written scheduler target, which stays at N, so nothing is
+killed or forked in the timed region. Warm-up runs ceil(W / L) launches of
+L other sources. All timed launches are queued on the stream before the
+first is waited for; the region is bracketed by torch.cuda.synchronize().
 
 Printed JSON line (one):
-  value          GTEPS of the cooperative launches: sum over sources of the
-                 undirected edges in the source's component / wall time of
-                 the timed region (synchronised on both sides)
-  plain          same sources in plain persistent launches (fixed M)
-  coop_overhead  cooperative time / plain time (kernel events)
-  sssp           frontier Bellman-Ford on the 1024x1024 grid, coop vs plain,
-                 and one run under a seeded random kill/fork schedule
-  cotask         a co-task every 10 ms needing half the CUs for 1 ms while
-                 a cooperative launch runs: p50/p99 latency, gather time,
-                 slowdown of the traversal
-  shared         a long cooperative BFS and the SSSP grid launched together,
-                 the host sharer splitting the resident workgroups between
-                 them: each one's time alone and shared, wall time shared
-  octree         work-stealing octree build (4M clustered points): coop vs
-                 plain, and co-task latency during one build
-  gather_sweep   gather time against the workgroups a co-task claims (1, a
-                 quarter, half, all but one), query barrier vs the regular
-                 barrier that lets one workgroup go per barrier
-  roofline       algorithmic bytes per launch / mean launch time (HIP events
-                 on the launch stream) vs 8 TB/s; traffic from the committed
-                 PMC summary when it was taken on the current kernel sources
-  cpu_baseline   the oracle's FIFO BFS on the host, bounded sample
+  value          GTEPS of the cooperative launches: sum over the timed
+                 sources of the undirected edges in the source's component
+                 / wall time of the timed region
+  plain          the same sources in plain persistent launches (fixed M)
+  coop_overhead  cooperative / plain kernel time (HIP events)
+  roofline       the BFS kernel: algorithmic bytes per launch (8 B per
+                 scanned arc + 20 B per reached vertex) / mean launch time
+                 vs 8 TB/s ("frac"); "traffic" = HBM bytes per launch from
+                 the committed PMC summary when it was taken on the current
+                 kernel sources and launch size, "traffic_frac" = that over
+                 the launch time vs 8 TB/s
+  er4096         ER n=4096, d=8: BFS from vertex 0, coop vs plain (median)
+  sssp           frontier Bellman-Ford on the 1024x1024 grid: coop vs plain,
+                 and 16 seeded random kill/fork schedules checked equal to
+                 the never-resizing run
+  cotask         a co-task every 10 ms needing half the CUs for 1 ms during
+                 one long cooperative launch (>= 1000 samples): latency,
+                 gather time, slowdown against the same launch alone
+  gather_sweep   gather time against the workgroups a co-task claims, query
+                 barrier vs the regular barrier
+  shared         a long BFS and the SSSP grid launched together
+  octree         work-stealing octree build, coop vs plain, with co-tasks
+  batch          512 ER instances, BFS (+ colouring) in one launch: default
+                 vs autotuned schedule
+  barrier_ns     2000 barriers of an empty cooperative launch
+  cpu_baseline   the oracle (one core) on a bounded sample of the headline
+                 sources; all_cores: the OpenMP level-synchronous BFS
 """
 from __future__ import annotations
 
@@ -68,48 +75,52 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def committed_traffic():
+def committed_traffic(roots_per_launch: int):
     """HBM bytes per launch from the committed PMC summary, or None when the
-    summary is missing or was taken on other kernel sources."""
+    summary is missing, was taken on other kernel sources, or on launches of
+    another size."""
     try:
         text = open(TRAFFIC_FILE).read()
     except OSError:
         return None
     m = re.search(r"^source_hash:\s*(\w+)", text, re.M)
     b = re.search(r"^traffic_bytes_per_launch:\s*([0-9.eE+]+)", text, re.M)
-    if not m or not b or m.group(1) != kernel_source_hash():
+    L = re.search(r"^roots_per_launch:\s*(\d+)", text, re.M)
+    if not m or not b or not L or m.group(1) != kernel_source_hash() or int(L.group(1)) != roots_per_launch:
         return None
     return float(b.group(1))
+
+
+def chunks(seq, L):
+    return [seq[i:i + L] for i in range(0, len(seq), L)]
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=64)
-    ap.add_argument("--warmup", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=40, help="timed BFS sources (any count >= 1)")
+    ap.add_argument("--warmup", type=int, default=10, help="warm-up sources (any count >= 0)")
     ap.add_argument("--scale", type=int, default=22)
-    ap.add_argument("--roots-per-launch", type=int, default=8)
-    ap.add_argument("--cotask-seconds", type=float, default=4.0)
+    ap.add_argument("--roots-per-launch", type=int, default=10)
+    ap.add_argument("--er-reps", type=int, default=21)
+    ap.add_argument("--sssp-reps", type=int, default=11)
+    ap.add_argument("--sssp-seeds", type=int, default=16)
+    ap.add_argument("--cotask-seconds", type=float, default=10.5)
     ap.add_argument("--gather-seconds", type=float, default=0.5, help="per point of the gather-time sweep")
-    ap.add_argument("--cpu-sample", type=int, default=32, help="sources for the oracle timing")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="bound on the oracle timing")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one int32 'x + 1' elementwise kernel over this many MiB (counter calibration)")
-    ap.add_argument("--skip-cotask", action="store_true")
-    ap.add_argument("--skip-sssp", action="store_true")
-    ap.add_argument("--skip-share", action="store_true")
-    ap.add_argument("--skip-octree", action="store_true")
-    ap.add_argument("--barrier-bench-plain", action="store_true",
-                    help="also time 2000 barriers of an empty plain persistent launch (off by default: "
-                         "one such run waited out its watchdog under the profiler)")
-    ap.add_argument("--skip-barrier", action="store_true")
+    for leg in ("er", "sssp", "cotask", "share", "octree", "batch", "barrier", "cpu"):
+        ap.add_argument(f"--skip-{leg}", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark measures one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "this benchmark measures one GPU; runs on several GPUs are not part of it",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        sys.exit("--steps must be >= 1 and --warmup >= 0")
     L = max(1, args.roots_per_launch)
-    if args.steps % L or args.warmup % L:
-        sys.exit(f"--steps and --warmup must be multiples of --roots-per-launch ({L})")
+    t_all = time.time()
 
     import numpy as np
     import torch
@@ -120,7 +131,8 @@ def main():
     g = gg.rmat(args.scale, 16, seed=3)
     log(f"rmat{args.scale}: n={g.n} arcs={g.arcs} generated in {time.time() - t0:.1f}s")
     deg = g.degrees()
-    roots = gg.sources(g, 3, args.warmup + args.steps)
+    n_warm = -(-args.warmup // L) * L if args.warmup else 0
+    roots = gg.sources(g, 3, n_warm + args.steps)
 
     # per-source traversal sizes (component of each source)
     from scipy.sparse import csr_matrix
@@ -128,6 +140,7 @@ def main():
     A = csr_matrix((np.ones(g.arcs, dtype=np.int8), g.col.astype(np.int64), g.row_ptr.astype(np.int64)),
                    shape=(g.n, g.n))
     _, comp = connected_components(A, directed=False)
+    del A
     comp_edges = np.bincount(comp, weights=deg, minlength=comp.max() + 1) / 2
     comp_verts = np.bincount(comp, minlength=comp.max() + 1)
     edges_of = lambda r: float(comp_edges[comp[r]])
@@ -135,9 +148,9 @@ def main():
 
     rt = coop.Runtime(0)
     dg = rt.graph(g)
-    timed = [int(r) for r in roots[args.warmup:]]
-    batches_w = [rt._roots(roots[i:i + L]) for i in range(0, args.warmup, L)]
-    batches_t = [rt._roots(timed[i:i + L]) for i in range(0, args.steps, L)]
+    timed = [int(r) for r in roots[n_warm:]]
+    batches_w = [rt._roots(b) for b in chunks([int(r) for r in roots[:n_warm]], L)]
+    batches_t = [rt._roots(b) for b in chunks(timed, L)]
     level = torch.empty(g.n, dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
 
@@ -177,7 +190,7 @@ def main():
     ms_p = sum(s["kernel_ms"] for s in sts_p)
     launch_ms = ms_c / len(sts_c)
     log(f"coop {ms_c:.3f} ms kernel / {wall_c*1e3:.1f} ms wall, plain {ms_p:.3f} / {wall_p*1e3:.1f}; "
-        f"launch mean {launch_ms:.3f} ms, levels {sum(s['levels'] for s in sts_c)}")
+        f"{len(sts_c)} launches, mean {launch_ms:.3f} ms, levels {sum(s['levels'] for s in sts_c)}")
 
     edges = sum(edges_of(r) for r in timed)
     verts = sum(verts_of(r) for r in timed)
@@ -187,13 +200,16 @@ def main():
     # algorithmic bytes of a level-synchronous BFS, at the data's natural
     # width: 8 B per scanned arc (column index + state probe) and 20 B per
     # reached vertex (row range, frontier read and write, level write);
-    # arcs scanned = the degree sum of the reached vertices
+    # arcs scanned = the degree sum of the reached vertices. Per launch =
+    # the timed total over the timed launches (all of L sources unless the
+    # step count is not a multiple of L).
     alg_bytes_launch = (8 * 2 * edges + 20 * verts) / len(sts_c)
     achieved = alg_bytes_launch / (launch_ms * 1e-3) / 1e9
     # what this kernel itself read, by its own counters (direction-optimising
     # BFS skips arcs): 4 B per arc examined, 8 B per row range, 4 B per
-    # bitmap word, summed over the timed launches
+    # bitmap word
     counted = sum(4 * s["arcs"] + 8 * s["rows"] + 4 * s["bitmap_words"] for s in sts_c) / len(sts_c)
+    uniform = args.steps % L == 0
 
     result = {
         "metric": "GTEPS BFS/SSSP coop vs plain persistent kernel; p99 co-task latency",
@@ -209,18 +225,63 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": f"BFS on R-MAT scale {args.scale} (edge factor 16, a=.57 b=.19 c=.19, seed 3), "
-                               f"one seeded source per step, {L} sources per persistent cooperative launch, "
-                               f"co-task every 10 ms needing half the CUs for 1 ms",
-                   "n": g.n, "arcs": g.arcs, "sources": len(timed), "roots_per_launch": L,
-                   "groups": sts_c[0]["grid"], "group_size": 1024},
+                               f"one seeded source per step, {L} sources per persistent cooperative launch "
+                               f"(scheduler target queried at every barrier and kept at N: no kill/fork, "
+                               f"no co-task in the timed region)",
+                   "n": g.n, "arcs": g.arcs, "sources": len(timed), "launches": len(sts_c),
+                   "roots_per_launch": L, "groups": sts_c[0]["grid"], "group_size": 1024,
+                   "warmup_sources_run": n_warm},
         "plain": {"value": round(gteps_p, 3), "kernel_ms": round(ms_p, 3), "wall_ms": round(wall_p * 1e3, 3)},
         "coop_overhead": round(ms_c / ms_p, 4),
         "kernel_ms": round(ms_c, 3),
+        "wall_ms": round(wall_c * 1e3, 3),
         "barriers": sum(s["barriers"] for s in sts_c),
     }
 
+    if not args.skip_er:
+        # configuration 0: ER n = 4096, average degree 8 (seed 1), BFS from
+        # vertex 0, one launch per run; latency bound (a handful of levels)
+        ge = gg.er(4096, 8, 1)
+        dge = rt.graph(ge)
+        lv_e = torch.empty(ge.n, dtype=torch.int32, device="cuda")
+        r0 = rt._roots([0])
+        Ae = csr_matrix((np.ones(ge.arcs, dtype=np.int8), ge.col.astype(np.int64), ge.row_ptr.astype(np.int64)),
+                        shape=(ge.n, ge.n))
+        _, ce = connected_components(Ae, directed=False)
+        e_edges = float(ge.degrees()[ce == ce[0]].sum() / 2)
+
+        def run_e(opts):
+            h = coop.coop_bfs(rt.rt, dge.handle, r0, 1, lv_e, 0, opts, stream)
+            rc, st = coop.coop_wait(h)
+            if rc != 0:
+                raise RuntimeError(coop.coop_strerror(rc))
+            return st
+        for _ in range(3):
+            run_e(coop_opts)
+            run_e(plain_opts)
+        ec, ep = [], []
+        for _ in range(args.er_reps):            # interleaved, so drift hits both alike
+            ec.append(run_e(coop_opts))
+            ep.append(run_e(plain_opts))
+        mc = float(np.median([s["kernel_ms"] for s in ec]))
+        mp = float(np.median([s["kernel_ms"] for s in ep]))
+        dc = float(np.median([s["device_ms"] for s in ec]))
+        dp = float(np.median([s["device_ms"] for s in ep]))
+        result["er4096"] = {
+            "workload": "BFS from vertex 0, ER G(n=4096, m=16384) (seed 1), one persistent launch per run",
+            "reps": args.er_reps, "levels": ec[0]["levels"], "barriers": ec[0]["barriers"],
+            "ms_coop": round(mc, 4), "ms_plain": round(mp, 4), "coop_overhead": round(mc / mp, 4),
+            "gteps_coop": round(e_edges / (mc * 1e-3) / 1e9, 4), "gteps_plain": round(e_edges / (mp * 1e-3) / 1e9, 4),
+            "ns_per_barrier_coop": round(dc * 1e6 / ec[0]["barriers"], 1),
+            "ns_per_barrier_plain": round(dp * 1e6 / ep[0]["barriers"], 1),
+            "note": "ns per barrier = device time from the first barrier on / barriers (one level's work plus its barrier)",
+        }
+        log(f"er4096: {result['er4096']}")
+        dge.release()
+
     if not args.skip_sssp:
-        # frontier Bellman-Ford on the 1024x1024 grid, w U[1,1000], source 0
+        # configuration 1: frontier Bellman-Ford on the 1024x1024 grid,
+        # w U[1,1000] (seed 2), source 0
         gs = gg.add_weights(gg.grid(1024, 1024), 2, 1, 1000)
         dgs = rt.graph(gs)
         dist = torch.empty(gs.n, dtype=torch.int32, device="cuda")
@@ -234,32 +295,43 @@ def main():
             return st
         run_s(coop_opts)
         run_s(plain_opts)
-        reps = 5
-        sc = [run_s(coop_opts)["kernel_ms"] for _ in range(reps)]
-        sp = [run_s(plain_opts)["kernel_ms"] for _ in range(reps)]
-        rnd = coop.make_opts(coop.COOP_MODE_COOP, flags=coop.COOP_F_RANDOM_SCHEDULE | coop.COOP_F_PARK_KILLED,
-                             sched_seed=1, sched_p=0.25)
-        st_r = run_s(rnd)
-        ref = dist.clone()
+        sc, sp = [], []
+        for _ in range(args.sssp_reps):
+            sc.append(run_s(coop_opts)["kernel_ms"])
+            sp.append(run_s(plain_opts)["kernel_ms"])
         st_1 = run_s(coop_opts)
-        same = bool(torch.equal(ref, dist))
+        ref = dist.clone()
+        sched = []
+        for seed in range(1, args.sssp_seeds + 1):
+            rnd = coop.make_opts(coop.COOP_MODE_COOP, flags=coop.COOP_F_RANDOM_SCHEDULE | coop.COOP_F_PARK_KILLED,
+                                 sched_seed=seed, sched_p=0.25)
+            st_r = run_s(rnd)
+            sched.append({"seed": seed, "ms": round(st_r["kernel_ms"], 3), "kills": st_r["kills"],
+                          "forks": st_r["forks"], "min_groups": st_r["min_groups"],
+                          "same_as_never_resize": bool(torch.equal(ref, dist))})
         e_s = gs.edges
         result["sssp"] = {
             "workload": "frontier Bellman-Ford, 1024x1024 grid, w U[1,1000] (seed 2), source 0",
+            "reps": args.sssp_reps,
             "gteps_coop": round(e_s / (np.median(sc) * 1e-3) / 1e9, 4),
             "gteps_plain": round(e_s / (np.median(sp) * 1e-3) / 1e9, 4),
             "ms_coop": round(float(np.median(sc)), 3), "ms_plain": round(float(np.median(sp)), 3),
             "coop_overhead": round(float(np.median(sc) / np.median(sp)), 4),
             "rounds": st_1["barriers"],
-            "ns_per_barrier_coop": round(float(np.median(sc)) * 1e6 / st_1["barriers"], 1),
-            "random_schedule": {"seed": 1, "p": 0.25, "ms": round(st_r["kernel_ms"], 3), "kills": st_r["kills"],
-                                "forks": st_r["forks"], "min_groups": st_r["min_groups"],
-                                "same_as_never_resize": same},
+            "ns_per_round_coop": round(float(np.median(sc)) * 1e6 / st_1["barriers"], 1),
+            "random_schedules": {"p": 0.25, "seeds": len(sched),
+                                 "all_same_as_never_resize": all(s["same_as_never_resize"] for s in sched),
+                                 "kills": sum(s["kills"] for s in sched), "forks": sum(s["forks"] for s in sched),
+                                 "ms_median": round(float(np.median([s["ms"] for s in sched])), 3),
+                                 "runs": sched},
         }
-        log(f"sssp: {result['sssp']}")
+        log(f"sssp: coop {result['sssp']['ms_coop']} ms plain {result['sssp']['ms_plain']} ms "
+            f"ratio {result['sssp']['coop_overhead']}; schedules same: "
+            f"{result['sssp']['random_schedules']['all_same_as_never_resize']}")
 
     if not args.skip_cotask:
-        # co-task every 10 ms needing half the CUs for 1 ms during a long launch
+        # configuration 2's co-task: every 10 ms, half the CUs for 1 ms, during
+        # one long cooperative launch over the headline's sources
         per_root_ms = ms_c / len(timed)
         cus = rt.info["compute_units"]
 
@@ -279,12 +351,15 @@ def main():
         alone = run(coop_opts, d_many)
         result["cotask"] = {
             "period_ms": 10, "busy_ms": 1, "groups": cus // 2, "count": cst["count"],
+            "seconds": round(st_m["kernel_ms"] / 1e3, 2),
             "latency_p50_ms": round(cst["latency_p50_ms"], 4), "latency_p99_ms": round(cst["latency_p99_ms"], 4),
             "latency_max_ms": round(cst["latency_max_ms"], 4),
             "gather_p50_ms": round(cst["gather_p50_ms"], 4), "gather_p99_ms": round(cst["gather_p99_ms"], 4),
             "busy_mean_ms": round(cst["busy_mean_ms"], 4),
             "traversal_ms_alone": round(alone["kernel_ms"], 2), "traversal_ms_with_cotask": round(st_m["kernel_ms"], 2),
             "slowdown": round(st_m["kernel_ms"] / alone["kernel_ms"], 4),
+            "gteps_with_cotask": round(sum(edges_of(int(r)) for r in d_many.cpu().numpy()) /
+                                       (st_m["kernel_ms"] * 1e-3) / 1e9, 3),
             "kills": st_m["kills"], "forks": st_m["forks"], "join_full": st_m["join_full"],
             "model_kernel_preemption": round(10 / 9, 4), "model_half_cu": round(10 / 9.5, 4),
         }
@@ -382,16 +457,16 @@ def main():
                        "build_ms": round(st_oi["kernel_ms"], 3), "kills": st_oi["kills"]},
         }
         log(f"octree: {result['octree']}")
+        del dxo, dyo, dzo, o_out, o_leaves
+
+    if not args.skip_batch:
+        result["batch"] = batch_leg(rt, coop, gg, np, torch, stream)
 
     if not args.skip_barrier:
         # global-barrier latency (persistent launch doing barriers only)
-        bar = {}
-        modes = (("plain", plain_opts),) if args.barrier_bench_plain else ()
-        for name, o in modes + (("coop", coop_opts),):
-            ns, _ = coop.coop_barrier_bench(rt.rt, 2000, o, stream)
-            bar[name] = round(ns, 1)
-        result["barrier_ns"] = bar
-        log(f"barrier ns: {bar}")
+        ns, _ = coop.coop_barrier_bench(rt.rt, 2000, coop_opts, stream)
+        result["barrier_ns"] = {"coop": round(ns, 1)}
+        log(f"barrier ns: {result['barrier_ns']}")
 
     if args.copy_probe_mib > 0:
         x = torch.zeros(args.copy_probe_mib << 18, dtype=torch.int32, device="cuda")
@@ -399,28 +474,104 @@ def main():
         torch.cuda.synchronize()
         del x, y
 
-    traffic = committed_traffic()
+    traffic = committed_traffic(L) if uniform else None
     result["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": round(achieved / HBM_PEAK_GBS, 4),
                           "traffic": None if traffic is None else int(traffic),
+                          "traffic_frac": None if traffic is None else
+                          round(traffic / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "frac_basis": "algorithmic bytes (8 B per arc of the reached vertices + 20 B per "
+                                        "reached vertex) per launch / mean launch time",
                           "kernel": "bfs_kernel<true>", "launch_ms": round(launch_ms, 4),
+                          "units_per_launch": L if uniform else round(len(timed) / len(sts_c), 3),
                           "alg_bytes_per_launch": int(alg_bytes_launch),
                           "kernel_counted_bytes_per_launch": int(counted),
                           "source_hash": kernel_source_hash()}
 
-    # CPU baseline: the oracle (single-threaded FIFO BFS) on a bounded sample
+    if not args.skip_cpu:
+        result["cpu_baseline"] = cpu_leg(g, timed, edges_of, args.cpu_seconds)
+    rt.close()
+    result["bench_wall_s"] = round(time.time() - t_all, 1)
+    print(json.dumps(result), flush=True)
+
+
+def batch_leg(rt, coop, gg, np, torch, stream):
+    """Configuration 3: 512 ER instances (n log-uniform in [2^10, 2^18),
+    average degree U[4, 32], seeds 1000 + i), BFS from vertex 0 (then greedy
+    colouring with priority seed i) per instance in one launch; the default
+    schedule against the autotuned one (median of 3 launches each)."""
+    t0 = time.time()
+    gs = gg.er_batch(512, 1000, workers=16)
+    dgs = [rt.graph(g) for g in gs]
+    log(f"batch: 512 instances, n={sum(g.n for g in gs)} arcs={sum(g.arcs for g in gs)} "
+        f"({time.time() - t0:.1f}s)")
+    copts = coop.make_opts(coop.COOP_MODE_COOP)
+    out = {"workload": "512 ER instances, n = floor(2^U(10,18)), d = U(4,32), seeds 1000+i; "
+                       "BFS from vertex 0 (+ greedy colouring, priority seed i) per instance, one launch",
+           "instances": len(gs), "n_total": int(sum(g.n for g in gs)), "arcs_total": int(sum(g.arcs for g in gs))}
+    bfs_edges = None
+    for name, ops in (("bfs", coop.COOP_BATCH_BFS), ("bfs_color", coop.COOP_BATCH_BFS | coop.COOP_BATCH_COLOR)):
+        items, outs = rt.batch_items(dgs, ops)
+        rt.batch(items, None, copts)             # warm-up
+        if bfs_edges is None:
+            torch.cuda.synchronize()
+            bfs_edges = 0.0
+            for g, o in zip(gs, outs):
+                reached = o["level"].cpu().numpy().view(np.uint32) != 0xFFFFFFFF
+                bfs_edges += float(g.degrees()[reached].sum()) / 2
+        ta = time.time()
+        best, best_ms, def_ms = coop.coop_batch_autotune(rt.rt, items, stride=4, reps=3, opts=copts)
+        tune_s = time.time() - ta
+        res = {}
+        for tname, tune in (("default", None), ("tuned", best)):
+            ms = []
+            for _ in range(3):
+                rc, st = rt.batch(items, tune, copts)
+                if rc != 0:
+                    raise RuntimeError(coop.coop_strerror(rc))
+                ms.append(st["kernel_ms"])
+            res[tname] = float(np.median(ms))
+        out[name] = {"ms_default": round(res["default"], 3), "ms_tuned": round(res["tuned"], 3),
+                     "speedup_tuned": round(res["default"] / res["tuned"], 4),
+                     "tuned": best.as_dict(), "tune_seconds": round(tune_s, 1),
+                     "subset_ms_default": round(def_ms, 3) if def_ms > 0 else None,
+                     "subset_ms_tuned": round(best_ms, 3)}
+        if name == "bfs":
+            out[name]["gteps_default"] = round(bfs_edges / (res["default"] * 1e-3) / 1e9, 3)
+            out[name]["gteps_tuned"] = round(bfs_edges / (res["tuned"] * 1e-3) / 1e9, 3)
+        log(f"batch {name}: {out[name]}")
+        del items, outs
+    for dg in dgs:
+        dg.release()
+    return out
+
+
+def cpu_leg(g, timed, edges_of, seconds):
+    """The oracle's FIFO BFS on one core, over as many of the timed sources
+    as fit in `seconds` (at least one); then the OpenMP level-synchronous
+    BFS on every host core over the same sources."""
     import oracle
-    sample = timed[:args.cpu_sample]
+    sample = []
     t = time.perf_counter()
-    for r in sample:
+    for r in timed:
         oracle.bfs(g, r)
+        sample.append(r)
+        if time.perf_counter() - t >= seconds:
+            break
     cpu_s = time.perf_counter() - t
     cpu_edges = sum(edges_of(r) for r in sample)
-    result["cpu_baseline"] = {"value": round(cpu_edges / cpu_s / 1e9, 5), "unit": "GTEPS", "cores": 1,
-                              "kind": "oracle", "sample": f"{len(sample)} sources of the same graph, "
-                                                          f"{cpu_s:.2f} s"}
-    rt.close()
-    print(json.dumps(result), flush=True)
+    t = time.perf_counter()
+    used = 0
+    for r in sample:
+        _, used = oracle.bfs_parallel(g, r)
+    par_s = time.perf_counter() - t
+    res = {"value": round(cpu_edges / cpu_s / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+           "sample": f"{len(sample)} of the timed sources of the same graph, {cpu_s:.2f} s",
+           "all_cores": {"value": round(cpu_edges / par_s / 1e9, 5), "unit": "GTEPS", "cores": used,
+                         "nproc": os.cpu_count(), "kind": "OpenMP level-synchronous BFS",
+                         "sample": f"the same {len(sample)} sources, {par_s:.2f} s"}}
+    log(f"cpu: {res}")
+    return res
 
 
 if __name__ == "__main__":

@@ -13,10 +13,17 @@ Functions (all results are integer and unique):
   sssp(g, src)        -> int32[n] distances, INT32_MAX = unreached
   color(g, prio_seed) -> uint32[n] greedy colours in decreasing key order
   mis(g, prio_seed)   -> uint8[n] greedy maximal independent set, same order
+  cc(g)               -> uint32[n] connected-component labels, each the smallest
+                         vertex id of its component
   priority_order(n, prio_seed) -> vertices by decreasing key
   octree(x, y, z, cap) -> (uint32[n, 4] points in final order {x, y, z, index},
                            uint32[k, 5] leaves {first, end, depth, code_lo, code_hi})
   splitmix64(x)       -> SplitMix64 output for state x
+
+All-core CPU baselines (``cpu_parallel.c``, OpenMP; not the oracle, pinned to
+it by tests, timed by the benchmark beside it):
+  bfs_parallel(g, src, threads=0)  -> (uint32[n] levels, threads used)
+  sssp_parallel(g, src, threads=0) -> (int32[n] distances, threads used)
 
 The cooperative-scheduling semantics model lives in ``oracle.coop_model``.
 """
@@ -33,6 +40,7 @@ UNREACHED_LEVEL = 0xFFFFFFFF
 UNREACHED_DIST = 0x7FFFFFFF
 
 _lib = None
+_par = None
 
 
 class OracleError(RuntimeError):
@@ -59,12 +67,31 @@ def _load():
     lib.oracle_color.argtypes = [ctypes.c_uint32, u32p, u32p, ctypes.c_uint64, u32p]
     lib.oracle_mis.restype = ctypes.c_int
     lib.oracle_mis.argtypes = [ctypes.c_uint32, u32p, u32p, ctypes.c_uint64, u8p]
+    lib.oracle_cc.restype = ctypes.c_int
+    lib.oracle_cc.argtypes = [ctypes.c_uint32, u32p, u32p, u32p]
     lib.oracle_octree.restype = ctypes.c_int
     lib.oracle_octree.argtypes = [ctypes.c_uint32, u32p, u32p, u32p, ctypes.c_uint32, u32p, u32p,
                                   ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
     lib.oracle_priority_order.restype = ctypes.c_int
     lib.oracle_priority_order.argtypes = [ctypes.c_uint32, ctypes.c_uint64, u32p]
     _lib = lib
+    return lib
+
+
+def _load_parallel():
+    global _par
+    if _par is not None:
+        return _par
+    if not os.path.exists(_build.PARALLEL_SO):
+        _build.build_parallel()
+    lib = ctypes.CDLL(_build.PARALLEL_SO)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.cpu_bfs_par.restype = ctypes.c_int
+    lib.cpu_bfs_par.argtypes = [ctypes.c_uint32, u32p, u32p, ctypes.c_uint32, u32p, ctypes.c_int]
+    lib.cpu_sssp_par.restype = ctypes.c_int
+    lib.cpu_sssp_par.argtypes = [ctypes.c_uint32, u32p, u32p, u32p, ctypes.c_uint32, i32p, ctypes.c_int]
+    _par = lib
     return lib
 
 
@@ -127,6 +154,16 @@ def mis(g, prio_seed: int) -> np.ndarray:
     return out
 
 
+def cc(g) -> np.ndarray:
+    rp, prp = _u32(g.row_ptr)
+    col, pcol = _u32(g.col)
+    out = np.empty(g.n, dtype=np.uint32)
+    rc = _load().oracle_cc(g.n, prp, pcol, _ptr(out, ctypes.c_uint32))
+    if rc != 0:
+        raise OracleError(f"oracle_cc failed ({rc})")
+    return out
+
+
 def priority_order(n: int, prio_seed: int) -> np.ndarray:
     out = np.empty(n, dtype=np.uint32)
     rc = _load().oracle_priority_order(n, prio_seed & (2**64 - 1), _ptr(out, ctypes.c_uint32))
@@ -152,3 +189,30 @@ def octree(x, y, z, cap: int) -> tuple[np.ndarray, np.ndarray]:
     if rc != 0:
         raise OracleError(f"oracle_octree failed ({rc})")
     return out, leaves[: nl.value].copy()
+
+
+def bfs_parallel(g, src: int, threads: int = 0) -> tuple[np.ndarray, int]:
+    """All-core level-synchronous BFS (OpenMP); threads = 0: the OpenMP default."""
+    rp, prp = _u32(g.row_ptr)
+    col, pcol = _u32(g.col)
+    out = np.empty(g.n, dtype=np.uint32)
+    rc = _load_parallel().cpu_bfs_par(g.n, prp, pcol, src, _ptr(out, ctypes.c_uint32), threads)
+    if rc <= 0:
+        raise OracleError(f"cpu_bfs_par failed ({rc})")
+    return out, rc
+
+
+def sssp_parallel(g, src: int, threads: int = 0) -> tuple[np.ndarray, int]:
+    """All-core frontier Bellman-Ford (OpenMP); threads = 0: the OpenMP default."""
+    if g.w is None:
+        raise OracleError("sssp needs weights")
+    rp, prp = _u32(g.row_ptr)
+    col, pcol = _u32(g.col)
+    w, pw = _u32(g.w)
+    out = np.empty(g.n, dtype=np.int32)
+    rc = _load_parallel().cpu_sssp_par(g.n, prp, pcol, pw, src, _ptr(out, ctypes.c_int32), threads)
+    if rc == -6:
+        raise OverflowError("shortest-path distance exceeds int32")
+    if rc <= 0:
+        raise OracleError(f"cpu_sssp_par failed ({rc})")
+    return out, rc

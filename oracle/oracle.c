@@ -23,6 +23,12 @@
  *                 by an already coloured (higher-key) neighbour.
  *   oracle_mis    greedy maximal independent set in the same priority order:
  *                 a vertex joins unless a higher-key neighbour already joined.
+ *   oracle_cc     connected components, each vertex labelled with the
+ *                 smallest vertex id of its component (a FIFO BFS started
+ *                 from every still unlabelled vertex in increasing id order;
+ *                 the start is then the smallest id the BFS reaches). This is
+ *                 the fixed point a label-propagation kernel reaches with
+ *                 minimum labels in any schedule, so it is unique.
  *
  * Priority keys: key(v) = (h(v), v) compared lexicographically, higher first,
  * where h(v) is output number v (0-based) of a SplitMix64 generator whose
@@ -290,5 +296,31 @@ int oracle_octree(uint32_t n, const uint32_t* x, const uint32_t* y, const uint32
     *nleaves = nl;
     free(tmp);
     free(stack);
+    return 0;
+}
+
+/* ------------------------------------------------- connected components */
+
+int oracle_cc(uint32_t n, const uint32_t* row_ptr, const uint32_t* col, uint32_t* label) {
+    uint32_t* queue = (uint32_t*)malloc(sizeof(uint32_t) * (n ? n : 1));
+    if (!queue) return -2;
+    for (uint32_t v = 0; v < n; ++v) label[v] = ORACLE_UNREACHED_LEVEL;
+    for (uint32_t s = 0; s < n; ++s) {
+        if (label[s] != ORACLE_UNREACHED_LEVEL) continue;
+        uint32_t head = 0, tail = 0;
+        label[s] = s;
+        queue[tail++] = s;
+        while (head < tail) {
+            uint32_t v = queue[head++];
+            for (uint32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                uint32_t u = col[e];
+                if (label[u] == ORACLE_UNREACHED_LEVEL) {
+                    label[u] = s;
+                    queue[tail++] = u;
+                }
+            }
+        }
+    }
+    free(queue);
     return 0;
 }

@@ -314,3 +314,59 @@ def test_mis_verifier_catches_planted_error(gg):
     v = int(np.nonzero(ins)[0][0])
     ins[v] = 0
     assert not verify_mis(g, ins, kv)
+
+
+# --------------------------------------------------- connected components
+
+def cc_min_labels_scipy(g):
+    """Smallest vertex id of every vertex's component, from scipy's
+    connected_components (its own component numbering, mapped to minima)."""
+    k, comp = csgraph.connected_components(to_scipy(g), directed=False)
+    mins = np.full(k, np.iinfo(np.int64).max)
+    np.minimum.at(mins, comp, np.arange(g.n))
+    return mins[comp].astype(np.uint32)
+
+
+@pytest.mark.parametrize("make", [
+    lambda gg: gg.er(2000, 1.5, 4),           # many components near the ER threshold
+    lambda gg: gg.er(3000, 8, 5),
+    lambda gg: gg.rmat(12, 8, seed=6),        # isolated vertices and one giant component
+    lambda gg: gg.grid(30, 40),
+    lambda gg: gg.disjoint_union(gg.disjoint_union(gg.path(50), gg.empty(9)), gg.star(30)),
+])
+def test_cc_vs_scipy(gg, make):
+    g = make(gg)
+    assert np.array_equal(oracle.cc(g), cc_min_labels_scipy(g))
+
+
+def test_cc_closed_forms(gg):
+    assert np.array_equal(oracle.cc(gg.path(100)), np.zeros(100, np.uint32))
+    assert np.array_equal(oracle.cc(gg.empty(17)), np.arange(17, dtype=np.uint32))
+    u = gg.disjoint_union(gg.complete(5), gg.disjoint_union(gg.empty(3), gg.path(4)))
+    assert list(oracle.cc(u)) == [0] * 5 + [5, 6, 7] + [8] * 4
+
+
+def test_cc_characterisation(gg):
+    """The labels are the fixed point of minimum-label propagation that is
+    also minimal: every arc joins equal labels, every label is a vertex of
+    its own class and the smallest one, and classes are connected (the BFS
+    levels from the label reach exactly the class)."""
+    g = gg.er(1500, 2.0, 9)
+    lab = oracle.cc(g)
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr.astype(np.int64)))
+    assert np.all(lab[src] == lab[g.col])
+    assert np.all(lab <= np.arange(g.n))
+    assert np.all(lab[lab] == lab)
+    for r in np.unique(lab)[:50]:
+        reach = oracle.bfs(g, int(r)) != UNREACHED_LEVEL
+        assert np.array_equal(reach, lab == r)
+
+
+def test_cc_checks_catch_planted_error(gg):
+    g = gg.er(800, 3.0, 2)
+    lab = oracle.cc(g).copy()
+    v = int(np.nonzero(lab != np.arange(g.n))[0][0])
+    lab[v] = v                                  # split a vertex off its component
+    assert not np.array_equal(lab, cc_min_labels_scipy(g))
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr.astype(np.int64)))
+    assert not np.all(lab[src] == lab[g.col])
