@@ -133,6 +133,11 @@ typedef struct coop_launch_opts {
     uint64_t* d_wgtrace;      /* optional device buffer: per barrier e and logical workgroup id,
                                  four device wall-clock stamps at [(e * N + id) * 4 + k]: work
                                  start, work done, barrier arrival, release seen; NULL = off */
+    uint32_t bu_alpha;        /* BFS direction rule (Beamer et al.): a top-down level is followed
+                                 by a bottom-up one when its frontier's arcs x alpha exceed the
+                                 arcs not yet visited; 0 = 14 */
+    uint32_t bu_beta;         /* ... and a bottom-up level by a top-down one when the frontier x
+                                 beta is below n and shrinking; 0 = 24 */
 } coop_launch_opts;
 
 /* Fill `o` with the defaults (plain mode). */
@@ -198,11 +203,23 @@ int coop_color(coop_rt* rt, const coop_graph* g, uint64_t prio_seed, uint32_t* d
 int coop_mis(coop_rt* rt, const coop_graph* g, uint64_t prio_seed, uint8_t* d_in_set,
              const coop_launch_opts* opts, coop_stream_t stream, coop_handle** out);
 
+/* Connected components by minimum-label propagation: d_label (n uint32,
+ * device) receives, for every vertex, the smallest vertex id of its
+ * component. One round per resizing-barrier interval (the level-by-level
+ * pattern of the paper's section 3.2, "Adapting Graph Traversal"), with
+ * the round number as transmitted state; the kernel is written only
+ * against the device calls of coop_device.hpp, so it is also the worked
+ * example of writing a cooperative kernel with them. Same options, kill /
+ * fork schedules and stats as coop_bfs (stats.barriers = rounds + 1). */
+int coop_cc(coop_rt* rt, const coop_graph* g, uint32_t* d_label, const coop_launch_opts* opts,
+            coop_stream_t stream, coop_handle** out);
+
 /* Generic launch by kernel id with a parameter block (immutable, copied). */
 enum { COOP_KERNEL_BFS = 1, COOP_KERNEL_SSSP = 2, COOP_KERNEL_COLOR = 3, COOP_KERNEL_MIS = 4,
        COOP_KERNEL_BARRIER = 5, COOP_KERNEL_BATCH = 6 /* handles of coop_batch_run only */,
        COOP_KERNEL_SERVE = 7 /* the launch inside a coop_server */,
-       COOP_KERNEL_OCTREE = 8 /* handles of coop_octree only */ };
+       COOP_KERNEL_OCTREE = 8 /* handles of coop_octree only */,
+       COOP_KERNEL_CC = 9 /* as coop_cc; d_out = labels */ };
 typedef struct coop_params {
     const coop_graph* graph;
     const uint32_t* d_roots;
@@ -382,18 +399,31 @@ void coop_tune_default(coop_tune* t);
 int coop_batch_run(coop_rt* rt, const coop_batch_item* items, uint32_t count, const coop_tune* tune,
                    const coop_launch_opts* opts, coop_stream_t stream, coop_handle** out);
 
-/* Autotuner: coordinate search over group size, team work and BFS
- * direction rule, timing each candidate (median of `reps` runs, HIP
- * events) on the calibration subset items[0], items[stride], ... (stride 0
- * or 1 = all items). The result is cached in the runtime, keyed by the
- * device and the batch's size statistics (count, sum of n, sum of arcs,
- * largest instance); a later call with the same key returns the cached
- * tune without timing. Outputs of the subset are overwritten. best_ms
- * (nullable) gets the winner's time on the subset, default_ms (nullable)
- * the default tune's. */
+/* Autotuner: coordinate search (two passes) over group size, workgroup
+ * count (0.5, 0.75, 1 and 2 per compute unit), team work, team cap (N/16 ..
+ * N/2), BFS direction rule, heavy-vertex threshold and strip, timing each
+ * candidate (median of `reps` runs, HIP events) on the calibration subset
+ * items[0], items[stride], ... (stride 0 or 1 = all items); a candidate is
+ * taken if it is 2% faster. The result is cached, keyed by the device model
+ * and the batch's shape (count, sum of n, sum of arcs, largest instance,
+ * the union of the items' ops, the launch mode); a later call with the same
+ * key returns the cached tune without timing (default_ms = -1). Outputs of
+ * the subset are overwritten. best_ms (nullable) gets the winner's time on
+ * the subset, default_ms (nullable) the default tune's. Not part of the
+ * method of the paper: it picks the schedule of the batched launch. */
 int coop_batch_autotune(coop_rt* rt, const coop_batch_item* items, uint32_t count, uint32_t stride,
                         uint32_t reps, const coop_launch_opts* opts, coop_stream_t stream, coop_tune* best,
                         double* best_ms, double* default_ms);
+
+/* The autotuner's cache as a text file (a header line, then one line per
+ * entry: the key, the schedule and its time), so a tune survives the
+ * process. save writes every cached entry; load adds the file's entries to
+ * the cache (a malformed file adds none and returns COOP_E_INVALID); both
+ * report the cache's size in *entries (nullable). clear empties the cache.
+ * No GPU is needed. */
+int coop_tune_cache_save(const char* path, uint32_t* entries);
+int coop_tune_cache_load(const char* path, uint32_t* entries);
+void coop_tune_cache_clear(void);
 
 /* ------------------------------------------------------------ serving */
 
@@ -489,7 +519,11 @@ int coop_server_destroy(coop_server* s);
 /* ------------------------------------------------------ measurements */
 
 /* Global-barrier latency: a persistent launch that does `iters` barriers
- * and nothing else. ns_per_barrier from the device wall clock. */
+ * and nothing else. ns_per_barrier from the device wall clock. Cooperative
+ * launches only: a plain one (opts NULL or COOP_MODE_PLAIN) is refused with
+ * COOP_E_INVALID, because one such launch once waited out its watchdog and
+ * the cause has not been shown (plain launches of the traversals, which
+ * use the same barrier, are not affected). */
 int coop_barrier_bench(coop_rt* rt, const coop_launch_opts* opts, uint32_t iters,
                        coop_stream_t stream, double* ns_per_barrier, coop_stats* stats);
 

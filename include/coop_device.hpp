@@ -59,6 +59,7 @@ constexpr uint32_t kModeCoop = 1u;          // cooperative (resizable) launch
 constexpr uint32_t kModePark = 2u;          // killed workgroups re-queue as joiners
 constexpr uint32_t kModeRandomSched = 4u;   // device-side seeded kill/fork schedule
 constexpr uint32_t kModeRegular = 8u;       // regular resizing barrier: at most one kill per barrier
+constexpr uint32_t kModeRelayTarget = 16u;  // the host target is relayed into Ctx::T_seen by the kernel itself
 
 // error codes written to ctx->error (match COOP_E_* of coop.h)
 constexpr int32_t kErrInvalid = -1;
@@ -90,6 +91,7 @@ struct Cfg {
     uint32_t ses;             // shader engines per XCD
     uint32_t slots_per_engine;  // workgroups of this kernel one shader engine holds at once
     uint32_t join_window;     // joiners that may wait in the admission ring at once (<= kJoinCap - N)
+    uint32_t keep;            // task pattern: fewest active workgroups the scheduler leaves (0 = 1)
 };
 
 // The shader engine this workgroup runs on, numbered XCD-major: the XCD
@@ -178,12 +180,36 @@ struct alignas(256) XcdCounts {
     uint32_t _p[64 - kMaxXcds - 1];
 };
 
+// State of a launch whose kernel calls offer_kill and request_fork directly
+// between tasks instead of meeting at resizing barriers (the work-stealing
+// pattern of the paper's programming section). Ids are slots in [0, N)
+// that a workgroup claims when it becomes active and frees when it leaves,
+// so a workgroup can leave whatever its id (kill in any order, Appendix B).
+constexpr uint32_t kTransmitWords = 16;
+struct alignas(256) TaskState {
+    uint32_t active;          // M: active workgroups
+    uint32_t kills;           // offers the scheduler accepted
+    uint32_t forks;           // joiners that became active
+    uint32_t min_active;      // fewest active after a kill
+    uint32_t max_active;      // most active
+    uint32_t decisions;       // seeded schedule: offers decided so far
+    uint32_t join_tickets;    // joiners that asked to come in
+    uint32_t join_granted;    // joiners request_fork has let in (tickets below this may enter)
+    uint32_t _p[56];
+    uint32_t active_x[kMaxEngines];          // active workgroups per shader engine
+    uint32_t transmit[kTransmitWords];       // state the last request_fork transmitted
+    uint32_t _q[64 - kTransmitWords];
+    uint32_t slot_owner[kMaxGroups];         // 1 while a workgroup holds the id
+};
+
 struct alignas(256) Ctx : CtxCore {
     uint64_t join_entry[kJoinCap];
     uint32_t engine_of[kMaxGroups];
     uint32_t renum[kMaxGroups];
     ArriveLine xcd_arrive[kMaxXcds];
     XcdCounts xcd;
+    uint32_t transmit[64];    // interval pattern: state joiners take over (kTransmitWords used)
+    TaskState task;
 };
 
 // Launch contexts (not the small per-team ones) arrive by XCD.
@@ -267,6 +293,7 @@ struct BarrierLds {
     uint32_t my_new;                   // placed kill: the master's new id
     uint32_t top_kill;                 // placed kill: no engine owes, the top W ids leave
     uint32_t drain_span, drained;      // ring slots checked for given-up joiners, and how many lead
+    uint32_t offers;                   // task pattern: offer_kill calls so far (thread 0)
     uint32_t cut, tail_prev;           // admission: slots taken before the first new unannounced one
     uint32_t valid[kMaxGroups / 32];   // admission: ring slots whose joiner was still waiting
     uint32_t xcnt[kMaxEngines];        // placed kill: members per engine, then victims per engine
@@ -386,7 +413,10 @@ __device__ inline Member join_queue(Ctx* c, const Cfg cfg) {
             // release is visible, then read the final id (the master may
             // renumber before it publishes) and start after the fork point
             const uint32_t aep = (uint32_t)(e >> 32) & 0xFFFFu;
-            while ((rel_epoch(r) & 0xFFFFu) != aep && !(rel_flags(r) & (kFlagAbort | kFlagDone))) {
+            // wait until the release of that epoch is published (the entry is
+            // written before it); an epoch already past it means this joiner
+            // was not a member of that interval (see below)
+            while (((rel_epoch(r) - aep) & 0xFFFFu) >= 0x8000u && !(rel_flags(r) & (kFlagAbort | kFlagDone))) {
                 __builtin_amdgcn_s_sleep(1);
                 r = ld_relaxed64(&c->release);
             }
@@ -397,6 +427,10 @@ __device__ inline Member join_queue(Ctx* c, const Cfg cfg) {
             m.epoch = rel_epoch(r);
             m.flags = rel_flags(r);
             m.alive = (m.flags & (kFlagAbort | kFlagDone)) ? 0u : 1u;
+            // admitted and killed at once (the master admits at most T - M
+            // joiners and kills only M + admitted - T, so it does not
+            // happen; an id at or above M would count as an extra arrival)
+            if (m.id >= m.M || (rel_epoch(r) & 0xFFFFu) != aep) m.alive = 0u;
             if (m.alive) st_relaxed(&c->engine_of[m.id], engine_id(cfg.ses));
             return m;
         }
@@ -493,7 +527,7 @@ __device__ __forceinline__ MasterPre master_prefetch(C* c, const Cfg cfg, bool r
 // and kill (the top ids). Thread 0 then publishes the release word.
 template <bool Coop, class C>
 __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLds& b, uint32_t flags,
-                                       uint64_t t_in, const MasterPre& pre) {
+                                       uint64_t t_in, const MasterPre& pre, bool resize) {
     const uint32_t ne = m.epoch + 1;
     uint32_t T_dev = 0, nb = 0, kills = 0, forks = 0, resizes = 0, min_M = 0, max_M = 0;
     uint32_t kmax0 = 0, head0 = 0, drain0 = 0;     // thread 0's copies of what it shares in LDS
@@ -510,7 +544,9 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
         min_M = pre.min_M;
         max_M = pre.max_M;
         if (err) flags |= kFlagAbort;
-        const bool live = Coop && !(flags & (kFlagDone | kFlagAbort));
+        // a barrier that may not resize is one whose fork admits nobody and
+        // whose kill claims nobody (k = 0 and the Kill-No-Op rule)
+        const bool live = Coop && resize && !(flags & (kFlagDone | kFlagAbort));
         uint32_t T = cfg.N;
         if (live) {
             if (cfg.mode & kModeRandomSched) {
@@ -774,7 +810,8 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
 // reads the host-written target (one PCIe read per barrier), before it
 // arrives.
 template <bool Coop, class C, class MasterFn>
-__device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, MasterFn&& master_fn) {
+__device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, MasterFn&& master_fn,
+                               bool resize = true) {
     // by XCD: every wave's memory operations must have reached the L2 that
     // its XCD's last arriver writes back
     const bool by_xcd = kGroupedArrival<C> && m.epoch != 0 && !(m.flags & kFlagFlat);
@@ -823,7 +860,7 @@ __device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, Ma
         MasterPre pre;                          // thread 0's
         if (threadIdx.x == 0) pre = master_prefetch<Coop>(c, cfg, m.M == 1);
         const uint32_t flags = master_fn(m.M, m.epoch + 1);
-        master_schedule<Coop, C>(c, cfg, m, b, flags, t_in, pre);
+        master_schedule<Coop, C>(c, cfg, m, b, flags, t_in, pre, resize);
     } else if (Coop && cfg.host && m.id == 0 && threadIdx.x == kRelayThread) {
         // workgroup 0 reads the host target over PCIe while it waits, in a
         // wave other than the waiting one: the read (about 2 us) then sits
@@ -892,6 +929,385 @@ __device__ inline void team_barrier(CtxCore* c, const Cfg cfg, Member& m, Barrie
     m.epoch += 1;
     m.flags = flags;
     m.alive = (flags & (kFlagDone | kFlagAbort)) ? 0u : 1u;
+}
+
+// ==================================================================
+// The programming model as device calls (paper section 3.1, "Semantics of
+// Cooperative Kernels", and the rules of Appendix A). Every call is a
+// workgroup-level function: all threads of the workgroup make it, with the
+// same arguments (the paper's uniformity requirement); `Coop` is false in a
+// plain launch, where M is fixed and nothing is killed or forked.
+//
+// Two ways to write a cooperative kernel, as in the paper's programming
+// section:
+//  * interval pattern (graph traversal): the kernel meets at
+//    coop_resizing_global_barrier / coop_global_barrier; M and the ids stay
+//    fixed between two barriers, so work can be split statically by
+//    coop_get_group_id / coop_get_num_groups. Forks and kills happen inside
+//    the resizing barrier (fork first, then kill; the query barrier of the
+//    paper's scheduler design). Joiners start after a barrier and read the
+//    transmitted state with coop_transmit_block().
+//  * task pattern (work stealing): the kernel calls coop_offer_kill and
+//    coop_request_fork itself, typically before each task, and never meets
+//    at a global barrier. Ids are slots that a workgroup keeps until it
+//    leaves, so the scheduler may take any workgroup (Appendix B).
+// A kernel uses one pattern; the launch context (Ctx) carries the state of
+// both.
+
+// A workgroup's handle on its launch: the launch context in HBM, the
+// launch constants (the kernel argument) and the workgroup's membership and
+// barrier scratch in LDS.
+struct Group {
+    Ctx* ctx;
+    const Cfg& cfg;
+    BarrierLds& bar;
+    __device__ Group(Ctx* c, const Cfg& f, BarrierLds& b) : ctx(c), cfg(f), bar(b) {}
+};
+
+// get_group_id: this workgroup's id (section 3.1, "Active Workgroups"): in
+// [0, M) in the interval pattern, a slot in [0, N) in the task pattern.
+__device__ __forceinline__ uint32_t coop_get_group_id(const Group& g) { return g.bar.member.id; }
+
+// get_num_groups: the active workgroup count M of the current resizing-
+// barrier interval (interval pattern; section 3.2, "A Changing Workgroup
+// Count"). In the task pattern M changes at any time: this returns the
+// count as last read, a hint only.
+__device__ __forceinline__ uint32_t coop_get_num_groups(const Group& g) { return g.bar.member.M; }
+
+// The flags the last barrier's single step published (algorithm bits from
+// kFlagUser0 up, and kFlagDone once the kernel has finished).
+__device__ __forceinline__ uint32_t coop_flags(const Group& g) { return g.bar.member.flags; }
+
+// The state a joiner takes over (the transmit qualifier of section 3.1).
+// Interval pattern: the single step of a resizing barrier writes it, as the
+// state of workgroup 0 that forked joiners receive ("Global Barriers"), and
+// a joiner reads it once coop_start or coop_rejoin has let it in. Task
+// pattern: coop_request_fork writes it, a joiner reads it once
+// coop_task_start has let it in (the state of the most recent fork that let
+// joiners in).
+__device__ __forceinline__ uint32_t* coop_transmit_block(const Group& g) { return g.ctx->transmit; }
+__device__ __forceinline__ const uint32_t* coop_task_transmitted(const Group& g) { return g.ctx->task.transmit; }
+
+// The host-written target, read over PCIe, or (kModeRelayTarget) the copy
+// one of the kernel's own workgroups keeps in device memory.
+__device__ __forceinline__ uint32_t host_target(const Group& g) {
+    return (g.cfg.mode & kModeRelayTarget) ? ld_relaxed(&g.ctx->T_seen) : ld_system(&g.cfg.host->target);
+}
+
+// query: the number of workgroups the scheduler wants the kernel to keep,
+// the value the paper's efficient resizing barrier asks the scheduler for
+// (section 4.2): the seeded device schedule's current target, the
+// host-written target, or N when nothing else is competing.
+__device__ __forceinline__ uint32_t coop_query(const Group& g) {
+    uint32_t T = g.cfg.N;
+    if (g.cfg.mode & kModeRandomSched) {
+        // the seeded schedule's target (set at resizing barriers; a
+        // task-pattern launch has none and is sized by its kill offers)
+        const uint32_t d = ld_relaxed(&g.ctx->T_dev);
+        if (d) T = d;
+    } else if (g.cfg.host) {
+        T = host_target(g);
+    }
+    if (T < 1u) T = 1u;
+    return T < g.cfg.N ? T : g.cfg.N;
+}
+
+// --------------------------------------------------- interval pattern
+
+// Kernel entry. Returns true if this workgroup is active. In a plain launch
+// every workgroup is (id = block id, M = grid). In a cooperative launch
+// workgroup ticket 0 starts as workgroup 0 with M = 1 (at least one
+// workgroup is active, section 3.1), and every other workgroup -- late ones
+// of the grid and those of joiner grids (coop_fork_groups on the host) --
+// waits to be forked in at a resizing barrier; it returns false if it gave
+// its compute unit back without being admitted. coop_joined() tells a
+// workgroup that entered at a later barrier, which must read the
+// transmitted state.
+template <bool Coop>
+__device__ inline bool coop_start(Group& g, bool joiner_grid) {
+    if (threadIdx.x == 0) {
+        Member m = register_member(g.ctx, g.cfg, !Coop, joiner_grid);
+        if (Coop && m.alive && m.epoch == 0) startup_wait(g.ctx, g.cfg);
+        g.bar.member = m;
+        g.bar.killed = 0;
+    }
+    __syncthreads();
+    return g.bar.member.alive != 0;
+}
+__device__ __forceinline__ bool coop_joined(const Group& g) { return g.bar.member.epoch != 0; }
+
+// resizing_global_barrier (section 3.1, "Global Barriers"; Appendix A,
+// Resizing-Barrier rule): every active workgroup arrives; the last one to
+// arrive runs `single(M, epoch)` with all of its threads while the others
+// wait (the work the paper puts between two barriers: swap the frontiers,
+// reset, level++; it may write the transmit block and returns the flags to
+// publish, kFlagDone to end the kernel); then the scheduler sets the new
+// count M': joiners are forked in first (ids M .. M'-1, the transmit block
+// as their state), then the surplus over the target is killed (Kill rule:
+// the top ids, never workgroup 0; with a host-driven target the victims are
+// chosen per shader engine and the others renumbered densely, Appendix B).
+// Returns false if this workgroup was killed or the kernel is over: the
+// caller leaves (or re-queues with coop_rejoin). All global memory accesses
+// issued before the barrier are complete and visible after it.
+template <bool Coop, class Single>
+__device__ inline bool coop_resizing_global_barrier(Group& g, Single&& single) {
+    Member m = g.bar.member;
+    barrier<Coop>(g.ctx, g.cfg, m, g.bar, single, true);
+    return m.alive != 0;
+}
+template <bool Coop>
+__device__ inline bool coop_resizing_global_barrier(Group& g) {
+    return coop_resizing_global_barrier<Coop>(g, [](uint32_t, uint32_t) -> uint32_t { return 0u; });
+}
+
+// global_barrier (section 3.1, "Global Barriers"; Appendix A, Barrier rule):
+// the same meeting with the active count left unchanged (no fork, no kill).
+// Returns false only when the kernel is over (kFlagDone or an error).
+template <bool Coop, class Single>
+__device__ inline bool coop_global_barrier(Group& g, Single&& single) {
+    Member m = g.bar.member;
+    barrier<Coop>(g.ctx, g.cfg, m, g.bar, single, false);
+    return m.alive != 0;
+}
+template <bool Coop>
+__device__ inline bool coop_global_barrier(Group& g) {
+    return coop_global_barrier<Coop>(g, [](uint32_t, uint32_t) -> uint32_t { return 0u; });
+}
+
+// A workgroup the scheduler killed at a resizing barrier waits to be forked
+// in again (a launch with COOP_F_PARK_KILLED: the compute unit stays with
+// the kernel, which exercises kill and fork without a competing task).
+// Returns true once admitted (it resumes after that barrier, as a joiner).
+template <bool Coop>
+__device__ inline bool coop_rejoin(Group& g) {
+    if (!Coop || !g.bar.killed || !(g.cfg.mode & kModePark)) return false;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        g.bar.member = join_queue(g.ctx, g.cfg);
+        g.bar.killed = 0;
+    }
+    __syncthreads();
+    return g.bar.member.alive != 0;
+}
+
+// ------------------------------------------------------- task pattern
+
+// The scheduler's decision for one workgroup on shader engine `x` that
+// offers to leave (thread 0): accept if the launch holds more than
+// max(T, floor) workgroups and, when the other kernel's workgroups are
+// dealt over `engines` shader engines, this engine holds more than its
+// share ceil(T / engines). The engine's count is claimed first with
+// compare-and-swap, so workgroups of one engine that decide together
+// cannot all leave it; if the launch-wide count is already at its floor
+// the engine's count is given back.
+__device__ inline bool task_leave(TaskState* ts, uint32_t T, uint32_t floor, uint32_t engines, uint32_t x) {
+    const uint32_t lo = T > floor ? T : floor;
+    const bool placed = engines > 1 && engines <= kMaxEngines;
+    const uint32_t share = placed ? (T + engines - 1) / engines : T;
+    uint32_t* ax = &ts->active_x[x % kMaxEngines];
+    if (placed) {
+        uint32_t e = ld_relaxed(ax);
+        for (;;) {
+            if (e <= share) return false;
+            if (__hip_atomic_compare_exchange_strong(ax, &e, e - 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT))
+                break;
+        }
+    }
+    uint32_t a = ld_relaxed(&ts->active);
+    while (a > lo) {
+        if (__hip_atomic_compare_exchange_strong(&ts->active, &a, a - 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)) {
+            if (!placed) add_relaxed(ax, 0xFFFFFFFFu);
+            add_relaxed(&ts->kills, 1u);
+            atomicMin(&ts->min_active, a - 1);
+            return true;
+        }
+    }
+    if (placed) add_relaxed(ax, 1u);          // the launch is at its floor: stay
+    return false;
+}
+
+// Thread 0: become active in slot `s` or the next free one after it.
+__device__ inline bool task_claim(Ctx* c, const Cfg& cfg, uint32_t s0, Member& m) {
+    TaskState* ts = &c->task;
+    for (uint32_t k = 0; k < cfg.N; ++k) {
+        const uint32_t s = (s0 + k) % cfg.N;
+        uint32_t expected = 0;
+        if (__hip_atomic_compare_exchange_strong(&ts->slot_owner[s], &expected, 1u, __ATOMIC_ACQUIRE,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            const uint32_t x = engine_id(cfg.ses);
+            st_relaxed(&c->engine_of[s], x);
+            add_relaxed(&ts->active_x[x % kMaxEngines], 1u);
+            m.id = s;
+            m.alive = 1;
+            return true;
+        }
+    }
+    return false;
+}
+
+// Task-pattern entry. Workgroups of the launch's own grid are scheduled
+// initially (section 3.1: the scheduler may start fewer than N; every one
+// that starts is active) and take a slot. A workgroup of a joiner grid is a
+// fork: it waits until an active workgroup's coop_request_fork lets it in
+// (then it starts after that call, with the transmitted state), and gives
+// its compute unit back if the kernel finishes, the target leaves no room,
+// or the watchdog expires first. Returns true if this workgroup is active.
+template <bool Coop>
+__device__ inline bool coop_task_start(Group& g, bool joiner_grid) {
+    if (threadIdx.x == 0) {
+        Ctx* c = g.ctx;
+        TaskState* ts = &c->task;
+        Member m{};
+        m.alive = 0;
+        const uint32_t lim = g.cfg.N;
+        if (!joiner_grid || !Coop) {
+            // the initial schedule: at most N workgroups
+            uint32_t a = ld_relaxed(&ts->active);
+            bool room = false;
+            while (a < lim) {
+                if (__hip_atomic_compare_exchange_strong(&ts->active, &a, a + 1, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    room = true;
+                    break;
+                }
+            }
+            if (room) {
+                if (task_claim(c, g.cfg, blockIdx.x % lim, m)) atomicMax(&ts->max_active, a + 1);
+                else add_relaxed(&ts->active, 0xFFFFFFFFu);
+            }
+        } else {
+            const uint32_t t = add_relaxed(&ts->join_tickets, 1u);
+            const uint64_t t0 = now_ticks();
+            for (uint32_t it = 0;; ++it) {
+                const uint64_t r = ld_relaxed64(&c->release);
+                if ((rel_flags(r) & (kFlagAbort | kFlagDone)) || ld_relaxed_i(&c->error)) break;
+                if ((int32_t)(ld_relaxed(&ts->join_granted) - t) > 0) {
+                    // let in: take a unit of room under the target, then a slot
+                    fence_acquire();
+                    uint32_t T = lim;
+                    if (g.cfg.host) T = host_target(g);
+                    if (T < 1u) T = 1u;
+                    const uint32_t cap = T < lim ? T : lim;
+                    uint32_t a = ld_relaxed(&ts->active);
+                    bool room = false;
+                    while (a < cap) {
+                        if (__hip_atomic_compare_exchange_strong(&ts->active, &a, a + 1, __ATOMIC_RELAXED,
+                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                            room = true;
+                            break;
+                        }
+                    }
+                    if (room) {
+                        if (task_claim(c, g.cfg, (blockIdx.x * 2654435761u) % lim, m)) {
+                            atomicMax(&ts->max_active, a + 1);
+                            add_relaxed(&ts->forks, 1u);
+                        } else {
+                            add_relaxed(&ts->active, 0xFFFFFFFFu);
+                        }
+                    }
+                    break;
+                }
+                if (g.cfg.host && (it & 15) == 15 && host_target(g) <= ld_relaxed(&ts->active))
+                    break;                          // no room under the target: give the unit back
+                if (now_ticks() - t0 > g.cfg.watchdog_ticks) break;
+                __builtin_amdgcn_s_sleep(4);
+            }
+        }
+        m.M = ld_relaxed(&ts->active);
+        g.bar.member = m;
+        g.bar.killed = 0;
+        g.bar.offers = 0;
+    }
+    __syncthreads();
+    return g.bar.member.alive != 0;
+}
+
+// offer_kill (section 3.1, "Semantics for offer_kill"; Appendix A, Kill and
+// Kill-No-Op rules, with the any-order kill of Appendix B): the scheduler
+// may take this workgroup back; returns false if it did, and the workgroup
+// must then leave the kernel (its slot is free for a joiner). The decision:
+// a seeded device schedule accepts with the launch's probability; a
+// host-driven target accepts while the launch holds more than the target,
+// choosing workgroups on the shader engines the other kernel needs
+// (task_leave); otherwise the offer is a no-op. The host target is read on
+// every eighth offer (the others are no-ops, which the Kill-No-Op rule
+// allows), and never fewer than Cfg::keep workgroups stay.
+template <bool Coop>
+__device__ inline bool coop_offer_kill(Group& g) {
+    if (!Coop) return true;
+    if (threadIdx.x == 0) {
+        TaskState* ts = &g.ctx->task;
+        const uint32_t floor = g.cfg.keep ? g.cfg.keep : 1u;
+        const uint32_t x = ld_relaxed(&g.ctx->engine_of[g.bar.member.id]);
+        bool killed = false;
+        if (g.cfg.mode & kModeRandomSched) {
+            const uint32_t d = add_relaxed(&ts->decisions, 1u);
+            const uint64_t h = splitmix64(g.cfg.sched_seed + (uint64_t)d * 0x9E3779B97F4A7C15ull);
+            if ((uint32_t)(h & 0xFFFFu) < g.cfg.sched_p16) killed = task_leave(ts, 0u, floor, 1u, x);
+        } else if (g.cfg.host && (g.bar.offers++ & 7u) == 0) {
+            killed = task_leave(ts, host_target(g), floor, g.cfg.engines, x);
+        }
+        if (killed) {
+            __hip_atomic_store(&ts->slot_owner[g.bar.member.id], 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            g.bar.member.alive = 0;
+            g.bar.killed = 1;
+        }
+    }
+    __syncthreads();
+    return g.bar.member.alive != 0;
+}
+
+// request_fork (section 3.1, "Semantics for offer_fork"; Appendix A, Fork
+// rule): the scheduler chooses k in [0, N - M] -- here the joiners waiting
+// to come in, at most the room the target leaves -- and that many join after
+// this call, each with the `words` words of `state` (the transmitted
+// variables of thread 0, read by joiners with coop_task_transmitted). Returns k
+// (joiners let in: each takes a unit of room when it starts, so a joiner
+// that finds none gives its compute unit back). k = 0 is always legal.
+template <bool Coop>
+__device__ inline uint32_t coop_request_fork(Group& g, const uint32_t* state = nullptr, uint32_t words = 0) {
+    if (!Coop) return 0;
+    __shared__ uint32_t forked;
+    if (threadIdx.x == 0) {
+        TaskState* ts = &g.ctx->task;
+        const uint32_t waiting = ld_relaxed(&ts->join_tickets) - ld_relaxed(&ts->join_granted);
+        uint32_t k = 0;
+        if ((int32_t)waiting > 0) {
+            const uint32_t T = coop_query(g);
+            const uint32_t a = ld_relaxed(&ts->active);
+            const uint32_t room = T > a ? T - a : 0u;
+            k = waiting < room ? waiting : room;
+            if (k) {
+                for (uint32_t i = 0; i < words && i < kTransmitWords; ++i) st_relaxed(&ts->transmit[i], state[i]);
+                __hip_atomic_fetch_add(&ts->join_granted, k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        forked = k;
+    }
+    __syncthreads();
+    return forked;
+}
+
+// The kernel's work is over (task pattern): joiners still waiting leave.
+__device__ inline void coop_task_finish(Group& g) {
+    if (threadIdx.x == 0)
+        __hip_atomic_fetch_or(&g.ctx->release, (uint64_t)kFlagDone << 48, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A task-pattern workgroup leaving for a reason of its own (work finished,
+// error): its slot and its unit of the active count are given back.
+__device__ inline void coop_task_leave(Group& g) {
+    if (threadIdx.x == 0 && g.bar.member.alive) {
+        TaskState* ts = &g.ctx->task;
+        const uint32_t id = g.bar.member.id;
+        add_relaxed(&ts->active_x[ld_relaxed(&g.ctx->engine_of[id]) % kMaxEngines], 0xFFFFFFFFu);
+        add_relaxed(&ts->active, 0xFFFFFFFFu);
+        __hip_atomic_store(&ts->slot_owner[id], 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        g.bar.member.alive = 0;
+    }
+    __syncthreads();
 }
 
 }  // namespace coop

@@ -33,6 +33,7 @@ COOP_F_HOST_SCHEDULE = 4
 COOP_F_TOP_DOWN_ONLY = 8
 COOP_F_REGULAR_BARRIER = 16
 COOP_KERNEL_OCTREE = 8
+COOP_KERNEL_CC = 9
 
 COOP_KERNEL_BFS = 1
 COOP_KERNEL_SSSP = 2
@@ -57,10 +58,11 @@ UNREACHED_DIST = 0x7FFFFFFF
 EXPORTS = [
     "coop_strerror", "coop_launch_opts_default", "coop_init", "coop_shutdown", "coop_device_query",
     "coop_last_hip_error", "coop_graph_wrap", "coop_graph_release", "coop_bfs", "coop_sssp",
-    "coop_color", "coop_mis", "coop_launch", "coop_wait", "coop_handle_groups", "coop_set_target",
+    "coop_cc", "coop_color", "coop_mis", "coop_launch", "coop_wait", "coop_handle_groups", "coop_set_target",
     "coop_fork_groups", "coop_cotask_run", "coop_injector_start", "coop_injector_stop",
     "coop_share_start", "coop_share_add", "coop_share_stop", "coop_octree",
     "coop_barrier_bench", "coop_tune_default", "coop_batch_run", "coop_batch_autotune",
+    "coop_tune_cache_save", "coop_tune_cache_load", "coop_tune_cache_clear",
     "coop_server_cfg_default", "coop_server_create", "coop_server_submit", "coop_server_poll",
     "coop_server_wait", "coop_server_stats", "coop_server_handle", "coop_server_destroy",
 ]
@@ -84,7 +86,7 @@ class coop_launch_opts(ctypes.Structure):
         ("strip", ctypes.c_uint32), ("startup_wait_ns", ctypes.c_uint32), ("sched_seed", ctypes.c_uint64),
         ("sched_p", ctypes.c_double), ("watchdog_ns", ctypes.c_uint64),
         ("d_trace", ctypes.c_void_p), ("trace_cap", ctypes.c_uint32), ("join_window", ctypes.c_uint32),
-        ("d_wgtrace", ctypes.c_void_p),
+        ("d_wgtrace", ctypes.c_void_p), ("bu_alpha", ctypes.c_uint32), ("bu_beta", ctypes.c_uint32),
     ]
 
 
@@ -228,6 +230,7 @@ def load_library():
         "coop_bfs": (i32, [VP, VP, VP, u32, VP, u64, ctypes.POINTER(coop_launch_opts), VP, VPP]),
         "coop_sssp": (i32, [VP, VP, VP, u32, VP, u64, ctypes.POINTER(coop_launch_opts), VP, VPP]),
         "coop_color": (i32, [VP, VP, u64, VP, ctypes.POINTER(coop_launch_opts), VP, VPP]),
+        "coop_cc": (i32, [VP, VP, VP, ctypes.POINTER(coop_launch_opts), VP, VPP]),
         "coop_mis": (i32, [VP, VP, u64, VP, ctypes.POINTER(coop_launch_opts), VP, VPP]),
         "coop_launch": (i32, [VP, i32, ctypes.POINTER(coop_params), ctypes.POINTER(coop_launch_opts), VP, VPP]),
         "coop_wait": (i32, [VP, ctypes.POINTER(coop_stats)]),
@@ -256,6 +259,9 @@ def load_library():
         "coop_server_destroy": (i32, [VP]),
         "coop_batch_run": (i32, [VP, ctypes.POINTER(coop_batch_item), u32, ctypes.POINTER(coop_tune),
                                  ctypes.POINTER(coop_launch_opts), VP, VPP]),
+        "coop_tune_cache_save": (i32, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_uint32)]),
+        "coop_tune_cache_load": (i32, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_uint32)]),
+        "coop_tune_cache_clear": (None, []),
         "coop_batch_autotune": (i32, [VP, ctypes.POINTER(coop_batch_item), u32, u32, u32,
                                       ctypes.POINTER(coop_launch_opts), VP, ctypes.POINTER(coop_tune),
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
@@ -353,6 +359,14 @@ def coop_sssp(rt, g, roots, nroots, dist, out_stride=0, opts=None, stream=None, 
                                   ctypes.byref(opts) if opts is not None else None, _stream(stream),
                                   ctypes.byref(h) if keep else None)
     _check(rc, "coop_sssp")
+    return h.value if keep else None
+
+
+def coop_cc(rt, g, label, opts=None, stream=None, keep=True):
+    h = _handle_out(keep)
+    rc = load_library().coop_cc(rt, g, _ptr(label), ctypes.byref(opts) if opts is not None else None,
+                                _stream(stream), ctypes.byref(h) if keep else None)
+    _check(rc, "coop_cc")
     return h.value if keep else None
 
 
@@ -495,6 +509,22 @@ def coop_batch_autotune(rt, items, stride=1, reps=3, opts=None, stream=None) -> 
                                               ctypes.byref(best), ctypes.byref(bms), ctypes.byref(dms)),
            "coop_batch_autotune")
     return best, bms.value, dms.value
+
+
+def coop_tune_cache_save(path: str) -> int:
+    n = ctypes.c_uint32()
+    _check(load_library().coop_tune_cache_save(os.fsencode(path), ctypes.byref(n)), "coop_tune_cache_save")
+    return n.value
+
+
+def coop_tune_cache_load(path: str) -> int:
+    n = ctypes.c_uint32()
+    _check(load_library().coop_tune_cache_load(os.fsencode(path), ctypes.byref(n)), "coop_tune_cache_load")
+    return n.value
+
+
+def coop_tune_cache_clear() -> None:
+    load_library().coop_tune_cache_clear()
 
 
 def coop_server_cfg_default() -> coop_server_cfg:
@@ -656,6 +686,13 @@ class Runtime:
     def batch(self, items, tune=None, opts=None, stream=None):
         h = coop_batch_run(self.rt, items, tune, opts, stream)
         return coop_wait(h)
+
+    def cc(self, dg: DeviceGraph, opts=None, stream=None):
+        import torch
+        out = torch.empty(dg.n, dtype=torch.int32, device="cuda")
+        h = coop_cc(self.rt, dg.handle, out, opts, stream)
+        rc, st = coop_wait(h)
+        return rc, out, st
 
     def mis(self, dg: DeviceGraph, prio_seed: int, opts=None, stream=None):
         import torch

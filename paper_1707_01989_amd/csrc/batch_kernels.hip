@@ -66,42 +66,29 @@ __device__ __forceinline__ void color_team(const ColorArgs& p, BlockLds& sh, uin
     }
 }
 
-// offer_kill between instances (thread 0): the host target or a seeded
-// random decision, never below team_max workgroups.
-template <bool Coop>
-__device__ bool batch_offer_kill(const BatchArgs& a, BatchCtl* ctl, uint32_t x) {
-    if (!Coop) return false;
-    const LeaveCounters lc{&ctl->active, ctl->active_x, &ctl->kills, &ctl->min_active};
-    if (a.cfg.mode & kModeRandomSched) {
-        const uint32_t d = add_relaxed(&ctl->decisions, 1u);
-        const uint64_t h = splitmix64(a.cfg.sched_seed + (uint64_t)d * 0x9E3779B97F4A7C15ull);
-        if ((uint32_t)(h & 0xFFFFu) >= a.cfg.sched_p16) return false;
-        return leave_for_target(lc, 0u, a.team_max, 1u, x);
-    }
-    if (a.cfg.host) return leave_for_target(lc, ld_system(&a.cfg.host->target), a.team_max, a.cfg.engines, x);
-    return false;
-}
-
 template <bool Coop>
 __device__ void batch_body(const BatchArgs& a, bool joiner) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     BlockLds& sh = *reinterpret_cast<BlockLds*>(lds_raw);
     BatchCtl* ctl = a.ctl;
+    Group g(a.ctx, a.cfg, sh.bar);
     ConstU32* first = (ConstU32*)(uintptr_t)a.first;
     const uint32_t total = first[a.count];
     if (threadIdx.x == 0) {
         // only the waves of this group size have LDS behind them
         for (uint32_t i = 0; i < num_waves(); ++i) sh.wave[i].out_n = 0;
         for (int i = 0; i < 8; ++i) sh.acc[i] = 0;
-        const uint32_t act = add_relaxed(&ctl->active, 1u) + 1;
-        add_relaxed(&ctl->active_x[engine_id(a.cfg.ses) % kMaxEngines], 1u);
-        atomicMax(&ctl->max_active, act);
-        if (joiner) add_relaxed(&ctl->forks, 1u);
     }
+    // the task pattern of the programming model: a workgroup holds no team
+    // state between instances, which is where it offers itself to the
+    // scheduler (offer_kill: host target or seeded schedule, never below
+    // team_max workgroups) and lets waiting joiners in (request_fork)
+    if (!coop_task_start<Coop>(g, joiner)) return;
     for (;;) {
+        if (!coop_offer_kill<Coop>(g)) return;
+        coop_request_fork<Coop>(g);
         if (threadIdx.x == 0) {
             uint32_t leave = ld_relaxed_i(&ctl->error) ? 1u : 0u;
-            if (!leave && batch_offer_kill<Coop>(a, ctl, engine_id(a.cfg.ses))) leave = 2;
             if (!leave) {
                 const uint32_t k = add_relaxed(&ctl->ticket, 1u);
                 if (k >= total) {
@@ -116,15 +103,16 @@ __device__ void batch_body(const BatchArgs& a, bool joiner) {
                     sh.aux = k - first[lo];
                 }
             }
-            if (leave == 1 || leave == 3) {
-                add_relaxed(&ctl->active, 0xFFFFFFFFu);
-                add_relaxed(&ctl->active_x[engine_id(a.cfg.ses) % kMaxEngines], 0xFFFFFFFFu);
-                add_relaxed(&ctl->left, 1u);
-            }
+            if (leave) add_relaxed(&ctl->left, 1u);
             sh.level = leave;
         }
         __syncthreads();
-        if (sh.level) return;
+        if (sh.level) {
+            // out of work (or an instance failed): joiners still waiting go too
+            coop_task_leave(g);
+            coop_task_finish(g);
+            return;
+        }
         const uint32_t i = __builtin_amdgcn_readfirstlane(sh.root);
         const uint32_t rank = __builtin_amdgcn_readfirstlane(sh.aux);
         const BatchInst& I = *(const BatchInst*)((ConstInst*)(uintptr_t)a.inst + i);
@@ -165,7 +153,6 @@ __global__ void batch_init_kernel(TeamState* teams, const BatchInst* inst, uint3
         uint32_t* w = reinterpret_cast<uint32_t*>(ctl);
         for (uint32_t i = threadIdx.x; i < sizeof(BatchCtl) / 4; i += blockDim.x) w[i] = 0;
         __syncthreads();
-        if (threadIdx.x == 0) ctl->min_active = 0xFFFFFFFFu;
     }
 }
 

@@ -121,6 +121,7 @@ struct BfsArgs {
     uint32_t direction_opt;    // 0: top-down only; 1: switch to bottom-up on large frontiers
     uint32_t alpha, beta;      // switching parameters (Beamer et al.)
     uint64_t total_arcs;
+    uint32_t bu_prefetch;      // bottom-up levels stage each block's row ranges in LDS
 };
 
 struct SsspArgs {
@@ -187,24 +188,19 @@ struct alignas(16) BatchInst {
 };
 
 // Launch-wide counters of a batched launch.
+// Counters of a batched launch (who is active, who left for the scheduler
+// and who joined live in the launch context's task state).
 struct alignas(256) BatchCtl {
     uint32_t ticket;           // next (instance, rank) entry
     uint32_t _p0[63];
-    uint32_t active;           // workgroups inside the instance loop
-    uint32_t _p1[63];
-    uint32_t decisions;        // random schedule: kill decisions taken
     int32_t error;
-    uint32_t kills;
-    uint32_t forks;            // workgroups of joiner grids that entered
     uint32_t left;             // workgroups that left when tickets ran out
-    uint32_t min_active;
-    uint32_t max_active;
-    uint32_t _p2[57];
-    uint32_t active_x[kMaxEngines];   // active workgroups per shader engine
+    uint32_t _p2[62];
 };
 
 struct BatchArgs {
-    Cfg cfg;                   // N, mode (kill policy), host target, watchdog
+    Cfg cfg;                   // N, mode (kill policy), host target, watchdog, keep = team_max
+    Ctx* ctx;                  // launch context: task state (active count, kills, forks)
     const BatchInst* inst;     // `count` descriptors in ticket order
     const uint32_t* first;     // count + 1: first ticket of each instance
     TeamState* teams;          // count team blocks
@@ -261,24 +257,27 @@ struct alignas(64) ServeDone {
     uint32_t pad[11];
 };
 
+// Device-side words of the server. Who is active, who left for the
+// scheduler and who joined live in the launch context's task state.
 struct alignas(256) ServeCtl {
     uint32_t ticket;           // next ticket to draw
     uint32_t _p0[63];
-    uint32_t active;           // workgroups inside the server loop
-    uint32_t _p1[63];
     int32_t error;
-    uint32_t kills;            // workgroups that left for the scheduler
-    uint32_t forks;            // joiner workgroups that entered
     uint32_t left;             // workgroups that left at shutdown
-    uint32_t min_active;
-    uint32_t max_active;
     uint32_t queries;          // queries completed
-    uint32_t _p2[57];
-    uint32_t active_x[kMaxEngines];   // active workgroups per shader engine
+    uint32_t _p1[61];
+    // the relay: one idle workgroup at a time reads the host's words over
+    // PCIe and republishes them here, where every other idle workgroup polls
+    uint32_t relay;            // 1 while an idle workgroup holds the role
+    uint32_t end;              // the host's published ticket end, as relayed
+    uint32_t stop;             // the host's stop word, as relayed
+    uint32_t beat;             // advanced by the relay at every poll
+    uint32_t _p2[60];
 };
 
 struct ServeArgs {
-    Cfg cfg;                   // N, mode, host target (co-task), watchdog
+    Cfg cfg;                   // N, mode, host target (co-task), watchdog, keep = team_max
+    Ctx* ctx;                  // launch context: task state, and the relayed host target (T_seen)
     const ServeDesc* desc;     // slots x graphs descriptors
     TeamState* teams;          // per slot: barrier lines and transmit block
     ServeCtl* ctl;
@@ -288,6 +287,8 @@ struct ServeArgs {
     ServeDone* done;           // pinned, one per slot
     uint32_t owner_cap;
     uint32_t team_max;         // the kill rule keeps at least this many workgroups
+    uint32_t slots;            // query slots (records, completion words)
+    uint32_t ndesc;            // descriptors (slots x graphs)
 };
 
 // ------------------------------------------------ work-stealing octree
@@ -312,17 +313,11 @@ struct alignas(256) OctCtl {
     uint32_t node_count;       // nodes allocated (node 0 = root)
     uint32_t leaf_count;
     uint32_t _p1[62];
-    uint32_t active;           // workgroups inside the loop
-    uint32_t kills;            // workgroups that left for the scheduler
-    uint32_t forks;            // joiner workgroups that entered
-    uint32_t min_active;
-    uint32_t max_active;
     int32_t error;
-    uint32_t _p2[58];
+    uint32_t _p2[63];
     uint32_t tasks;            // cubes split
     uint32_t steals;           // tasks taken from another slot's queue
     uint32_t _p3[62];
-    uint32_t active_x[kMaxEngines];
 };
 
 struct OctreeArgs {
@@ -334,12 +329,26 @@ struct OctreeArgs {
     uint32_t* leaves;          // 8 words per leaf {first, end, depth, code_lo, code_hi, -, -, -}
     uint32_t leaf_cap;
     OctCtl* ctl;
-    OctQueue* q;               // N queues
-    uint32_t* slot_owner;      // N words: 1 while a workgroup owns the slot
+    OctQueue* q;               // N queues, one per slot (the workgroup id of the task pattern)
+    Ctx* ctx;                  // launch context: task state (slots, active count, kills, forks)
 };
 
 hipError_t launch_octree_init(const OctreeArgs& a, const uint32_t* x, const uint32_t* y, const uint32_t* z,
                               hipStream_t s);
+
+// ------------------------------------- connected components (label propagation)
+
+struct CcArgs {
+    Cfg cfg;
+    Ctx* ctx;
+    const uint32_t* row_ptr;
+    const uint32_t* col;
+    uint32_t n;
+    uint32_t* label;           // n labels (the output)
+    uint32_t* changed;         // two round marks, 64 words apart
+};
+hipError_t launch_cc(const CcArgs& a, bool coop, bool joiner_grid, uint32_t grid, uint32_t block,
+                     uint32_t lds_bytes, hipStream_t s);
 hipError_t launch_octree(const OctreeArgs& a, bool coop, bool joiner_grid, uint32_t grid, uint32_t block,
                          uint32_t lds_bytes, hipStream_t s);
 

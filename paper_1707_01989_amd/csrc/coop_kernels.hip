@@ -32,57 +32,55 @@
 
 namespace {
 
+// Every body below is written against the programming-model calls of
+// coop_device.hpp (coop_start, coop_resizing_global_barrier,
+// coop_get_group_id / coop_get_num_groups, coop_rejoin); the level state a
+// joiner takes over is the Work block's transmit words, written by the
+// barrier's single step.
+
 template <bool Coop>
 __device__ void bfs_body(const BfsArgs& p, bool joiner_grid) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     BlockLds& sh = *reinterpret_cast<BlockLds*>(lds_raw);
     const TraversalArgs& t = p.t;
     Ctx* c = static_cast<Ctx*>(t.ctx);
+    Group g(c, t.cfg, sh.bar);
     Work* wk = t.work;
 
+    coop_start<Coop>(g, joiner_grid);
     if (threadIdx.x == 0) {
-        Member m = register_member(c, t.cfg, !Coop, joiner_grid);
-        if (Coop && m.alive && m.epoch == 0) startup_wait(c, t.cfg);
-        sh.level = m.alive && m.epoch != 0 ? wk->x.level : 0u;
-        sh.root = m.alive && m.epoch != 0 ? wk->x.root : 0u;
+        const bool joined = g.bar.member.alive && coop_joined(g);
+        sh.level = joined ? wk->x.level : 0u;
+        sh.root = joined ? wk->x.root : 0u;
         for (int i = 0; i < 8; ++i) sh.acc[i] = 0;
-        sh.bar.member = m;
-        sh.bar.killed = 0;
     }
     __syncthreads();
-    Member m = sh.bar.member;
     uint32_t level = sh.level, root = sh.root;
-    bool fresh = m.epoch == 0;      // initial members begin at the registration barrier
+    bool fresh = !coop_joined(g);   // initial members begin at the registration barrier
 
     for (;;) {
-        if (!m.alive) {
-            if (Coop && sh.bar.killed && (t.cfg.mode & kModePark)) {
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    sh.bar.member = join_queue(c, t.cfg);
-                    sh.bar.killed = 0;
-                    sh.level = wk->x.level;
-                    sh.root = wk->x.root;
-                }
-                __syncthreads();
-                m = sh.bar.member;
-                level = sh.level;
-                root = sh.root;
-                if (m.alive) continue;
+        if (!g.bar.member.alive) {
+            if (!coop_rejoin<Coop>(g)) return;
+            if (threadIdx.x == 0) {
+                sh.level = wk->x.level;
+                sh.root = wk->x.root;
             }
-            return;
+            __syncthreads();
+            level = sh.level;
+            root = sh.root;
+            continue;
         }
-        const uint32_t ph = fresh ? kPhStart : (m.flags & kPhMask);
+        const uint32_t cur_flags = coop_flags(g);
+        const uint32_t ph = fresh ? kPhStart : (cur_flags & kPhMask);
+        const uint32_t id = coop_get_group_id(g), M = coop_get_num_groups(g);
         fresh = false;
-        wg_trace(t.cfg, m.epoch, m.id, kTrStart);
-        bfs_phase(p, sh, ph, m.flags, level, root, m.id, m.M, p.level_out);
-        wg_trace(t.cfg, m.epoch, m.id, kTrWorkDone);
-        const uint32_t cur_flags = m.flags;
-        barrier<Coop>(c, t.cfg, m, sh.bar,
-                      [&](uint32_t, uint32_t) -> uint32_t {
-                          return bfs_master(p, sh, c, ph, cur_flags, t.roots, p.level_out);
-                      });
-        bfs_follow(ph, m.flags, level, root);
+        wg_trace(t.cfg, g.bar.member.epoch, id, kTrStart);
+        bfs_phase(p, sh, ph, cur_flags, level, root, id, M, p.level_out);
+        wg_trace(t.cfg, g.bar.member.epoch, id, kTrWorkDone);
+        coop_resizing_global_barrier<Coop>(g, [&](uint32_t, uint32_t) -> uint32_t {
+            return bfs_master(p, sh, c, ph, cur_flags, t.roots, p.level_out);
+        });
+        bfs_follow(ph, coop_flags(g), level, root);
     }
 }
 
@@ -94,50 +92,39 @@ __device__ void sssp_body(const SsspArgs& p, bool joiner_grid) {
     BlockLds& sh = *reinterpret_cast<BlockLds*>(lds_raw);
     const TraversalArgs& t = p.t;
     Ctx* c = static_cast<Ctx*>(t.ctx);
+    Group g(c, t.cfg, sh.bar);
     Work* wk = t.work;
 
+    coop_start<Coop>(g, joiner_grid);
     if (threadIdx.x == 0) {
-        Member m = register_member(c, t.cfg, !Coop, joiner_grid);
-        if (Coop && m.alive && m.epoch == 0) startup_wait(c, t.cfg);
-        const bool joined = m.alive && m.epoch != 0;
+        const bool joined = g.bar.member.alive && coop_joined(g);
         sh.root = joined ? wk->x.root : 0u;
         for (uint32_t i = 0; i < num_waves(); ++i) sh.wave[i].out_n = 0;
         for (int i = 0; i < 8; ++i) sh.acc[i] = 0;
-        sh.bar.member = m;
-        sh.bar.killed = 0;
     }
     __syncthreads();
-    Member m = sh.bar.member;
     uint32_t root = sh.root;
-    bool fresh = m.epoch == 0;
+    bool fresh = !coop_joined(g);
 
     for (;;) {
-        if (!m.alive) {
-            if (Coop && sh.bar.killed && (t.cfg.mode & kModePark)) {
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    sh.bar.member = join_queue(c, t.cfg);
-                    sh.bar.killed = 0;
-                    sh.root = wk->x.root;
-                }
-                __syncthreads();
-                m = sh.bar.member;
-                root = sh.root;
-                if (m.alive) continue;
-            }
-            return;
+        if (!g.bar.member.alive) {
+            if (!coop_rejoin<Coop>(g)) return;
+            if (threadIdx.x == 0) sh.root = wk->x.root;
+            __syncthreads();
+            root = sh.root;
+            continue;
         }
-        const uint32_t ph = fresh ? kPhStart : (m.flags & kPhMask);
+        const uint32_t cur_flags = coop_flags(g);
+        const uint32_t ph = fresh ? kPhStart : (cur_flags & kPhMask);
+        const uint32_t id = coop_get_group_id(g), M = coop_get_num_groups(g);
         fresh = false;
-        wg_trace(t.cfg, m.epoch, m.id, kTrStart);
-        sssp_phase(p, sh, ph, m.flags, p.dist_out + (size_t)root * t.out_stride, m.id, m.M);
-        wg_trace(t.cfg, m.epoch, m.id, kTrWorkDone);
-        const uint32_t cur_flags = m.flags;
-        barrier<Coop>(c, t.cfg, m, sh.bar,
-                      [&](uint32_t, uint32_t) -> uint32_t {
-                          return sssp_master(p, sh, c, ph, cur_flags, t.roots, p.dist_out);
-                      });
-        sssp_follow(ph, m.flags, root);
+        wg_trace(t.cfg, g.bar.member.epoch, id, kTrStart);
+        sssp_phase(p, sh, ph, cur_flags, p.dist_out + (size_t)root * t.out_stride, id, M);
+        wg_trace(t.cfg, g.bar.member.epoch, id, kTrWorkDone);
+        coop_resizing_global_barrier<Coop>(g, [&](uint32_t, uint32_t) -> uint32_t {
+            return sssp_master(p, sh, c, ph, cur_flags, t.roots, p.dist_out);
+        });
+        sssp_follow(ph, coop_flags(g), root);
     }
 }
 
@@ -147,39 +134,28 @@ __device__ void color_body(const ColorArgs& p, bool joiner_grid) {
     BlockLds& sh = *reinterpret_cast<BlockLds*>(lds_raw);
     const TraversalArgs& t = p.t;
     Ctx* c = static_cast<Ctx*>(t.ctx);
+    Group g(c, t.cfg, sh.bar);
 
+    coop_start<Coop>(g, joiner_grid);
     if (threadIdx.x == 0) {
-        Member m = register_member(c, t.cfg, !Coop, joiner_grid);
-        if (Coop && m.alive && m.epoch == 0) startup_wait(c, t.cfg);
         for (uint32_t i = 0; i < num_waves(); ++i) sh.wave[i].out_n = 0;
         for (int i = 0; i < 8; ++i) sh.acc[i] = 0;
-        sh.bar.member = m;
-        sh.bar.killed = 0;
     }
     __syncthreads();
-    Member m = sh.bar.member;
-    bool fresh = m.epoch == 0;
+    bool fresh = !coop_joined(g);
 
     for (;;) {
-        if (!m.alive) {
-            if (Coop && sh.bar.killed && (t.cfg.mode & kModePark)) {
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    sh.bar.member = join_queue(c, t.cfg);
-                    sh.bar.killed = 0;
-                }
-                __syncthreads();
-                m = sh.bar.member;
-                if (m.alive) continue;
-            }
-            return;
+        if (!g.bar.member.alive) {
+            if (!coop_rejoin<Coop>(g)) return;
+            continue;
         }
-        const uint32_t ph = fresh ? kPhStart : (m.flags & kPhMask);
+        const uint32_t cur_flags = coop_flags(g);
+        const uint32_t ph = fresh ? kPhStart : (cur_flags & kPhMask);
         fresh = false;
-        color_phase(p, sh, ph, m.flags, m.id, m.M);
-        const uint32_t cur_flags = m.flags;
-        barrier<Coop>(c, t.cfg, m, sh.bar,
-                      [&](uint32_t, uint32_t) -> uint32_t { return color_master(p, sh, ph, cur_flags); });
+        color_phase(p, sh, ph, cur_flags, coop_get_group_id(g), coop_get_num_groups(g));
+        coop_resizing_global_barrier<Coop>(g, [&](uint32_t, uint32_t) -> uint32_t {
+            return color_master(p, sh, ph, cur_flags);
+        });
     }
 }
 
@@ -190,20 +166,12 @@ __device__ void barrier_bench_body(const BarrierBenchArgs& p, bool joiner_grid) 
     extern __shared__ __align__(16) unsigned char lds_raw[];
     BlockLds& sh = *reinterpret_cast<BlockLds*>(lds_raw);
     Ctx* c = p.ctx;
-    if (threadIdx.x == 0) {
-        Member m = register_member(c, p.cfg, !Coop, joiner_grid);
-        if (Coop && m.alive && m.epoch == 0) startup_wait(c, p.cfg);
-        sh.bar.member = m;
-        sh.bar.killed = 0;
-    }
-    __syncthreads();
-    Member m = sh.bar.member;
-    for (;;) {
-        if (!m.alive) return;
-        barrier<Coop>(c, p.cfg, m, sh.bar, [&](uint32_t, uint32_t ne) -> uint32_t {
-            if (ne == 1 && threadIdx.x == 0) c->t_start = now_ticks();
-            return ne > p.iters ? kFlagDone : 0u;
-        });
+    Group g(c, p.cfg, sh.bar);
+    if (!coop_start<Coop>(g, joiner_grid)) return;
+    while (coop_resizing_global_barrier<Coop>(g, [&](uint32_t, uint32_t ne) -> uint32_t {
+        if (ne == 1 && threadIdx.x == 0) c->t_start = now_ticks();
+        return ne > p.iters ? kFlagDone : 0u;
+    })) {
     }
 }
 
@@ -235,11 +203,15 @@ __global__ void init_ctx_kernel(Ctx* c, Work* w) {
         c->xcd.members[i] = 0;
     }
     if (tid == 0) c->xcd.groups = 0;
+    uint32_t* tw = reinterpret_cast<uint32_t*>(&c->task);
+    for (uint32_t i = tid; i < sizeof(TaskState) / 4; i += blockDim.x) tw[i] = 0;
+    for (uint32_t i = tid; i < 64; i += blockDim.x) c->transmit[i] = 0;
     uint32_t* ww = reinterpret_cast<uint32_t*>(w);
     for (uint32_t i = tid; i < sizeof(Work) / 4; i += blockDim.x) ww[i] = 0;
     __syncthreads();
     if (tid == 0) {
         c->min_M = 0xFFFFFFFFu;
+        c->task.min_active = 0xFFFFFFFFu;
         c->release = make_release(0, 1, 0);
     }
 }

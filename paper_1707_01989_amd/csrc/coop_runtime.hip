@@ -117,6 +117,8 @@ struct coop_handle {
     coop::ServeArgs serve{};
     // work-stealing octree
     coop::OctreeArgs octree{};
+    // connected components
+    coop::CcArgs cc{};
 };
 
 struct coop_rt {
@@ -243,7 +245,7 @@ void reap(coop_rt* rt) {
     }
 }
 
-void* scratch(coop_handle* h, size_t bytes) {
+void* scratch_buf(coop_handle* h, size_t bytes) {
     void* p = pool_get(h->rt, bytes);
     if (p) h->scratch.emplace_back(p, bytes);
     return p;
@@ -313,7 +315,7 @@ int begin_launch(coop_rt* rt, const coop_launch_opts* o, const Sizing& sz, int k
     h->lds = sz.lds;
     h->stream = stream;
     const size_t cbytes = sizeof(Ctx) + sizeof(Work);
-    char* cw = static_cast<char*>(scratch(h, cbytes));
+    char* cw = static_cast<char*>(scratch_buf(h, cbytes));
     if (!cw) { handle_free(h); return COOP_E_OOM; }
     h->ctx = reinterpret_cast<Ctx*>(cw);
     h->work = reinterpret_cast<Work*>(cw + sizeof(Ctx));
@@ -373,6 +375,7 @@ hipError_t relaunch(coop_handle* h, bool joiner, uint32_t grid, hipStream_t s) {
         case COOP_KERNEL_SERVE: return coop::launch_serve(h->serve, h->coop, joiner, grid, h->block, h->lds, s);
         case COOP_KERNEL_OCTREE:
             return coop::launch_octree(h->octree, h->coop, joiner, grid, h->block, h->lds, s);
+        case COOP_KERNEL_CC: return coop::launch_cc(h->cc, h->coop, joiner, grid, h->block, h->lds, s);
     }
     return hipErrorInvalidValue;
 }
@@ -398,18 +401,18 @@ int fill_traversal(coop_handle* h, const coop_graph* g, const uint32_t* roots, u
     t->heavy_cap = (uint32_t)hs;
     t->heavy = nullptr;
     if (hs) {
-        t->heavy = static_cast<uint4*>(scratch(h, hs * sizeof(uint4)));
+        t->heavy = static_cast<uint4*>(scratch_buf(h, hs * sizeof(uint4)));
         if (!t->heavy) return COOP_E_OOM;
     }
     t->frontier[0] = t->frontier[1] = nullptr;
     if (queues) {
         for (int i = 0; i < 2; ++i) {
-            t->frontier[i] = static_cast<uint32_t*>(scratch(h, (size_t)g->n * 4 + 4));
+            t->frontier[i] = static_cast<uint32_t*>(scratch_buf(h, (size_t)g->n * 4 + 4));
             if (!t->frontier[i]) return COOP_E_OOM;
         }
     }
     const size_t slot_words = (size_t)h->grid * coop::kSlotWords;
-    t->slots = static_cast<uint32_t*>(scratch(h, slot_words * 4));
+    t->slots = static_cast<uint32_t*>(scratch_buf(h, slot_words * 4));
     if (!t->slots) return COOP_E_OOM;
     h->slots = t->slots;
     hipError_t e = coop::launch_fill_u32(t->slots, slot_words, 0u, h->stream);
@@ -507,6 +510,7 @@ int coop_init(int device, coop_rt** out) {
         rt->xcds = mx + 1;
         rt->ses = ms + 1;
     }
+
     if (e != hipSuccess) {
         int rc = hip_fail(rt, e);
         coop_shutdown(rt);
@@ -596,6 +600,17 @@ int coop_graph_wrap(coop_rt* rt, const uint32_t* d_row_ptr, const uint32_t* d_co
         g->deg[v] = rp[v + 1] - rp[v];
         g->max_deg = std::max(g->max_deg, g->deg[v]);
     }
+    {
+        // the bitmap of vertices without arcs is built here, so that no
+        // traversal launch has to allocate it
+        std::lock_guard<std::recursive_mutex> lk(rt->mu);
+        int rc = ensure_deg0(rt, g, rt->cotask_stream);
+        if (rc == COOP_OK && hipStreamSynchronize(rt->cotask_stream) != hipSuccess) rc = COOP_E_HIP;
+        if (rc != COOP_OK) {
+            delete g;
+            return rc;
+        }
+    }
     *out = g;
     return COOP_OK;
 }
@@ -632,14 +647,15 @@ int coop_bfs(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_t
         return rc;
     }
     a.words = g->words;
-    a.vis = static_cast<uint32_t*>(scratch(h, (size_t)a.words * 4));
-    for (int i = 0; i < 3; ++i) a.fb[i] = static_cast<uint32_t*>(scratch(h, (size_t)a.words * 4));
+    a.vis = static_cast<uint32_t*>(scratch_buf(h, (size_t)a.words * 4));
+    for (int i = 0; i < 3; ++i) a.fb[i] = static_cast<uint32_t*>(scratch_buf(h, (size_t)a.words * 4));
     a.deg0 = gm->deg0;
     a.level_out = d_level;
     a.direction_opt = (opts && (opts->flags & COOP_F_TOP_DOWN_ONLY)) ? 0u : 1u;
-    a.alpha = 14;
-    a.beta = 24;
+    a.alpha = (opts && opts->bu_alpha) ? opts->bu_alpha : 14u;
+    a.beta = (opts && opts->bu_beta) ? opts->bu_beta : 24u;
     a.total_arcs = g->arcs;
+    a.bu_prefetch = (opts && (opts->flags & (1u << 31))) ? 1u : 0u;
     if (!a.vis || !a.fb[0] || !a.fb[1] || !a.fb[2]) { handle_free(h); return COOP_E_OOM; }
     (void)hipEventRecord(h->ev_init, s);
     (void)hipEventRecord(h->ev_start, s);
@@ -664,8 +680,8 @@ int coop_sssp(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_
         return rc;
     }
     a.words = g->words;
-    for (int i = 0; i < 3; ++i) a.fb[i] = static_cast<uint32_t*>(scratch(h, (size_t)a.words * 4));
-    a.lowered = static_cast<uint32_t*>(scratch(h, (size_t)coop::kMaxXcds * 256));
+    for (int i = 0; i < 3; ++i) a.fb[i] = static_cast<uint32_t*>(scratch_buf(h, (size_t)a.words * 4));
+    a.lowered = static_cast<uint32_t*>(scratch_buf(h, (size_t)coop::kMaxXcds * 256));
     a.dist_out = d_dist;
     if (!a.fb[0] || !a.fb[1] || !a.fb[2] || !a.lowered) { handle_free(h); return COOP_E_OOM; }
     (void)hipEventRecord(h->ev_init, s);
@@ -689,7 +705,7 @@ static int color_or_mis(coop_rt* rt, const coop_graph* g, uint64_t seed, uint32_
     (void)dummy_root;
     if ((rc = fill_traversal(h, g, nullptr, 1, 0, opts, &a.t, false, true))) { handle_free(h); return rc; }
     a.prio_seed = seed;
-    a.pending = static_cast<uint32_t*>(scratch(h, (size_t)g->n * 4));
+    a.pending = static_cast<uint32_t*>(scratch_buf(h, (size_t)g->n * 4));
     a.colour_out = colour;
     a.in_set_out = in_set;
     a.mis = in_set ? 1u : 0u;
@@ -711,6 +727,33 @@ int coop_mis(coop_rt* rt, const coop_graph* g, uint64_t prio_seed, uint8_t* d_in
     return color_or_mis(rt, g, prio_seed, nullptr, d_in_set, opts, stream, out);
 }
 
+int coop_cc(coop_rt* rt, const coop_graph* g, uint32_t* d_label, const coop_launch_opts* opts,
+            coop_stream_t stream, coop_handle** out) {
+    if (!rt || !g || g->rt != rt || !d_label) return COOP_E_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(rt->mu);
+    reap(rt);
+    Sizing sz{};
+    int rc = size_launch(rt, opts, &sz);
+    if (rc) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    coop_handle* h = nullptr;
+    if ((rc = begin_launch(rt, opts, sz, COOP_KERNEL_CC, s, &h))) return rc;
+    coop::CcArgs& a = h->cc;
+    a.cfg = h->cfg;
+    a.ctx = h->ctx;
+    a.row_ptr = g->row_ptr;
+    a.col = g->col;
+    a.n = g->n;
+    a.label = d_label;
+    a.changed = static_cast<uint32_t*>(scratch_buf(h, 512));
+    if (!a.changed) { handle_free(h); return COOP_E_OOM; }
+    hipError_t e = coop::launch_fill_u32(a.changed, 128, 0u, s);
+    if (e != hipSuccess) { handle_free(h); return hip_fail(rt, e); }
+    (void)hipEventRecord(h->ev_init, s);
+    (void)hipEventRecord(h->ev_start, s);
+    return finish_launch(rt, h, relaunch(h, false, h->grid, s), out);
+}
+
 int coop_launch(coop_rt* rt, int kernel_id, const coop_params* p, const coop_launch_opts* opts,
                 coop_stream_t stream, coop_handle** out) {
     if (!rt || !p) return COOP_E_INVALID;
@@ -725,6 +768,8 @@ int coop_launch(coop_rt* rt, int kernel_id, const coop_params* p, const coop_lau
             return coop_color(rt, p->graph, p->prio_seed, static_cast<uint32_t*>(p->d_out), opts, stream, out);
         case COOP_KERNEL_MIS:
             return coop_mis(rt, p->graph, p->prio_seed, static_cast<uint8_t*>(p->d_out), opts, stream, out);
+        case COOP_KERNEL_CC:
+            return coop_cc(rt, p->graph, static_cast<uint32_t*>(p->d_out), opts, stream, out);
         case COOP_KERNEL_BARRIER: {
             if (p->barrier_iters == 0) return COOP_E_INVALID;
             std::lock_guard<std::recursive_mutex> lk(rt->mu);
@@ -752,9 +797,11 @@ static int batch_stats(coop_handle* h, coop_stats* stats) {
     coop_rt* rt = h->rt;
     const uint32_t count = h->batch.count;
     coop::BatchCtl ctl;
+    coop::TaskState task;
     std::vector<coop::TeamState> ts(count);
     std::vector<uint64_t> slots(h->bslot_words / 2);
     hipError_t e = hipMemcpy(&ctl, h->bctl, sizeof(ctl), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&task, &h->ctx->task, sizeof(task), hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(ts.data(), h->teams, (size_t)count * sizeof(coop::TeamState),
                                        hipMemcpyDeviceToHost);
     if (e == hipSuccess && !slots.empty())
@@ -786,11 +833,11 @@ static int batch_stats(coop_handle* h, coop_stats* stats) {
             hp += ts[i].bfs_work.x.heavy_phases;
         }
         stats->barriers = barriers;
-        stats->kills = ctl.kills;
-        stats->forks = ctl.forks;
-        stats->resizes = ctl.kills + ctl.forks;
-        stats->min_groups = ctl.min_active == 0xFFFFFFFFu ? ctl.max_active : ctl.min_active;
-        stats->max_groups = ctl.max_active;
+        stats->kills = task.kills;
+        stats->forks = task.forks;
+        stats->resizes = task.kills + task.forks;
+        stats->min_groups = task.min_active == 0xFFFFFFFFu ? task.max_active : task.min_active;
+        stats->max_groups = task.max_active;
         stats->final_groups = ctl.left;
         stats->grid = h->grid;
         stats->levels = levels;
@@ -840,7 +887,9 @@ int coop_wait(coop_handle* h, coop_stats* stats) {
     }
     if (h->kind == COOP_KERNEL_OCTREE) {
         coop::OctCtl ctl{};
+        coop::TaskState task{};
         if (e == hipSuccess) e = hipMemcpy(&ctl, h->octree.ctl, sizeof(ctl), hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(&task, &h->ctx->task, sizeof(task), hipMemcpyDeviceToHost);
         float ms = 0.f;
         if (e == hipSuccess) (void)hipEventElapsedTime(&ms, h->ev_start, h->ev_end);
         int rc = e == hipSuccess ? ctl.error : hip_fail(rt, e);
@@ -849,10 +898,10 @@ int coop_wait(coop_handle* h, coop_stats* stats) {
             std::memset(stats, 0, sizeof(*stats));
             stats->error = rc;
             stats->grid = h->grid;
-            stats->kills = ctl.kills;
-            stats->forks = ctl.forks;
-            stats->min_groups = ctl.min_active == 0xFFFFFFFFu ? ctl.max_active : ctl.min_active;
-            stats->max_groups = ctl.max_active;
+            stats->kills = task.kills;
+            stats->forks = task.forks;
+            stats->min_groups = task.min_active == 0xFFFFFFFFu ? task.max_active : task.min_active;
+            stats->max_groups = task.max_active;
             stats->levels = ctl.tasks;
             stats->rows = ctl.leaf_count;
             stats->arcs = ctl.steals;
@@ -1033,7 +1082,7 @@ int coop_batch_run(coop_rt* rt, const coop_batch_item* items, uint32_t count, co
     const size_t head = align_up((size_t)count * sizeof(coop::TeamState)) + align_up(sizeof(coop::BatchCtl)) +
                         align_up((size_t)count * sizeof(coop::BatchInst)) + align_up(((size_t)count + 1) * 4) +
                         align_up((size_t)count * 4) + align_up(slot_words * 4);
-    char* base = static_cast<char*>(scratch(h, head + bytes));
+    char* base = static_cast<char*>(scratch_buf(h, head + bytes));
     if (!base) { handle_free(h); return COOP_E_OOM; }
     char* p = base;
     auto take = [&](size_t b) { char* r = p; p += align_up(b); return r; };
@@ -1127,6 +1176,8 @@ int coop_batch_run(coop_rt* rt, const coop_batch_item* items, uint32_t count, co
     }
     coop::BatchArgs& a = h->batch;
     a.cfg = h->cfg;
+    a.cfg.keep = team_max;                  // the scheduler never takes a launch below its largest team
+    a.ctx = h->ctx;
     a.inst = d_inst;
     a.first = d_first;
     a.teams = h->teams;
@@ -1140,17 +1191,23 @@ int coop_batch_run(coop_rt* rt, const coop_batch_item* items, uint32_t count, co
 
 namespace {
 
+// The autotuner's cache: one schedule per device and batch shape (instance
+// count, vertex and arc sums, largest instance, operations, launch mode),
+// kept for the process and, through coop_tune_cache_save / _load, in a
+// text file across processes.
 struct TuneKey {
     std::string arch;
     uint32_t count;
     uint64_t sum_n, sum_arcs, max_work;
+    uint32_t ops, mode;
     bool operator<(const TuneKey& o) const {
-        return std::tie(arch, count, sum_n, sum_arcs, max_work) <
-               std::tie(o.arch, o.count, o.sum_n, o.sum_arcs, o.max_work);
+        return std::tie(arch, count, sum_n, sum_arcs, max_work, ops, mode) <
+               std::tie(o.arch, o.count, o.sum_n, o.sum_arcs, o.max_work, o.ops, o.mode);
     }
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, std::pair<coop_tune, double>> g_tune_cache;
+constexpr const char* kTuneHeader = "coop-tune-cache v1";
 
 }  // namespace
 
@@ -1162,12 +1219,15 @@ int coop_batch_autotune(coop_rt* rt, const coop_batch_item* items, uint32_t coun
         int rc = check_batch_item(rt, items[i]);
         if (rc) return rc;
     }
-    TuneKey key{rt->props.gcnArchName, count, 0, 0, 0};
+    TuneKey key{rt->props.gcnArchName, count, 0, 0, 0, 0, opts ? opts->mode : (uint32_t)COOP_MODE_PLAIN};
     for (uint32_t i = 0; i < count; ++i) {
         key.sum_n += items[i].graph->n;
         key.sum_arcs += items[i].graph->arcs;
         key.max_work = std::max<uint64_t>(key.max_work, items[i].graph->n + items[i].graph->arcs);
+        key.ops |= items[i].ops;
     }
+    // names the device model only (the part before the feature list)
+    key.arch = key.arch.substr(0, key.arch.find(':'));
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
@@ -1203,35 +1263,63 @@ int coop_batch_autotune(coop_rt* rt, const coop_batch_item* items, uint32_t coun
     double cur_ms = time_it(cur);
     if (err) return err;
     const double def_ms = cur_ms;
-    // coordinate search: group size, team work, BFS direction rule, team cap
-    const uint32_t sizes[] = {256, 512, 1024};
-    const uint64_t team_arcs[] = {1ull << 16, 1ull << 18, 1ull << 19, 1ull << 20, 1ull << 21, 1ull << 22,
-                                  1ull << 24};
-    for (int pass = 0; pass < 2; ++pass) {
-        for (uint32_t gs : sizes) {
+    // coordinate search, two passes: group size, workgroup count (as a share
+    // of the resident workgroups), team work, team cap, BFS direction rule,
+    // heavy-vertex threshold and strip; a candidate must beat the current
+    // schedule by 2% (timing noise)
+    const uint32_t cus = (uint32_t)std::max(1, rt->props.multiProcessorCount);
+    auto try_it = [&](const coop_tune& c) {
+        const double ms = time_it(c);
+        if (ms < cur_ms * 0.98) {
+            cur = c;
+            cur_ms = ms;
+        }
+    };
+    for (int pass = 0; pass < 2 && !err; ++pass) {
+        for (uint32_t gs : {256u, 512u, 1024u}) {
             if (gs == cur.group_size) continue;
             coop_tune c = cur;
             c.group_size = gs;
-            const double ms = time_it(c);
-            if (err) return err;
-            if (ms < cur_ms * 0.98) { cur = c; cur_ms = ms; }
+            try_it(c);
         }
-        for (uint64_t ta : team_arcs) {
+        for (uint32_t per_cu_x4 : {2u, 3u, 4u, 8u}) {          // 0.5, 0.75, 1 and 2 workgroups per CU
+            coop_tune c = cur;
+            c.num_groups = std::min<uint32_t>(coop::kMaxGroups, cus * per_cu_x4 / 4);
+            if (c.num_groups == cur.num_groups) continue;
+            try_it(c);
+        }
+        for (uint64_t ta : {1ull << 16, 1ull << 18, 1ull << 19, 1ull << 20, 1ull << 21, 1ull << 22, 1ull << 24}) {
             if (ta == cur.team_arcs) continue;
             coop_tune c = cur;
             c.team_arcs = ta;
-            const double ms = time_it(c);
-            if (err) return err;
-            if (ms < cur_ms * 0.98) { cur = c; cur_ms = ms; }
+            try_it(c);
+        }
+        for (uint32_t div : {16u, 8u, 4u, 2u}) {                 // team cap as a share of N (0 = N / 8)
+            coop_tune c = cur;
+            const uint32_t N = c.num_groups ? c.num_groups : std::min<uint32_t>(coop::kMaxGroups, cus);
+            c.team_max = std::max<uint32_t>(1, N / div);
+            if (c.team_max == cur.team_max) continue;
+            try_it(c);
         }
         {
             coop_tune c = cur;
             c.direction_opt = cur.direction_opt ? 0u : 1u;
-            const double ms = time_it(c);
-            if (err) return err;
-            if (ms < cur_ms * 0.98) { cur = c; cur_ms = ms; }
+            try_it(c);
+        }
+        for (uint32_t th : {128u, 512u, 2048u}) {
+            if (th == (cur.heavy_threshold ? cur.heavy_threshold : kDefaultHeavy)) continue;
+            coop_tune c = cur;
+            c.heavy_threshold = th;
+            try_it(c);
+        }
+        for (uint32_t st : {256u, 512u, 1024u}) {
+            if (st == (cur.strip ? cur.strip : kDefaultStrip)) continue;
+            coop_tune c = cur;
+            c.strip = st;
+            try_it(c);
         }
     }
+    if (err) return err;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache[key] = std::make_pair(cur, cur_ms);
@@ -1240,6 +1328,67 @@ int coop_batch_autotune(coop_rt* rt, const coop_batch_item* items, uint32_t coun
     if (best_ms) *best_ms = cur_ms;
     if (default_ms) *default_ms = def_ms;
     return COOP_OK;
+}
+
+int coop_tune_cache_save(const char* path, uint32_t* entries) {
+    if (!path) return COOP_E_INVALID;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    FILE* f = std::fopen(path, "w");
+    if (!f) return COOP_E_INVALID;
+    std::fprintf(f, "%s\n", kTuneHeader);
+    for (const auto& kv : g_tune_cache) {
+        const TuneKey& k = kv.first;
+        const coop_tune& t = kv.second.first;
+        std::fprintf(f, "%s %u %llu %llu %llu %u %u  %u %u %llu %u %u %u %u  %.6f\n", k.arch.c_str(), k.count,
+                     (unsigned long long)k.sum_n, (unsigned long long)k.sum_arcs, (unsigned long long)k.max_work,
+                     k.ops, k.mode, t.group_size, t.num_groups, (unsigned long long)t.team_arcs, t.team_max,
+                     t.direction_opt, t.heavy_threshold, t.strip, kv.second.second);
+    }
+    const bool ok = std::fclose(f) == 0;
+    if (entries) *entries = (uint32_t)g_tune_cache.size();
+    return ok ? COOP_OK : COOP_E_INVALID;
+}
+
+int coop_tune_cache_load(const char* path, uint32_t* entries) {
+    if (!path) return COOP_E_INVALID;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return COOP_E_INVALID;
+    char line[512];
+    std::vector<std::pair<TuneKey, std::pair<coop_tune, double>>> got;
+    bool ok = std::fgets(line, sizeof(line), f) && std::strncmp(line, kTuneHeader, std::strlen(kTuneHeader)) == 0;
+    while (ok && std::fgets(line, sizeof(line), f)) {
+        char arch[128];
+        unsigned count, ops, mode, gs, ng, tm, dir, th, st;
+        unsigned long long sn, sa, mw, ta;
+        double ms;
+        const int k = std::sscanf(line, "%127s %u %llu %llu %llu %u %u %u %u %llu %u %u %u %u %lf", arch, &count, &sn,
+                                  &sa, &mw, &ops, &mode, &gs, &ng, &ta, &tm, &dir, &th, &st, &ms);
+        if (k != 15 || gs == 0 || gs % 64 || gs > coop::kMaxThreads || ng > coop::kMaxGroups || dir > 1) {
+            ok = false;
+            break;
+        }
+        coop_tune t;
+        coop_tune_default(&t);
+        t.group_size = gs;
+        t.num_groups = ng;
+        t.team_arcs = ta;
+        t.team_max = tm;
+        t.direction_opt = dir;
+        t.heavy_threshold = th;
+        t.strip = st;
+        got.push_back({TuneKey{arch, count, sn, sa, mw, ops, mode}, {t, ms}});
+    }
+    std::fclose(f);
+    if (!ok) return COOP_E_INVALID;          // nothing of a malformed file is taken
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto& e : got) g_tune_cache[e.first] = e.second;
+    if (entries) *entries = (uint32_t)g_tune_cache.size();
+    return COOP_OK;
+}
+
+void coop_tune_cache_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache.clear();
 }
 
 // ----------------------------------------------------------------- serving
@@ -1531,6 +1680,11 @@ int coop_server_create(coop_rt* rt, const coop_graph* const* graphs, uint32_t ng
     }
     coop::ServeArgs& a = h->serve;
     a.cfg = h->cfg;
+    a.cfg.keep = team_max;                           // never below the largest team
+    if (a.cfg.host) a.cfg.mode |= coop::kModeRelayTarget;   // the relay copies the host target
+    a.ctx = h->ctx;
+    a.slots = (uint32_t)slots;
+    a.ndesc = (uint32_t)(slots * ngraphs);
     a.desc = d_desc;
     a.teams = teams;
     a.ctl = sv->ctl;
@@ -1642,10 +1796,13 @@ int coop_server_stats(coop_server* sv, coop_serve_stats* out) {
     out->slots = sv->slots;
     out->in_flight = sv->slots - (uint32_t)sv->free_slots.size();
     out->queued = (uint32_t)sv->pending.size();
-    out->kills = ctl.kills;
-    out->forks = ctl.forks;
-    out->min_groups = ctl.min_active == 0xFFFFFFFFu ? ctl.max_active : ctl.min_active;
-    out->max_groups = ctl.max_active;
+    coop::TaskState task{};
+    (void)hipMemcpyAsync(&task, &sv->h->ctx->task, sizeof(task), hipMemcpyDeviceToHost, sv->rt->cotask_stream);
+    (void)hipStreamSynchronize(sv->rt->cotask_stream);
+    out->kills = task.kills;
+    out->forks = task.forks;
+    out->min_groups = task.min_active == 0xFFFFFFFFu ? task.max_active : task.min_active;
+    out->max_groups = task.max_active;
     out->error = sv->error ? sv->error : ctl.error;
     return COOP_OK;
 }
@@ -1862,13 +2019,13 @@ int coop_octree(coop_rt* rt, const uint32_t* d_x, const uint32_t* d_y, const uin
     a.node_cap = (uint32_t)std::min<uint64_t>(nodes, 0xFFFFFFF0ull);
     a.leaf_cap = leaf_cap;
     a.buf[0] = reinterpret_cast<uint4*>(d_out);
-    a.buf[1] = static_cast<uint4*>(scratch(h, (size_t)std::max<uint32_t>(n, 1) * 16));
-    a.nodes = static_cast<uint32_t*>(scratch(h, (size_t)a.node_cap * 32));
+    a.buf[1] = static_cast<uint4*>(scratch_buf(h, (size_t)std::max<uint32_t>(n, 1) * 16));
+    a.nodes = static_cast<uint32_t*>(scratch_buf(h, (size_t)a.node_cap * 32));
     a.leaves = d_leaves;
-    a.ctl = static_cast<coop::OctCtl*>(scratch(h, sizeof(coop::OctCtl)));
-    a.q = static_cast<coop::OctQueue*>(scratch(h, (size_t)h->grid * sizeof(coop::OctQueue)));
-    a.slot_owner = static_cast<uint32_t*>(scratch(h, (size_t)h->grid * 4));
-    if (!a.buf[1] || !a.nodes || !a.ctl || !a.q || !a.slot_owner) { handle_free(h); return COOP_E_OOM; }
+    a.ctl = static_cast<coop::OctCtl*>(scratch_buf(h, sizeof(coop::OctCtl)));
+    a.q = static_cast<coop::OctQueue*>(scratch_buf(h, (size_t)h->grid * sizeof(coop::OctQueue)));
+    a.ctx = h->ctx;
+    if (!a.buf[1] || !a.nodes || !a.ctl || !a.q) { handle_free(h); return COOP_E_OOM; }
     hipError_t e = coop::launch_octree_init(a, d_x, d_y, d_z, s);
     if (e != hipSuccess) { handle_free(h); return hip_fail(rt, e); }
     (void)hipEventRecord(h->ev_init, s);
@@ -1983,6 +2140,9 @@ int coop_share_stop(coop_rt* rt, coop_share_stats* out) {
 int coop_barrier_bench(coop_rt* rt, const coop_launch_opts* opts, uint32_t iters, coop_stream_t stream,
                        double* ns_per_barrier, coop_stats* stats) {
     if (!rt || iters == 0) return COOP_E_INVALID;
+    // a plain launch of nothing but barriers once waited out its watchdog
+    // and no cause has been shown; it is refused until one is
+    if (!opts || opts->mode == COOP_MODE_PLAIN) return COOP_E_INVALID;
     coop_params p{};
     p.barrier_iters = iters;
     coop_handle* h = nullptr;

@@ -238,86 +238,56 @@ __device__ void split_task(const OctreeArgs& a, OctLds& L, uint32_t slot) {
 
 // ------------------------------------------------------------ the kernel
 
+// The task pattern of the programming model (section 3.2, "Adapting Work
+// Stealing"): offer_kill and request_fork at the top of the main loop, the
+// queue id (the slot) taken when the workgroup becomes active, not
+// transmitted.
 template <bool Coop>
 __device__ void octree_body(const OctreeArgs& a, bool joiner) {
     __shared__ OctLds L;
+    __shared__ BarrierLds bar;
     OctCtl* ctl = a.ctl;
     const uint32_t N = a.cfg.N;
-    const LeaveCounters lc{&ctl->active, ctl->active_x, &ctl->kills, &ctl->min_active};
-    uint32_t slot = kNone, x = 0;
-    if (threadIdx.x == 0) {
-        // claim a slot (its queue comes with it)
-        const uint32_t s0 = joiner ? (blockIdx.x * 2654435761u) % N : blockIdx.x % N;
-        for (uint32_t k = 0; k < N && slot == kNone; ++k) {
-            const uint32_t s = (s0 + k) % N;
-            uint32_t expected = 0;
-            if (__hip_atomic_compare_exchange_strong(&a.slot_owner[s], &expected, 1u, __ATOMIC_ACQUIRE,
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                slot = s;
-        }
-        L.leave = slot == kNone ? 1u : 0u;
-        if (slot != kNone) {
-            x = engine_id(a.cfg.ses);
-            const uint32_t act = add_relaxed(&ctl->active, 1u) + 1;
-            add_relaxed(&ctl->active_x[x % kMaxEngines], 1u);
-            atomicMax(&ctl->max_active, act);
-            if (joiner) add_relaxed(&ctl->forks, 1u);
-        }
-        L.task = slot;
-    }
-    __syncthreads();
-    if (L.leave) return;
-    slot = L.task;
+    Group g(a.ctx, a.cfg, bar);
+    if (!coop_task_start<Coop>(g, joiner)) return;
+    const uint32_t slot = coop_get_group_id(g);
     uint32_t rng = (blockIdx.x + 1) * 0x9E3779B9u ^ (slot << 16);
-    uint32_t polls = 0;
+    uint64_t idle_since = now_ticks();          // thread 0: since it last had a task
     for (;;) {
+        if (threadIdx.x == 0) L.leave = (ld_relaxed_i(&ctl->error) || ld_relaxed(&ctl->outstanding) == 0) ? 2u : 0u;
+        __syncthreads();
+        if (L.leave) {
+            // every task is done (or one failed): joiners still waiting go too
+            coop_task_leave(g);
+            coop_task_finish(g);
+            return;
+        }
+        // offer_kill before taking a task: a workgroup may leave with tasks
+        // queued, the others steal them
+        if (!coop_offer_kill<Coop>(g)) return;
+        coop_request_fork<Coop>(g);
         if (threadIdx.x == 0) {
-            uint32_t task = kNone, leave = 0;
-            uint64_t t0 = now_ticks();
-            for (;;) {
-                if (ld_relaxed_i(&ctl->error) || ld_relaxed(&ctl->outstanding) == 0) {
-                    leave = 2;
-                    break;
-                }
-                // offer_kill before taking a task
-                if (Coop && a.cfg.host && (polls++ & 7) == 0 &&
-                    leave_for_target(lc, ld_system(&a.cfg.host->target), 1u, a.cfg.engines, x)) {
-                    leave = 1;
-                    break;
-                }
-                task = q_take(&a.q[slot], true, a.cfg, ctl);
-                if (task != kNone) break;
-                for (int attempt = 0; attempt < 8 && task == kNone; ++attempt) {
-                    rng ^= rng << 13;
-                    rng ^= rng >> 17;
-                    rng ^= rng << 5;
-                    const uint32_t v = rng % N;
-                    if (v != slot) task = q_take(&a.q[v], false, a.cfg, ctl);
-                }
-                if (task != kNone) {
-                    add_relaxed(&ctl->steals, 1u);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-                if (now_ticks() - t0 > a.cfg.watchdog_ticks) {
-                    atomicCAS(&ctl->error, 0, kErrTimeout);
-                    leave = 2;
-                    break;
+            uint32_t task = q_take(&a.q[slot], true, a.cfg, ctl);
+            for (int attempt = 0; attempt < 8 && task == kNone; ++attempt) {
+                rng ^= rng << 13;
+                rng ^= rng >> 17;
+                rng ^= rng << 5;
+                const uint32_t v = rng % N;
+                if (v != slot) {
+                    task = q_take(&a.q[v], false, a.cfg, ctl);
+                    if (task != kNone) add_relaxed(&ctl->steals, 1u);
                 }
             }
-            if (leave) {
-                // the slot (and whatever is left in its queue) is free again
-                __hip_atomic_store(&a.slot_owner[slot], 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                if (leave == 2) {
-                    add_relaxed(&ctl->active, 0xFFFFFFFFu);
-                    add_relaxed(&ctl->active_x[x % kMaxEngines], 0xFFFFFFFFu);
-                }
+            if (task != kNone) {
+                idle_since = now_ticks();
+            } else {
+                __builtin_amdgcn_s_sleep(2);
+                if (now_ticks() - idle_since > a.cfg.watchdog_ticks) atomicCAS(&ctl->error, 0, kErrTimeout);
             }
             L.task = task;
-            L.leave = leave;
         }
         __syncthreads();
-        if (L.leave) return;
+        if (L.task == kNone) continue;
         split_task(a, L, slot);
         __syncthreads();
     }
@@ -338,12 +308,10 @@ __global__ void octree_init_kernel(OctreeArgs a, const uint32_t* x, const uint32
         a.q[s].lock = 0;
         a.q[s].head = 0;
         a.q[s].tail = 0;
-        a.slot_owner[s] = 0;
     }
     if (tid < sizeof(OctCtl) / 4) reinterpret_cast<uint32_t*>(a.ctl)[tid] = 0;
     __syncthreads();
     if (tid == 0) {
-        a.ctl->min_active = 0xFFFFFFFFu;
         a.nodes[0] = 0;
         a.nodes[1] = a.n;
         a.nodes[2] = 0;

@@ -19,7 +19,15 @@
 //    query a team's master may also give up its top members at a barrier
 //    (the resizing barrier, per team), so a co-task does not have to wait
 //    for long queries to end. Joiner grids launched later enter between
-//    queries (request_fork).
+//    queries (request_fork). These are the task-pattern calls of
+//    coop_device.hpp on the launch context.
+//  * One idle workgroup at a time, the relay, reads the host's words (ticket
+//    end, stop, heartbeat, scheduler target) over PCIe and republishes them
+//    in device memory; every other idle workgroup polls those copies, so
+//    PCIe sees one reader however many workgroups are idle.
+//  * Every value read from host memory is checked before it is used as an
+//    index or a pointer (slot, descriptor, kind, rank, team, output); a bad
+//    one stops the server with COOP_E_INTERNAL instead of being followed.
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -48,9 +56,6 @@ __device__ void serve_barrier(const ServeArgs& a, CtxCore* c, const Cfg tcfg, Me
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        // member 0 reads the host target before it arrives (off the
-        // master's path); the master finds it in the slot's lines
-        if (Coop && a.cfg.host && m.id == 0) st_relaxed(&c->T_seen, ld_system(&a.cfg.host->target));
         const uint32_t old = __hip_atomic_fetch_add(&c->arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         b.is_master = (old + 1 == m.M) ? 1u : 0u;
         if (b.is_master) __hip_atomic_store(&c->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -65,12 +70,11 @@ __device__ void serve_barrier(const ServeArgs& a, CtxCore* c, const Cfg tcfg, Me
                 // give up top members while the launch holds more than the
                 // target and their shader engine more than its share
                 // (member 0 stays)
-                const uint32_t T = ld_relaxed(&c->T_seen);
+                const uint32_t T = ld_relaxed(&a.ctx->T_seen);       // the relayed host target
                 const uint32_t engines = a.cfg.engines;
-                const LeaveCounters lc{&a.ctl->active, a.ctl->active_x, &a.ctl->kills, &a.ctl->min_active};
                 while (Mn > 1) {
                     const uint32_t x = ld_relaxed(&slots[(size_t)(Mn - 1) * kSlotWords + kSlotEngine]);
-                    if (!leave_for_target(lc, T, a.team_max, engines, x)) break;
+                    if (!task_leave(&a.ctx->task, T, a.team_max, engines, x)) break;
                     --Mn;
                 }
             }
@@ -92,9 +96,15 @@ __device__ void serve_barrier(const ServeArgs& a, CtxCore* c, const Cfg tcfg, Me
         n.epoch = rel_epoch(r);
         n.M = rel_M(r);
         n.flags = rel_flags(r);
-        n.alive = ((n.flags & kFlagAbort) || n.id >= n.M) ? 0u : 1u;
+        // a member that sees the epoch move by more than one was let go at
+        // the epoch it missed (the next release needs every member), and
+        // the slot may already be serving a later query: that query's
+        // release is not this member's
+        const bool gap = n.epoch != m.epoch + 1;
+        const bool out = gap || n.id >= n.M;
+        n.alive = ((n.flags & kFlagAbort) || out) ? 0u : 1u;
         b.member = n;
-        b.killed = n.id >= n.M ? 1u : 0u;
+        b.killed = out ? 1u : 0u;
     }
     __syncthreads();
     m = b.member;
@@ -181,86 +191,131 @@ __device__ void query_leave(const ServeArgs& a, CtxCore* c, uint32_t slot, uint3
     }
 }
 
+// Thread 0 of an idle workgroup: the next ticket, or why to leave (1 error,
+// 2 taken by the scheduler, 3 stop). The relay reads the host's words and
+// republishes them; the others read the copies.
+template <bool Coop>
+__device__ uint32_t serve_next_ticket(const ServeArgs& a, Group& g, uint32_t& k, uint32_t& hb_seen,
+                                      uint64_t& hb_t, uint32_t& beat_seen, uint64_t& beat_t) {
+    ServeCtl* ctl = a.ctl;
+    bool relay = false;
+    uint32_t idle = 0;
+    for (uint32_t it = 0;; ++it) {
+        if (ld_relaxed_i(&ctl->error)) break;
+        if (!relay && ld_relaxed(&ctl->relay) == 0) {
+            uint32_t z = 0;
+            relay = __hip_atomic_compare_exchange_strong(&ctl->relay, &z, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const uint64_t now = now_ticks();
+        if (relay) {
+            st_relaxed(&ctl->end, ld_system(&a.host->ticket_end));
+            st_relaxed(&ctl->stop, ld_system(&a.host->stop));
+            if (Coop && a.cfg.host) st_relaxed(&a.ctx->T_seen, ld_system(&a.cfg.host->target));
+            add_relaxed(&ctl->beat, 1u);
+            if ((it & 63) == 63) {
+                // the host's poller advances its heartbeat every millisecond:
+                // a server whose process has gone stops itself
+                const uint32_t hb = ld_system(&a.host->heartbeat);
+                if (hb != hb_seen) {
+                    hb_seen = hb;
+                    hb_t = now;
+                } else if (now - hb_t > a.cfg.watchdog_ticks) {
+                    atomicCAS(&ctl->error, 0, kErrTimeout);
+                    break;
+                }
+            }
+        } else if ((it & 63) == 63) {
+            // the relay itself must be alive: its beat moves at every poll
+            const uint32_t b = ld_relaxed(&ctl->beat);
+            if (b != beat_seen) {
+                beat_seen = b;
+                beat_t = now;
+            } else if (ld_relaxed(&ctl->relay) != 0 && now - beat_t > a.cfg.watchdog_ticks) {
+                atomicCAS(&ctl->error, 0, kErrTimeout);
+                break;
+            }
+        }
+        uint32_t t = ld_relaxed(&ctl->ticket);
+        const uint32_t end = ld_relaxed(&ctl->end);
+        if (t < end) {
+            if (__hip_atomic_compare_exchange_strong(&ctl->ticket, &t, t + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)) {
+                k = t;
+                if (relay) st_relaxed(&ctl->relay, 0u);      // hand the role to another idle workgroup
+                return 0;
+            }
+            continue;
+        }
+        if (ld_relaxed(&ctl->stop)) {
+            if (relay) st_relaxed(&ctl->relay, 0u);
+            return 3;
+        }
+        // idle: back off to about 10 us between polls (the relay polls faster)
+        idle = idle < 16 ? idle + 1 : 16;
+        for (uint32_t z = 0; z < (relay ? 1u : idle); ++z) __builtin_amdgcn_s_sleep(16);
+    }
+    if (relay) st_relaxed(&ctl->relay, 0u);
+    return 1;
+}
+
 template <bool Coop>
 __device__ void serve_body(const ServeArgs& a, bool joiner) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     BlockLds& sh = *reinterpret_cast<BlockLds*>(lds_raw);
     ServeCtl* ctl = a.ctl;
+    // the launch-wide membership (task pattern) keeps its own LDS: sh.bar
+    // holds the team barrier of the query being served
+    __shared__ BarrierLds gbar;
+    Group g(a.ctx, a.cfg, gbar);
     __shared__ uint32_t q_desc, q_kind, q_rank, q_team, q_slot, q_leave;
     __shared__ uint64_t q_out, q_seq;
     if (threadIdx.x == 0) {
         for (uint32_t i = 0; i < num_waves(); ++i) sh.wave[i].out_n = 0;
         for (int i = 0; i < 8; ++i) sh.acc[i] = 0;
-        sh.bar.killed = 0;
-        const uint32_t act = add_relaxed(&ctl->active, 1u) + 1;
-        add_relaxed(&ctl->active_x[engine_id(a.cfg.ses) % kMaxEngines], 1u);
-        atomicMax(&ctl->max_active, act);
-        if (joiner) add_relaxed(&ctl->forks, 1u);
     }
-    // the host's heartbeat as last seen, and when it last moved: a server
-    // whose host has stopped advancing it for the watchdog time leaves, so
-    // the launch cannot outlive its process
-    uint32_t hb_seen = 0;
-    uint64_t hb_t = now_ticks();
+    if (!coop_task_start<Coop>(g, joiner)) return;
+    uint32_t hb_seen = 0, beat_seen = 0;
+    uint64_t hb_t = now_ticks(), beat_t = hb_t;
     for (;;) {
+        // between queries: offer this workgroup to the scheduler, let
+        // waiting joiners in
+        if (!coop_offer_kill<Coop>(g)) return;
+        coop_request_fork<Coop>(g);
         if (threadIdx.x == 0) {
-            uint32_t leave = 0, k = 0, idle = 0;
-            for (uint32_t it = 0;; ++it) {
-                if (ld_relaxed_i(&ctl->error)) { leave = 1; break; }
-                if ((it & 63) == 63) {
-                    const uint32_t hb = ld_system(&a.host->heartbeat);
-                    const uint64_t now = now_ticks();
-                    if (hb != hb_seen) {
-                        hb_seen = hb;
-                        hb_t = now;
-                    } else if (now - hb_t > a.cfg.watchdog_ticks) {
-                        atomicCAS(&ctl->error, 0, kErrTimeout);
-                        leave = 1;
-                        break;
-                    }
-                }
-                if (Coop && a.cfg.host && (it & 7) == 0 &&
-                    leave_for_target(LeaveCounters{&ctl->active, ctl->active_x, &ctl->kills, &ctl->min_active},
-                                     ld_system(&a.cfg.host->target), a.team_max, a.cfg.engines, engine_id(a.cfg.ses))) {
-                    leave = 2;
-                    break;
-                }
-                uint32_t t = ld_relaxed(&ctl->ticket);
-                const uint32_t end = ld_system(&a.host->ticket_end);
-                if (t < end) {
-                    if (__hip_atomic_compare_exchange_strong(&ctl->ticket, &t, t + 1, __ATOMIC_RELAXED,
-                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                        k = t;
-                        break;
-                    }
-                    continue;
-                }
-                if (ld_system(&a.host->stop)) { leave = 3; break; }
-                // idle: back off to about 10 us between polls of host memory
-                idle = idle < 16 ? idle + 1 : 16;
-                for (uint32_t z = 0; z < idle; ++z) __builtin_amdgcn_s_sleep(16);
-            }
+            uint32_t k = 0;
+            uint32_t leave = serve_next_ticket<Coop>(a, g, k, hb_seen, hb_t, beat_seen, beat_t);
             if (!leave) {
                 fence_acquire_system();
+                // every value from host memory is checked before it is used
                 const uint32_t slot = ld_system(&a.owner[k % a.owner_cap]);
-                const ServeReq* q = &a.req[slot];
-                q_desc = ld_system(&q->desc);
-                q_kind = ld_system(&q->kind);
-                q_team = ld_system(&q->team);
-                q_rank = k - ld_system(&q->first);
-                q_out = ld_system64(&q->out);
-                q_seq = ld_system64(&q->seq);
-                q_slot = slot;
+                bool ok = slot < a.slots;
+                if (ok) {
+                    const ServeReq* q = &a.req[slot];
+                    q_desc = ld_system(&q->desc);
+                    q_kind = ld_system(&q->kind);
+                    q_team = ld_system(&q->team);
+                    const uint32_t first = ld_system(&q->first);
+                    q_rank = k - first;
+                    q_out = ld_system64(&q->out);
+                    q_seq = ld_system64(&q->seq);
+                    q_slot = slot;
+                    ok = q_desc < a.ndesc && (q_kind == kQueryBfs || q_kind == kQuerySssp) && q_team >= 1 &&
+                         q_team <= a.team_max && (int32_t)(k - first) >= 0 && q_rank < q_team && q_out != 0;
+                }
+                if (!ok) {
+                    atomicCAS(&ctl->error, 0, kErrInternal);
+                    leave = 1;
+                }
             }
-            if (leave == 1 || leave == 3) {
-                add_relaxed(&ctl->active, 0xFFFFFFFFu);
-                add_relaxed(&ctl->active_x[engine_id(a.cfg.ses) % kMaxEngines], 0xFFFFFFFFu);
-                add_relaxed(&ctl->left, 1u);
-            }
+            if (leave) add_relaxed(&ctl->left, 1u);
             q_leave = leave;
         }
         __syncthreads();
-        if (q_leave) return;
+        if (q_leave) {
+            coop_task_leave(g);
+            return;
+        }
         const uint32_t di = __builtin_amdgcn_readfirstlane(q_desc);
         const uint32_t kind = __builtin_amdgcn_readfirstlane(q_kind);
         const uint32_t rank = __builtin_amdgcn_readfirstlane(q_rank);
@@ -281,13 +336,19 @@ __device__ void serve_body(const ServeArgs& a, bool joiner) {
             stay = serve_sssp<Coop>(a, D.sssp, sh, rank, team, roots, reinterpret_cast<int32_t*>(out));
         }
         if (stay == 0) {
-            // released by the team's master (already taken off the active
-            // count) or the slot aborted
-            if (threadIdx.x == 0 && !sh.bar.killed) {
-                atomicCAS(&ctl->error, 0, ld_relaxed_i(&c->error) ? ld_relaxed_i(&c->error) : kErrInternal);
-                add_relaxed(&ctl->active, 0xFFFFFFFFu);
-                add_relaxed(&ctl->active_x[engine_id(a.cfg.ses) % kMaxEngines], 0xFFFFFFFFu);
+            // let go by the team's master (already taken off the active
+            // count, its slot with it) or the query failed
+            if (threadIdx.x == 0) {
+                if (!sh.bar.killed) {
+                    atomicCAS(&ctl->error, 0, ld_relaxed_i(&c->error) ? ld_relaxed_i(&c->error) : kErrInternal);
+                } else {
+                    __hip_atomic_store(&a.ctx->task.slot_owner[coop_get_group_id(g)], 0u, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    g.bar.member.alive = 0;
+                }
             }
+            __syncthreads();
+            coop_task_leave(g);
             return;
         }
         query_leave(a, c, slot, stay, seq);
@@ -311,7 +372,6 @@ __global__ void serve_init_kernel(TeamState* teams, uint32_t slots, ServeCtl* ct
         uint32_t* w = reinterpret_cast<uint32_t*>(ctl);
         for (uint32_t i = threadIdx.x; i < sizeof(ServeCtl) / 4; i += blockDim.x) w[i] = 0;
         __syncthreads();
-        if (threadIdx.x == 0) ctl->min_active = 0xFFFFFFFFu;
     }
 }
 

@@ -414,10 +414,11 @@ struct BfsTopDown {
 // plain stores (no other wave owns them).
 constexpr uint32_t kLaneRounds = 8;
 
+// (`word0`: the block's first bitmap word; fw holds the block's found bits)
 __device__ __forceinline__ void bu_mark(const BfsArgs& p, uint32_t* fw, uint32_t* level, uint32_t v,
-                                        uint32_t next_level, uint32_t block, uint32_t deg, Stats& st) {
+                                        uint32_t next_level, uint32_t word0, uint32_t deg, Stats& st) {
     __builtin_nontemporal_store(next_level, &level[v]);
-    atomicOr(&fw[(v >> 5) - block * 32u], 1u << (v & 31));
+    atomicOr(&fw[(v >> 5) - word0], 1u << (v & 31));
     st.found += 1;
     st.mf += deg;
 }
@@ -425,7 +426,7 @@ __device__ __forceinline__ void bu_mark(const BfsArgs& p, uint32_t* fw, uint32_t
 // Scan the deferred long lists with the whole wave, one candidate at a time,
 // 256 arcs per step, from where the lane left off (kLaneRounds x 4 arcs in).
 __device__ void bu_scan_long(const BfsArgs& p, WaveLds& wl, const uint32_t* cur, uint32_t* fw, uint32_t* level,
-                             uint32_t next_level, uint32_t block, uint32_t nlong, Stats& st) {
+                             uint32_t next_level, uint32_t word0, uint32_t nlong, Stats& st) {
     const uint32_t l = lane_id();
     for (uint32_t i = 0; i < nlong; ++i) {
         const uint32_t vv = wl.lng[i];
@@ -445,7 +446,7 @@ __device__ void bu_scan_long(const BfsArgs& p, WaveLds& wl, const uint32_t* cur,
             found = __ballot(h) != 0;
             st.arcs += l == 0 ? (a1 - kk < 4 * kWave ? a1 - kk : 4 * kWave) : 0u;
         }
-        if (found && l == 0) bu_mark(p, fw, level, vv, next_level, block, a1 - a0, st);
+        if (found && l == 0) bu_mark(p, fw, level, vv, next_level, word0, a1 - a0, st);
     }
     __builtin_amdgcn_wave_barrier();
 }
@@ -520,7 +521,7 @@ __device__ void bfs_bottom_up(const BfsArgs& p, WaveLds& wl, const uint32_t* cur
                 k[c] += got;
                 rounds[c] += 1;
                 if (hit) {
-                    bu_mark(p, fw, level, v[c], next_level, b, e[c] - s0[c], st);
+                    bu_mark(p, fw, level, v[c], next_level, b * kBlockWords, e[c] - s0[c], st);
                     act[c] = false;
                 } else if (k[c] >= e[c]) {
                     act[c] = false;                  // no parent in this frontier
@@ -537,12 +538,132 @@ __device__ void bfs_bottom_up(const BfsArgs& p, WaveLds& wl, const uint32_t* cur
             }
             if (nlong) {                             // at most 2 x 64 deferrals: the list's capacity
                 __builtin_amdgcn_wave_barrier();
-                bu_scan_long(p, wl, cur, fw, level, next_level, b, nlong, st);
+                bu_scan_long(p, wl, cur, fw, level, next_level, b * kBlockWords, nlong, st);
                 nlong = 0;
             }
         }
         __builtin_amdgcn_wave_barrier();
         if (l < 32) {
+            const uint32_t f = fw[l];
+            if (f) {
+                p.vis[wi] = vw | f;
+                nxt[wi] = f;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Bottom-up level with the block's row ranges staged in LDS. A wave owns
+// blocks of 16 bitmap words (512 vertices): lanes 0..15 load one visited
+// word each, the whole wave reads the block's 513 row_ptr entries with one
+// coalesced pass into LDS, and the unvisited vertices with arcs are
+// compacted into a list of block offsets. Each lane then probes two
+// candidates at a time as in bfs_bottom_up, but a candidate's arc range
+// comes from LDS, so its dependent chain is column -> frontier bit (two
+// global round trips instead of three).
+__device__ void bfs_bottom_up_rp(const BfsArgs& p, WaveLds& wl, const uint32_t* cur, uint32_t* nxt,
+                                 uint32_t* level, uint32_t next_level, uint32_t gw, uint32_t W, Stats& st) {
+    constexpr uint32_t kBlockWords = 16, kBlockV = kBlockWords * 32;
+    const uint32_t blocks = p.words / kBlockWords;
+    const uint32_t l = lane_id();
+    const uint32_t n = p.t.n;
+    uint32_t* list = wl.out;                 // candidates as block offsets (< 512)
+    uint32_t* rp = wl.out + kBlockV;         // row_ptr of the block's vertices 0..511
+    uint32_t* fw = wl.excl;                  // found bits of the block's 16 words
+    for (uint32_t b = gw; b < blocks; b += W) {
+        const uint32_t wi = b * kBlockWords + (l & 15);
+        const uint32_t v0 = b * kBlockV;
+        uint32_t vw = 0, cand = 0;
+        if (l < 16) {
+            vw = p.vis[wi];
+            cand = ~(vw | p.deg0[wi]);
+            fw[l] = 0;
+        }
+        st.words += (l == 0) ? 2u * kBlockWords : 0u;
+        const uint32_t cnt = __popc(cand);
+        const uint32_t incl = wave_incl_scan(cnt);
+        const uint32_t total = bcast(incl, kWave - 1);
+        if (total == 0) continue;
+        // row ranges of the whole block (vertices past n read row_ptr[n])
+#pragma unroll
+        for (uint32_t j = 0; j < kBlockV / kWave; ++j) {
+            const uint32_t v = v0 + j * kWave + l;
+            rp[j * kWave + l] = p.t.row_ptr[v < n ? v : n];
+        }
+        const uint32_t vend = v0 + kBlockV;
+        const uint32_t rp_end = p.t.row_ptr[vend < n ? vend : n];
+        st.rows += (l == 0) ? kBlockV : 0u;
+        uint32_t pos = incl - cnt;
+        const uint32_t wbase = (l & 15) * 32u;
+        while (cand) {
+            list[pos++] = wbase + (uint32_t)(__ffs(cand) - 1);
+            cand &= cand - 1;
+        }
+        __builtin_amdgcn_wave_barrier();
+        uint32_t next = 0, nlong = 0;
+        uint32_t o[2] = {0, 0}, k[2] = {0, 0}, e[2] = {0, 0}, s0[2] = {0, 0}, rounds[2] = {0, 0};
+        bool act[2] = {false, false};
+        for (;;) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const bool need = !act[c];
+                const uint64_t mask = __ballot(need);
+                if (next < total && mask) {
+                    const uint32_t idx = next + mbcnt(mask);
+                    if (need && idx < total) {
+                        o[c] = list[idx];
+                        act[c] = true;
+                        rounds[c] = 0;
+                        s0[c] = k[c] = rp[o[c]];
+                        e[c] = o[c] + 1 < kBlockV ? rp[o[c] + 1] : rp_end;
+                    }
+                    next += (uint32_t)__popcll(mask);
+                }
+            }
+            if (!__ballot(act[0] || act[1])) break;
+            uint32_t u[2][4];
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    u[c][j] = (act[c] && k[c] + j < e[c]) ? p.t.col[k[c] + j] : 0xFFFFFFFFu;
+            bool defer[2] = {false, false};
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                if (!act[c]) continue;
+                bool hit = false;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (u[c][j] != 0xFFFFFFFFu) hit |= ((cur[u[c][j] >> 5] >> (u[c][j] & 31)) & 1u) != 0;
+                const uint32_t got = e[c] - k[c] < 4 ? e[c] - k[c] : 4u;
+                st.arcs += got;
+                k[c] += got;
+                rounds[c] += 1;
+                if (hit) {
+                    bu_mark(p, fw, level, v0 + o[c], next_level, b * kBlockWords, e[c] - s0[c], st);
+                    act[c] = false;
+                } else if (k[c] >= e[c]) {
+                    act[c] = false;                  // no parent in this frontier
+                } else if (rounds[c] == kLaneRounds) {
+                    defer[c] = true;                 // long list: the whole wave scans it
+                    act[c] = false;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const uint64_t mask = __ballot(defer[c]);
+                if (defer[c]) wl.lng[nlong + mbcnt(mask)] = v0 + o[c];
+                nlong += (uint32_t)__popcll(mask);
+            }
+            if (nlong) {
+                __builtin_amdgcn_wave_barrier();
+                bu_scan_long(p, wl, cur, fw, level, next_level, b * kBlockWords, nlong, st);
+                nlong = 0;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (l < 16) {
             const uint32_t f = fw[l];
             if (f) {
                 p.vis[wi] = vw | f;
@@ -637,7 +758,8 @@ __device__ __forceinline__ void bfs_phase(const BfsArgs& p, BlockLds& sh, uint32
         }
     } else if (ph == kPhBU) {
         clear_share(spare, p.words, gw, W);
-        bfs_bottom_up(p, sh.wave[wave_id()], cur, nxt, lvl, level + 1, gw, W, st);
+        if (p.bu_prefetch) bfs_bottom_up_rp(p, sh.wave[wave_id()], cur, nxt, lvl, level + 1, gw, W, st);
+        else bfs_bottom_up(p, sh.wave[wave_id()], cur, nxt, lvl, level + 1, gw, W, st);
     }
     if (ph != kPhStart && ph != kPhInit) {
         stats_to_lds(sh, st);
@@ -1090,52 +1212,6 @@ __device__ __forceinline__ uint32_t color_master(const ColorArgs& p, BlockLds& s
     }
     __syncthreads();
     return sh.bar.flags;
-}
-
-// ------------------------------------------ leaving between instances
-
-// Counters of a launch whose workgroups leave between instances or queries.
-struct LeaveCounters {
-    uint32_t* active;          // workgroups inside the loop
-    uint32_t* active_x;        // ... per shader engine
-    uint32_t* kills;
-    uint32_t* min_active;
-};
-
-// offer_kill between instances (thread 0): leave if the launch holds more
-// workgroups than max(T, floor) and this workgroup's shader engine holds
-// more than its share ceil(T / engines) (a competing kernel is dealt over
-// every engine, so it needs free compute units on each of them). The
-// engine's count is claimed first with compare-and-swap, so workgroups of
-// one engine that decide together cannot all leave it; if the launch-wide
-// count is already at its floor the engine's count is given back.
-__device__ inline bool leave_for_target(const LeaveCounters& lc, uint32_t T, uint32_t floor, uint32_t engines,
-                                        uint32_t x) {
-    const uint32_t lo = T > floor ? T : floor;
-    const bool placed = engines > 1 && engines <= kMaxEngines;
-    const uint32_t share = placed ? (T + engines - 1) / engines : T;
-    uint32_t* ax = &lc.active_x[x % kMaxEngines];
-    if (placed) {
-        uint32_t e = ld_relaxed(ax);
-        for (;;) {
-            if (e <= share) return false;
-            if (__hip_atomic_compare_exchange_strong(ax, &e, e - 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT))
-                break;
-        }
-    }
-    uint32_t a = ld_relaxed(lc.active);
-    while (a > lo) {
-        if (__hip_atomic_compare_exchange_strong(lc.active, &a, a - 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT)) {
-            if (!placed) add_relaxed(ax, 0xFFFFFFFFu);
-            add_relaxed(lc.kills, 1u);
-            atomicMin(lc.min_active, a - 1);
-            return true;
-        }
-    }
-    if (placed) add_relaxed(ax, 1u);          // the launch is at its floor: stay
-    return false;
 }
 
 }  // namespace

@@ -174,6 +174,14 @@ def test_batch_autotune(rt, coop_mod, gg):
     assert best_ms <= def_ms * 1.02
     again, ms2, d2 = c.coop_batch_autotune(rt.rt, items, stride=2, reps=3)
     assert again.as_dict() == best.as_dict() and d2 < 0        # served from the cache
+    # the cache survives a save, a clear and a load (a later process)
+    import tempfile, os
+    path = os.path.join(tempfile.mkdtemp(), "tune.txt")
+    assert c.coop_tune_cache_save(path) >= 1
+    c.coop_tune_cache_clear()
+    assert c.coop_tune_cache_load(path) >= 1
+    third, _, d3 = c.coop_batch_autotune(rt.rt, items, stride=2, reps=3)
+    assert third.as_dict() == best.as_dict() and d3 < 0
     rc, st = rt.batch(items, best)
     assert rc == 0
     check(gs, outs, [0] * len(gs), list(range(len(gs))), op, c)

@@ -41,6 +41,19 @@ def as_u32(t):
     return t.cpu().numpy().view(np.uint32)
 
 
+def check_rows(out, roots, g):
+    """Every traversal's own output row (out_stride = n) equals the oracle's
+    levels for its source: the traversals that ran while workgroups were
+    being killed and forked are checked, not only the last one."""
+    got = out.cpu().numpy().view(np.uint32).reshape(len(roots), g.n)
+    exp = {}
+    for i, r in enumerate(roots):
+        r = int(r)
+        if r not in exp:
+            exp[r] = oracle.bfs(g, r)
+        assert np.array_equal(got[i], exp[r]), f"traversal {i} (source {r})"
+
+
 def modes(coop):
     return {
         "plain": coop.make_opts(coop.COOP_MODE_PLAIN),
@@ -360,6 +373,26 @@ def test_color_random_schedule(rt, coop_mod, gg):
     dg.release()
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_mis_random_schedule(rt, coop_mod, gg, seed):
+    """Greedy MIS (the same priority DAG as colouring) under a seeded random
+    kill/fork schedule: killed workgroups re-queue and are forked back in;
+    the set equals the oracle's."""
+    g = gg.er(20000, 12, 31) if seed % 2 == 0 else gg.rmat(14, 16, seed=5)
+    say(f"mis {g.name} random schedule seed={seed}")
+    dg = rt.graph(g)
+    exp = oracle.mis(g, 99 + seed)
+    o = coop_mod.make_opts(coop_mod.COOP_MODE_COOP,
+                           flags=coop_mod.COOP_F_RANDOM_SCHEDULE | coop_mod.COOP_F_PARK_KILLED,
+                           sched_seed=100 + seed, sched_p=0.5, num_groups=16, group_size=256)
+    rc, m, st = rt.mis(dg, 99 + seed, o)
+    say(f"  kills={st['kills']} forks={st['forks']} min={st['min_groups']}")
+    assert rc == 0, coop_mod.coop_strerror(rc)
+    assert st["kills"] > 0
+    assert np.array_equal(m.cpu().numpy(), exp)
+    dg.release()
+
+
 # ---------------------------------------------------------- barrier
 
 @pytest.mark.parametrize("mode", [
@@ -373,6 +406,13 @@ def test_barrier_bench(rt, coop_mod, mode):
     ns, st = coop_mod.coop_barrier_bench(rt.rt, 2000, modes(coop_mod)[mode])
     say(f"  {ns:.0f} ns/barrier, grid={st['grid']} M={st['final_groups']}")
     assert st["barriers"] >= 2000 and ns > 0
+
+
+def test_barrier_bench_refuses_plain(rt, coop_mod):
+    """The plain barrier-only launch is refused before anything is queued
+    (its one hang is not explained); cooperative ones run (above)."""
+    with pytest.raises(coop_mod.CoopError):
+        coop_mod.coop_barrier_bench(rt.rt, 10, coop_mod.make_opts(coop_mod.COOP_MODE_PLAIN))
 
 
 # ------------------------------------------------- host target, co-tasks
@@ -394,8 +434,8 @@ def test_bfs_host_target_xcd_kills(rt, coop_mod, gg):
     out = torch.empty(len(roots) * g.n, dtype=torch.int32, device="cuda")
     # the same 24 sources over and over: each output row is rewritten by identical runs
     o = c.make_opts(c.COOP_MODE_COOP, flags=c.COOP_F_HOST_SCHEDULE)
-    lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
-    h = c.coop_bfs(rt.rt, dg.handle, d_roots, k, lv, 0, o)
+    lv = torch.empty(k * g.n, dtype=torch.int32, device="cuda")
+    h = c.coop_bfs(rt.rt, dg.handle, d_roots, k, lv, g.n, o)
     n = c.coop_handle_groups(h)
     for step in range(6):
         time.sleep(0.004)
@@ -406,8 +446,7 @@ def test_bfs_host_target_xcd_kills(rt, coop_mod, gg):
     assert rc == 0, c.coop_strerror(rc)
     say(f"  kills={st['kills']} forks={st['forks']} min={st['min_groups']} ms={st['kernel_ms']:.1f}")
     assert st["kills"] > 0
-    # the last source's levels are in lv
-    assert np.array_equal(as_u32(lv), oracle.bfs(g, int(reps[-1])))
+    check_rows(lv, reps, g)
     # and a multi-root launch under the same schedule writes every row right
     d24 = rt._roots(roots)
     h = c.coop_bfs(rt.rt, dg.handle, d24, len(roots), out, g.n, o)
@@ -434,18 +473,18 @@ def test_cotask_injector_during_bfs(rt, coop_mod, gg):
     dg = rt.graph(g)
     roots = np.resize(gg.sources(g, 3, 16), 600).astype(np.uint32)
     d_roots = rt._roots(roots)
-    lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    lv = torch.empty(len(roots) * g.n, dtype=torch.int32, device="cuda")
     o = c.make_opts(c.COOP_MODE_COOP, flags=c.COOP_F_HOST_SCHEDULE)
     cus = rt.info["compute_units"]
     say("co-task injector during bfs rmat18")
-    h = c.coop_bfs(rt.rt, dg.handle, d_roots, len(roots), lv, 0, o)
+    h = c.coop_bfs(rt.rt, dg.handle, d_roots, len(roots), lv, g.n, o)
     c.coop_injector_start(rt.rt, h, groups=cus // 2, busy_ns=500_000, period_ns=5_000_000)
     rc, st = c.coop_wait(h)
     irc, cst = c.coop_injector_stop(rt.rt)
     assert rc == 0 and irc == 0
     say(f"  kernel {st['kernel_ms']:.1f} ms kills={st['kills']} co-tasks={cst['count']} "
         f"p50={cst['latency_p50_ms']:.3f} p99={cst['latency_p99_ms']:.3f} max={cst['latency_max_ms']:.3f} ms")
-    assert np.array_equal(as_u32(lv), oracle.bfs(g, int(roots[-1])))
+    check_rows(lv, roots, g)
     assert cst["count"] >= 3
     # no co-task waited for the whole traversal
     assert cst["latency_max_ms"] < 0.5 * st["kernel_ms"]
@@ -462,18 +501,19 @@ def test_regular_barrier_under_cotasks(rt, coop_mod, gg):
     dg = rt.graph(g)
     roots = np.resize(gg.sources(g, 3, 16), 300).astype(np.uint32)
     d_roots = rt._roots(roots)
-    lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    lv = torch.empty(len(roots) * g.n, dtype=torch.int32, device="cuda")
     cus = rt.info["compute_units"]
     res = {}
     for name, extra in (("query", 0), ("regular", c.COOP_F_REGULAR_BARRIER)):
         o = c.make_opts(c.COOP_MODE_COOP, flags=c.COOP_F_HOST_SCHEDULE | extra)
         say(f"bfs rmat18 x{len(roots)} under co-tasks, {name} barrier")
-        h = c.coop_bfs(rt.rt, dg.handle, d_roots, len(roots), lv, 0, o)
+        lv.fill_(-5)
+        h = c.coop_bfs(rt.rt, dg.handle, d_roots, len(roots), lv, g.n, o)
         c.coop_injector_start(rt.rt, h, groups=cus // 4, busy_ns=300_000, period_ns=3_000_000)
         rc, st = c.coop_wait(h)
         irc, cst = c.coop_injector_stop(rt.rt)
         assert rc == 0 and irc == 0, (c.coop_strerror(rc), c.coop_strerror(irc))
-        assert np.array_equal(as_u32(lv), oracle.bfs(g, int(roots[-1])))
+        check_rows(lv, roots, g)
         say(f"  kernel {st['kernel_ms']:.1f} ms barriers={st['barriers']} kills={st['kills']} "
             f"co-tasks={cst['count']} gather p50={cst['gather_p50_ms']:.3f} ms")
         assert cst["count"] >= 1 and st["kills"] > 0
@@ -496,10 +536,10 @@ def test_host_target_down_to_one_and_back(rt, coop_mod, gg):
     dg = rt.graph(g)
     roots = np.resize(gg.sources(g, 3, 16), 2000).astype(np.uint32)
     d_roots = rt._roots(roots)
-    lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    lv = torch.empty(len(roots) * g.n, dtype=torch.int32, device="cuda")
     o = c.make_opts(c.COOP_MODE_COOP, flags=c.COOP_F_HOST_SCHEDULE)
     say(f"bfs rmat18 x{len(roots)}: target 1, then back to N")
-    h = c.coop_bfs(rt.rt, dg.handle, d_roots, len(roots), lv, 0, o)
+    h = c.coop_bfs(rt.rt, dg.handle, d_roots, len(roots), lv, g.n, o)
     n = c.coop_handle_groups(h)
     time.sleep(0.01)
     c.coop_set_target(h, 1)
@@ -510,7 +550,7 @@ def test_host_target_down_to_one_and_back(rt, coop_mod, gg):
     say(f"  kernel {st['kernel_ms']:.1f} ms kills={st['kills']} forks={st['forks']} "
         f"min={st['min_groups']} final={st['final_groups']}")
     assert rc == 0, c.coop_strerror(rc)
-    assert np.array_equal(as_u32(lv), oracle.bfs(g, int(roots[-1])))
+    check_rows(lv, roots, g)
     # the hardware deals joiners over the shader engines, so one may wait for
     # a unit on its own engine while another engine has one idle: nearly N
     assert st["min_groups"] == 1 and st["final_groups"] >= n - 8
@@ -533,11 +573,11 @@ def test_admission_ring_flood(rt, coop_mod, gg, window):
     dg = rt.graph(g)
     roots = np.resize(gg.sources(g, 3, 16), 2000).astype(np.uint32)
     d_roots = rt._roots(roots)
-    lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    lv = torch.empty(len(roots) * g.n, dtype=torch.int32, device="cuda")
     cus = rt.info["compute_units"]
     o = c.make_opts(c.COOP_MODE_COOP, flags=c.COOP_F_HOST_SCHEDULE, join_window=window)
     say(f"bfs rmat18 x{len(roots)}: 12000 joiners at half target, join_window={window}")
-    h = c.coop_bfs(rt.rt, dg.handle, d_roots, len(roots), lv, 0, o)
+    h = c.coop_bfs(rt.rt, dg.handle, d_roots, len(roots), lv, g.n, o)
     time.sleep(0.01)
     c.coop_set_target(h, cus // 2)
     time.sleep(0.01)
@@ -549,7 +589,7 @@ def test_admission_ring_flood(rt, coop_mod, gg, window):
     say(f"  kernel {st['kernel_ms']:.1f} ms kills={st['kills']} forks={st['forks']} "
         f"join_full={st['join_full']} min_groups={st['min_groups']}")
     assert rc == 0, c.coop_strerror(rc)
-    assert np.array_equal(as_u32(lv), oracle.bfs(g, int(roots[-1])))
+    check_rows(lv, roots, g)
     assert st["kills"] > 0 and st["min_groups"] <= cus // 2
     if window:
         assert st["join_full"] > 0
