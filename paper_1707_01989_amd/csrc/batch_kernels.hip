@@ -117,12 +117,19 @@ __device__ void batch_body(const BatchArgs& a, bool joiner) {
         const uint32_t rank = __builtin_amdgcn_readfirstlane(sh.aux);
         const BatchInst& I = *(const BatchInst*)((ConstInst*)(uintptr_t)a.inst + i);
         const uint32_t ops = I.ops, team = I.team;
+        // the team barriers keep their membership in the same LDS block as
+        // the launch-wide (task-pattern) one, and leave it at the team's
+        // rank and not alive when the instance ends: the launch-wide one is
+        // put back before the next offer_kill
+        const Member task_member = g.bar.member;
         if (ops & kBatchBfs) bfs_team(I.bfs, sh, rank, team);
         if (ops & kBatchColor) color_team(I.col, sh, rank, team);
         if (threadIdx.x == 0) {
             int32_t e = ld_relaxed_i(&I.bfs.t.ctx->error);
             if (!e) e = ld_relaxed_i(&I.col.t.ctx->error);
             if (e) atomicCAS(&ctl->error, 0, e);
+            g.bar.member = task_member;
+            g.bar.killed = 0;
         }
         __syncthreads();
     }
