@@ -52,7 +52,8 @@ enum {
     COOP_E_TIMEOUT = -4,   /* barrier watchdog fired (non-residency or deadlock) */
     COOP_E_BUSY = -5,      /* request can never fit (serving) */
     COOP_E_OVERFLOW = -6,  /* a distance does not fit in int32 */
-    COOP_E_INTERNAL = -7   /* internal capacity or consistency error */
+    COOP_E_INTERNAL = -7,  /* internal capacity or consistency error */
+    COOP_E_TOO_BIG = -8    /* request exceeds a fixed capacity (coop_bfs_noalloc's scratch) */
 };
 
 /* Text for an error code (static storage). */
@@ -181,6 +182,37 @@ typedef struct coop_stats {
 int coop_bfs(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_t nroots,
              uint32_t* d_level, uint64_t out_stride, const coop_launch_opts* opts,
              coop_stream_t stream, coop_handle** out);
+
+/* coop_bfs for callers that cannot allocate: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc. The same BFS with
+ * the same roots, levels, out_stride and options as coop_bfs; it differs in
+ * this:
+ *  - Nothing is allocated (no device or pinned memory, no events, no
+ *    handle). Every scratch buffer of the launch (context, transmit block,
+ *    per-workgroup statistics, heavy-strip list, visited and three frontier
+ *    bitmaps: about n/2 bytes plus 130 KiB) lives in one static device array
+ *    of COOP_NOALLOC_SCRATCH_BYTES per GPU, whose address coop_init looks up.
+ *    A call needing more returns COOP_E_TOO_BIG and enqueues nothing (up to
+ *    about 60 million vertices fit).
+ *  - The call only enqueues four kernels on `stream` (context clear,
+ *    statistics clear, the BFS, a status copy) and returns COOP_OK; the
+ *    launch's result code (COOP_OK, COOP_E_INVALID for a source >= n,
+ *    COOP_E_TIMEOUT, ...) is written to *d_status, one int32 of caller-owned
+ *    device memory, in stream order. No statistics are returned.
+ *  - COOP_F_HOST_SCHEDULE is refused (COOP_E_INVALID): its target word
+ *    lives in pinned memory. Plain and cooperative launches and the seeded
+ *    device schedule (COOP_F_RANDOM_SCHEDULE) work.
+ *  - Every call on one GPU uses that GPU's one array, which keeps the last
+ *    call's contents (each call clears what must start at zero). Calls that
+ *    overlap on one GPU race: calls on different streams, threads or
+ *    runtimes of the same GPU must be ordered by the caller; calls on one
+ *    stream are ordered already.
+ * Other errors: COOP_E_INVALID for arguments coop_bfs refuses or a null
+ * d_status, COOP_E_HIP when a launch fails. */
+#define COOP_NOALLOC_SCRATCH_BYTES (32u << 20)
+int coop_bfs_noalloc(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_t nroots,
+                     uint32_t* d_level, uint64_t out_stride, const coop_launch_opts* opts,
+                     int32_t* d_status, coop_stream_t stream);
 
 /* SSSP by frontier Bellman-Ford (relaxations with atomicMin; a vertex whose
  * distance dropped is queued once for the next round). Distances int32;

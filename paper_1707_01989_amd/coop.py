@@ -24,6 +24,8 @@ COOP_E_TIMEOUT = -4
 COOP_E_BUSY = -5
 COOP_E_OVERFLOW = -6
 COOP_E_INTERNAL = -7
+COOP_E_TOO_BIG = -8
+COOP_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 COOP_MODE_PLAIN = 0
 COOP_MODE_COOP = 1
@@ -57,7 +59,7 @@ UNREACHED_DIST = 0x7FFFFFFF
 # every symbol include/coop.h declares (checked by the ABI test)
 EXPORTS = [
     "coop_strerror", "coop_launch_opts_default", "coop_init", "coop_shutdown", "coop_device_query",
-    "coop_last_hip_error", "coop_graph_wrap", "coop_graph_release", "coop_bfs", "coop_sssp",
+    "coop_last_hip_error", "coop_graph_wrap", "coop_graph_release", "coop_bfs", "coop_bfs_noalloc", "coop_sssp",
     "coop_cc", "coop_color", "coop_mis", "coop_launch", "coop_wait", "coop_handle_groups", "coop_set_target",
     "coop_fork_groups", "coop_cotask_run", "coop_injector_start", "coop_injector_stop",
     "coop_share_start", "coop_share_add", "coop_share_stop", "coop_octree",
@@ -228,6 +230,7 @@ def load_library():
         "coop_graph_wrap": (i32, [VP, VP, VP, VP, u32, u64, VPP]),
         "coop_graph_release": (i32, [VP]),
         "coop_bfs": (i32, [VP, VP, VP, u32, VP, u64, ctypes.POINTER(coop_launch_opts), VP, VPP]),
+        "coop_bfs_noalloc": (i32, [VP, VP, VP, u32, VP, u64, ctypes.POINTER(coop_launch_opts), VP, VP]),
         "coop_sssp": (i32, [VP, VP, VP, u32, VP, u64, ctypes.POINTER(coop_launch_opts), VP, VPP]),
         "coop_color": (i32, [VP, VP, u64, VP, ctypes.POINTER(coop_launch_opts), VP, VPP]),
         "coop_cc": (i32, [VP, VP, VP, ctypes.POINTER(coop_launch_opts), VP, VPP]),
@@ -351,6 +354,15 @@ def coop_bfs(rt, g, roots, nroots, level, out_stride=0, opts=None, stream=None, 
                                  ctypes.byref(h) if keep else None)
     _check(rc, "coop_bfs")
     return h.value if keep else None
+
+
+def coop_bfs_noalloc(rt, g, roots, nroots, level, out_stride=0, opts=None, status=None, stream=None):
+    """Enqueue only; the launch's result code lands in `status` (one int32
+    on the device)."""
+    rc = load_library().coop_bfs_noalloc(rt, g, _ptr(roots), nroots, _ptr(level), out_stride,
+                                         ctypes.byref(opts) if opts is not None else None, _ptr(status),
+                                         _stream(stream))
+    _check(rc, "coop_bfs_noalloc")
 
 
 def coop_sssp(rt, g, roots, nroots, dist, out_stride=0, opts=None, stream=None, keep=True):

@@ -364,6 +364,8 @@ uint32_t occupancy_batch(bool coop, uint32_t block, uint32_t lds_bytes);
 // Launchers (defined in coop_kernels.hip). Each returns a hipError_t.
 hipError_t launch_init_ctx(Ctx* c, Work* w, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s);
+// *out = the launch context's error word, in stream order after the launch
+hipError_t launch_copy_status(const CtxCore* c, int32_t* out, hipStream_t s);
 // Bitmap of vertices without arcs (words: multiple of 64, padding bits set).
 hipError_t launch_deg0_bitmap(const uint32_t* row_ptr, uint32_t n, uint32_t* bits, uint32_t words, hipStream_t s);
 // Count (into *bad, cleared first) the column indices that are >= n.

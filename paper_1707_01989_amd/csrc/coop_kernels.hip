@@ -238,6 +238,10 @@ __global__ void fill_u32_kernel(uint32_t* p, uint64_t count, uint32_t value) {
         p[i] = value;
 }
 
+__global__ void copy_status_kernel(const CtxCore* c, int32_t* out) {
+    if (threadIdx.x == 0) *out = ld_relaxed_i(&c->error);
+}
+
 // Bit v of `bits` is set when vertex v has no arcs; bits past n are set too.
 __global__ void deg0_bitmap_kernel(const uint32_t* row_ptr, uint32_t n, uint32_t* bits, uint32_t words) {
     for (uint32_t wi = blockIdx.x * blockDim.x + threadIdx.x; wi < words; wi += gridDim.x * blockDim.x) {
@@ -345,6 +349,11 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStrea
     uint64_t blocks = (count + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(fill_u32_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, p, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_status(const CtxCore* c, int32_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(copy_status_kernel, dim3(1), dim3(64), 0, s, c, out);
     return hipGetLastError();
 }
 

@@ -33,6 +33,12 @@ using coop::CtxCore;
 using coop::HostCtl;
 using coop::Work;
 
+// Scratch of coop_bfs_noalloc: one array per GPU, for callers that cannot
+// allocate. Host code never uses this name as an address (it is a host-side
+// stand-in): coop_init looks up the device address with
+// hipGetSymbolAddress and keeps it in the runtime.
+static __device__ __align__(256) unsigned char scratch[COOP_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 constexpr uint32_t kDefaultLds = 96 * 1024;       // > half a CU's 160 KiB: one workgroup per CU
@@ -43,6 +49,9 @@ constexpr uint64_t kDefaultWatchdogNs = 10ull * 1000 * 1000 * 1000;
 // memory fault or hung queue twice, and no cause has been shown yet.
 constexpr bool kServerEnabled = false;
 constexpr uint32_t kDefaultStartupNs = 20 * 1000;
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 double now_ms() {
     using namespace std::chrono;
@@ -82,6 +91,15 @@ struct coop_graph {
         for (uint32_t d : deg)
             if (d > th) s += (d + strip - 1) / strip;
         strips[key] = s;
+        return s;
+    }
+    // the same count without caching it (no allocation)
+    uint64_t heavy_strips_lookup(uint32_t th, uint32_t strip) const {
+        auto it = strips.find(std::make_pair(th, strip));
+        if (it != strips.end()) return it->second;
+        uint64_t s = 0;
+        for (uint32_t d : deg)
+            if (d > th) s += (d + strip - 1) / strip;
         return s;
     }
 };
@@ -137,6 +155,7 @@ struct coop_rt {
     // co-task state (counters on the device, stamps in pinned host memory)
     uint32_t* d_cot = nullptr;                 // [0] started, [1] finished (cumulative)
     uint32_t* d_check = nullptr;               // graph check: column indices outside [0, n)
+    void* noalloc = nullptr;                   // device address of `scratch` on this GPU
     uint32_t cot_launched = 0;                 // co-task workgroups launched so far
     uint64_t* h_stamp = nullptr;               // [0] all started, [1] all finished
     // injector
@@ -302,6 +321,28 @@ int size_launch(coop_rt* rt, const coop_launch_opts* o, Sizing* s, uint32_t min_
     return COOP_OK;
 }
 
+// Launch constants of a sized launch (`host`: the pinned target word of a
+// host-driven schedule, or null).
+void fill_cfg(coop_rt* rt, const coop_launch_opts* o, const Sizing& sz, HostCtl* host, coop::Cfg& cfg) {
+    cfg = coop::Cfg{};
+    cfg.N = sz.grid;
+    cfg.mode = sz.mode;
+    cfg.sched_p16 = sz.sched_p16;
+    cfg.sched_seed = o ? o->sched_seed : 0;
+    cfg.watchdog_ticks = sz.watchdog_ticks;
+    cfg.host = host;
+    cfg.trace = o ? o->d_trace : nullptr;
+    cfg.trace_cap = (o && o->d_trace) ? o->trace_cap : 0u;
+    cfg.epoch0_wait = sz.startup_ticks;
+    cfg.wgtrace = o ? o->d_wgtrace : nullptr;
+    cfg.wgtrace_cap = (o && o->d_wgtrace) ? o->trace_cap : 0u;
+    cfg.ses = rt->ses;
+    cfg.engines = rt->xcds * rt->ses;
+    cfg.slots_per_engine = std::max<uint32_t>(1, sz.resident / std::max<uint32_t>(1, cfg.engines));
+    cfg.join_window = coop::kJoinCap - sz.grid;
+    if (o && o->join_window) cfg.join_window = std::min(cfg.join_window, std::max(o->join_window, sz.grid));
+}
+
 // Common launch preamble: handle, context, pinned control block, events.
 int begin_launch(coop_rt* rt, const coop_launch_opts* o, const Sizing& sz, int kind, hipStream_t stream,
                  coop_handle** hout) {
@@ -328,23 +369,7 @@ int begin_launch(coop_rt* rt, const coop_launch_opts* o, const Sizing& sz, int k
     for (hipEvent_t* e : {&h->ev_init, &h->ev_start, &h->ev_end, &h->ev_join}) {
         if (hipEventCreate(e) != hipSuccess) { handle_free(h); return hip_fail(rt, hipErrorOutOfMemory); }
     }
-    coop::Cfg& cfg = h->cfg;
-    cfg.N = sz.grid;
-    cfg.mode = sz.mode;
-    cfg.sched_p16 = sz.sched_p16;
-    cfg.sched_seed = o ? o->sched_seed : 0;
-    cfg.watchdog_ticks = sz.watchdog_ticks;
-    cfg.host = host;
-    cfg.trace = o ? o->d_trace : nullptr;
-    cfg.trace_cap = (o && o->d_trace) ? o->trace_cap : 0u;
-    cfg.epoch0_wait = sz.startup_ticks;
-    cfg.wgtrace = o ? o->d_wgtrace : nullptr;
-    cfg.wgtrace_cap = (o && o->d_wgtrace) ? o->trace_cap : 0u;
-    cfg.ses = rt->ses;
-    cfg.engines = rt->xcds * rt->ses;
-    cfg.slots_per_engine = std::max<uint32_t>(1, sz.resident / std::max<uint32_t>(1, cfg.engines));
-    cfg.join_window = coop::kJoinCap - sz.grid;
-    if (o && o->join_window) cfg.join_window = std::min(cfg.join_window, std::max(o->join_window, sz.grid));
+    fill_cfg(rt, o, sz, host, h->cfg);
     hipError_t e = coop::launch_init_ctx(h->ctx, h->work, stream);
     if (e != hipSuccess) { handle_free(h); return hip_fail(rt, e); }
     *hout = h;
@@ -459,6 +484,7 @@ const char* coop_strerror(int code) {
         case COOP_E_BUSY: return "request can never fit";
         case COOP_E_OVERFLOW: return "distance overflows int32";
         case COOP_E_INTERNAL: return "internal capacity error";
+        case COOP_E_TOO_BIG: return "request exceeds a fixed capacity (the no-allocation scratch)";
     }
     return "unknown error";
 }
@@ -487,6 +513,9 @@ int coop_init(int device, coop_rt** out) {
     if (e == hipSuccess) e = hipMalloc(&rt->d_cot, 256);
     if (e == hipSuccess) e = hipMemset(rt->d_cot, 0, 256);
     if (e == hipSuccess) e = hipMalloc(&rt->d_check, 256);
+    // the allocation-free entry point's array, at its address on this GPU
+    if (e == hipSuccess) e = hipGetSymbolAddress(&rt->noalloc, HIP_SYMBOL(scratch));
+    if (e == hipSuccess && !rt->noalloc) e = hipErrorInvalidSymbol;
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&rt->h_stamp), 64,
                                            hipHostMallocCoherent | hipHostMallocMapped);
     if (e == hipSuccess) {
@@ -660,6 +689,72 @@ int coop_bfs(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_t
     (void)hipEventRecord(h->ev_init, s);
     (void)hipEventRecord(h->ev_start, s);
     return finish_launch(rt, h, relaunch(h, false, h->grid, s), out);
+}
+
+int coop_bfs_noalloc(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_t nroots,
+                     uint32_t* d_level, uint64_t out_stride, const coop_launch_opts* opts, int32_t* d_status,
+                     coop_stream_t stream) {
+    int rc = check_traversal_args(rt, g, d_roots, nroots, d_level, out_stride);
+    if (rc) return rc;
+    if (!d_status || !rt->noalloc) return COOP_E_INVALID;
+    // a host-driven target lives in pinned memory the library would allocate
+    if (opts && (opts->flags & COOP_F_HOST_SCHEDULE)) return COOP_E_INVALID;
+    Sizing sz{};
+    if ((rc = size_launch(rt, opts, &sz))) return rc;
+    const uint32_t th = (opts && opts->heavy_threshold) ? opts->heavy_threshold : kDefaultHeavy;
+    const uint32_t strip = (opts && opts->strip) ? opts->strip : kDefaultStrip;
+    uint64_t hs;
+    {
+        std::lock_guard<std::recursive_mutex> lk(rt->mu);
+        hs = g->heavy_strips_lookup(th, strip);
+    }
+    if (hs > 0xFFFFFFFFull) return COOP_E_TOO_BIG;
+    // the array's layout for this call: context | transmit block | slots |
+    // heavy strips | visited, frontier x 3
+    const size_t slot_words = (size_t)sz.grid * coop::kSlotWords;
+    const size_t o_work = align_up(sizeof(Ctx));
+    const size_t o_slots = o_work + align_up(sizeof(Work));
+    const size_t o_heavy = o_slots + align_up(slot_words * 4);
+    const size_t o_bits = o_heavy + align_up(hs * sizeof(uint4));
+    const size_t bm = align_up((size_t)g->words * 4);
+    const size_t total = o_bits + 4 * bm;
+    if (total > COOP_NOALLOC_SCRATCH_BYTES) return COOP_E_TOO_BIG;
+    char* base = static_cast<char*>(rt->noalloc);
+    coop::BfsArgs a{};
+    fill_cfg(rt, opts, sz, nullptr, a.t.cfg);
+    a.t.ctx = reinterpret_cast<Ctx*>(base);
+    a.t.work = reinterpret_cast<Work*>(base + o_work);
+    a.t.slots = reinterpret_cast<uint32_t*>(base + o_slots);
+    a.t.row_ptr = g->row_ptr;
+    a.t.col = g->col;
+    a.t.w = g->w;
+    a.t.n = g->n;
+    a.t.N = sz.grid;
+    a.t.heavy_th = th;
+    a.t.strip = strip;
+    a.t.heavy_cap = (uint32_t)hs;
+    a.t.heavy = hs ? reinterpret_cast<uint4*>(base + o_heavy) : nullptr;
+    a.t.roots = d_roots;
+    a.t.nroots = nroots;
+    a.t.out_stride = (uint32_t)out_stride;
+    a.words = g->words;
+    a.vis = reinterpret_cast<uint32_t*>(base + o_bits);
+    for (int i = 0; i < 3; ++i) a.fb[i] = reinterpret_cast<uint32_t*>(base + o_bits + (size_t)(i + 1) * bm);
+    a.deg0 = g->deg0;
+    a.level_out = d_level;
+    a.direction_opt = (opts && (opts->flags & COOP_F_TOP_DOWN_ONLY)) ? 0u : 1u;
+    a.alpha = (opts && opts->bu_alpha) ? opts->bu_alpha : 14u;
+    a.beta = (opts && opts->bu_beta) ? opts->bu_beta : 24u;
+    a.total_arcs = g->arcs;
+    a.bu_prefetch = (opts && (opts->flags & (1u << 31))) ? 1u : 0u;
+    // the array keeps the previous call's contents: the context and the
+    // slots are cleared here, the bitmaps by the kernel's per-source init
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = coop::launch_init_ctx(static_cast<Ctx*>(a.t.ctx), a.t.work, s);
+    if (e == hipSuccess) e = coop::launch_fill_u32(a.t.slots, slot_words, 0u, s);
+    if (e == hipSuccess) e = coop::launch_bfs(a, sz.coop, false, sz.grid, sz.block, sz.lds, s);
+    if (e == hipSuccess) e = coop::launch_copy_status(a.t.ctx, d_status, s);
+    return e == hipSuccess ? COOP_OK : hip_fail(rt, e);
 }
 
 int coop_sssp(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_t nroots, int32_t* d_dist,
@@ -998,9 +1093,6 @@ void coop_tune_default(coop_tune* t) {
 }
 
 namespace {
-
-constexpr size_t kAlign = 256;
-size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 int check_batch_item(coop_rt* rt, const coop_batch_item& it) {
     const coop_graph* g = it.graph;
