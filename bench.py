@@ -38,7 +38,7 @@ Printed JSON line (one):
   octree         work-stealing octree build, coop vs plain, with co-tasks
   batch          512 ER instances, BFS (+ colouring) in one launch: default
                  vs autotuned schedule
-  barrier_ns     2000 barriers of an empty cooperative launch
+  barrier_ns     2000 barriers of an empty launch, cooperative and plain
   cpu_baseline   the oracle (one core) on a bounded sample of the headline
                  sources; all_cores: the OpenMP level-synchronous BFS
 """
@@ -465,7 +465,9 @@ def main():
     if not args.skip_barrier:
         # global-barrier latency (persistent launch doing barriers only)
         ns, _ = coop.coop_barrier_bench(rt.rt, 2000, coop_opts, stream)
-        result["barrier_ns"] = {"coop": round(ns, 1)}
+        ns_p, _ = coop.coop_barrier_bench(rt.rt, 2000, plain_opts, stream)
+        result["barrier_ns"] = {"coop": round(ns, 1), "plain": round(ns_p, 1),
+                                "coop_overhead": round(ns / ns_p, 4)}
         log(f"barrier ns: {result['barrier_ns']}")
 
     if args.copy_probe_mib > 0:

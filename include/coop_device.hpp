@@ -579,9 +579,16 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
         drain0 = (live && kmax == 0 && span >= kDrainMin) ? span : 0u;
         b.drain_span = drain0;
     }
+    // every thread reads what thread 0 just shared (b.flags decides below
+    // whether the whole workgroup recounts the members per XCD, a block with
+    // workgroup barriers inside): in every launch mode, since an
+    // algorithm's single step need not have left the flags in b.flags, and
+    // the LDS may still hold an earlier launch's value (a plain launch that
+    // read it unsynchronised split its barriers between the threads that saw
+    // DONE there and thread 0, and miscounted the arrivals)
+    __syncthreads();
     uint32_t admitted = 0;
     if constexpr (Coop) {
-        __syncthreads();
         const uint32_t kmax = b.kmax, head = b.head;
         if (b.drain_span) {
             if (threadIdx.x == 0) b.drained = b.drain_span;

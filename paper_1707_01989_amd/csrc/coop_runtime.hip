@@ -2232,9 +2232,6 @@ int coop_share_stop(coop_rt* rt, coop_share_stats* out) {
 int coop_barrier_bench(coop_rt* rt, const coop_launch_opts* opts, uint32_t iters, coop_stream_t stream,
                        double* ns_per_barrier, coop_stats* stats) {
     if (!rt || iters == 0) return COOP_E_INVALID;
-    // a plain launch of nothing but barriers once waited out its watchdog
-    // and no cause has been shown; it is refused until one is
-    if (!opts || opts->mode == COOP_MODE_PLAIN) return COOP_E_INVALID;
     coop_params p{};
     p.barrier_iters = iters;
     coop_handle* h = nullptr;
