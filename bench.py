@@ -57,10 +57,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bfs_kernel_rmat22_traffic.txt")
-# the kernel and the runtime that sizes and parameterises its launches
+# the kernel, the runtime that sizes and parameterises its launches, and the
+# graph preparation that orders the arcs its bottom-up levels probe
 KERNEL_SOURCES = ("paper_1707_01989_amd/csrc/coop_kernels.hip", "paper_1707_01989_amd/csrc/traverse.h",
                   "paper_1707_01989_amd/csrc/coop_internal.h", "include/coop_device.hpp",
-                  "paper_1707_01989_amd/csrc/coop_runtime.hip")
+                  "paper_1707_01989_amd/csrc/coop_runtime.hip", "paper_1707_01989_amd/csrc/graph_prep.hip")
 
 
 def log(msg):

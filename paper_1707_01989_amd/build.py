@@ -25,7 +25,7 @@ GRAPHGEN_SO = os.path.join(LIB_DIR, "libgraphgen.so")
 COOP_SO = os.path.join(LIB_DIR, "libcoop.so")
 
 HIP_SOURCES = ["coop_kernels.hip", "batch_kernels.hip", "serve_kernels.hip", "octree_kernels.hip",
-               "cc_kernels.hip", "coop_runtime.hip"]
+               "cc_kernels.hip", "graph_prep.hip", "coop_runtime.hip"]
 HIP_ARCH = "gfx950"
 
 

@@ -122,6 +122,8 @@ struct BfsArgs {
     uint32_t alpha, beta;      // switching parameters (Beamer et al.)
     uint64_t total_arcs;
     uint32_t bu_prefetch;      // bottom-up levels stage each block's row ranges in LDS
+    const uint32_t* col_bu;    // bottom-up probe order: every list by decreasing neighbour degree,
+                               // 16-byte aligned and padded by 4 words (the graph's copy)
 };
 
 struct SsspArgs {
@@ -367,6 +369,11 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStrea
 // *out = the launch context's error word, in stream order after the launch
 hipError_t launch_copy_status(const CtxCore* c, int32_t* out, hipStream_t s);
 // Bitmap of vertices without arcs (words: multiple of 64, padding bits set).
+// Probe-order copy of `col` (every list by decreasing neighbour degree, ties
+// in list order) into `out` (arcs + 4 words); allocates its temporaries and
+// waits for `s`.
+hipError_t build_degree_order(const uint32_t* row_ptr, const uint32_t* col, uint32_t n, uint64_t arcs,
+                              uint32_t max_deg, uint32_t* out, hipStream_t s);
 hipError_t launch_deg0_bitmap(const uint32_t* row_ptr, uint32_t n, uint32_t* bits, uint32_t words, hipStream_t s);
 // Count (into *bad, cleared first) the column indices that are >= n.
 hipError_t launch_check_cols(const uint32_t* col, uint64_t arcs, uint32_t n, uint32_t* bad, hipStream_t s);

@@ -79,6 +79,7 @@ struct coop_graph {
     uint64_t arcs;
     uint32_t max_deg;
     uint32_t* deg0 = nullptr;                            // device bitmap: vertices without arcs
+    uint32_t* col_bu = nullptr;                          // bottom-up probe order (arcs + 4 words)
     uint32_t words = 0;                                  // bitmap words (multiple of 64)
     std::vector<uint32_t> deg;                           // host copy of the degrees
     std::map<std::pair<uint32_t, uint32_t>, uint64_t> strips;   // (threshold, strip) -> capacity
@@ -635,7 +636,17 @@ int coop_graph_wrap(coop_rt* rt, const uint32_t* d_row_ptr, const uint32_t* d_co
         std::lock_guard<std::recursive_mutex> lk(rt->mu);
         int rc = ensure_deg0(rt, g, rt->cotask_stream);
         if (rc == COOP_OK && hipStreamSynchronize(rt->cotask_stream) != hipSuccess) rc = COOP_E_HIP;
+        // and the bottom-up probe order: every list by decreasing neighbour
+        // degree (the first arc mostly decides a bottom-up probe)
+        if (rc == COOP_OK) {
+            hipError_t e = hipMalloc(&g->col_bu, (size_t)(arcs + 4) * 4);
+            if (e == hipSuccess)
+                e = coop::build_degree_order(d_row_ptr, d_col, n, arcs, g->max_deg, g->col_bu, rt->cotask_stream);
+            if (e != hipSuccess) rc = e == hipErrorOutOfMemory ? COOP_E_OOM : hip_fail(rt, e);
+        }
         if (rc != COOP_OK) {
+            if (g->col_bu) (void)hipFree(g->col_bu);
+            if (g->deg0) (void)hipFree(g->deg0);
             delete g;
             return rc;
         }
@@ -646,10 +657,9 @@ int coop_graph_wrap(coop_rt* rt, const uint32_t* d_row_ptr, const uint32_t* d_co
 
 int coop_graph_release(coop_graph* g) {
     if (!g) return COOP_E_INVALID;
-    if (g->deg0) {
-        (void)hipDeviceSynchronize();
-        (void)hipFree(g->deg0);
-    }
+    if (g->deg0 || g->col_bu) (void)hipDeviceSynchronize();
+    if (g->deg0) (void)hipFree(g->deg0);
+    if (g->col_bu) (void)hipFree(g->col_bu);
     delete g;
     return COOP_OK;
 }
@@ -685,6 +695,7 @@ int coop_bfs(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_t
     a.beta = (opts && opts->bu_beta) ? opts->bu_beta : 24u;
     a.total_arcs = g->arcs;
     a.bu_prefetch = (opts && (opts->flags & (1u << 31))) ? 1u : 0u;
+    a.col_bu = g->col_bu;
     if (!a.vis || !a.fb[0] || !a.fb[1] || !a.fb[2]) { handle_free(h); return COOP_E_OOM; }
     (void)hipEventRecord(h->ev_init, s);
     (void)hipEventRecord(h->ev_start, s);
@@ -747,6 +758,7 @@ int coop_bfs_noalloc(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, 
     a.beta = (opts && opts->bu_beta) ? opts->bu_beta : 24u;
     a.total_arcs = g->arcs;
     a.bu_prefetch = (opts && (opts->flags & (1u << 31))) ? 1u : 0u;
+    a.col_bu = g->col_bu;
     // the array keeps the previous call's contents: the context and the
     // slots are cleared here, the bitmaps by the kernel's per-source init
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -1235,6 +1247,7 @@ int coop_batch_run(coop_rt* rt, const coop_batch_item* items, uint32_t count, co
             I.bfs.alpha = 14;
             I.bfs.beta = 24;
             I.bfs.total_arcs = g->arcs;
+            I.bfs.col_bu = g->col_bu;
         }
         // colouring / MIS
         I.col.t = t;
@@ -1751,6 +1764,7 @@ int coop_server_create(coop_rt* rt, const coop_graph* const* graphs, uint32_t ng
             D.bfs.alpha = 14;
             D.bfs.beta = 24;
             D.bfs.total_arcs = g->arcs;
+            D.bfs.col_bu = g->col_bu;
             D.sssp.t = t;
             for (int k = 0; k < 3; ++k) D.sssp.fb[k] = D.bfs.fb[k];
             D.sssp.lowered = reinterpret_cast<uint32_t*>(st + 4 * wb);

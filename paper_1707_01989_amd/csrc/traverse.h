@@ -414,6 +414,31 @@ struct BfsTopDown {
 // plain stores (no other wave owns them).
 constexpr uint32_t kLaneRounds = 8;
 
+// One bottom-up probe: the aligned 16 bytes of the probe-order columns that
+// hold arc k, i.e. arcs (k & ~3) .. (k & ~3) + 3 (the copy is 16-byte
+// aligned and padded, so the load never leaves it); a lane tests the ones
+// in [k, e). One load instruction per probe, one cache line per lane.
+__device__ __forceinline__ uint4 probe_chunk(const uint32_t* __restrict__ col_bu, uint32_t k) {
+    return *reinterpret_cast<const uint4*>(col_bu + (k & ~3u));
+}
+
+// Whether arcs max(k, k & ~3) .. min(e, (k & ~3) + 4) - 1 of chunk q reach
+// the frontier `cur`; `got` = how many arcs that was.
+__device__ __forceinline__ bool probe_hits(const uint32_t* __restrict__ cur, uint4 q, uint32_t k, uint32_t e,
+                                          uint32_t& got) {
+    const uint32_t b0 = k & ~3u;
+    const uint32_t end = e < b0 + 4 ? e : b0 + 4;
+    got = end - k;
+    const uint32_t u[4] = {q.x, q.y, q.z, q.w};
+    bool hit = false;
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) {
+        const uint32_t a = b0 + j;
+        if (a >= k && a < end) hit |= ((cur[u[j] >> 5] >> (u[j] & 31)) & 1u) != 0;
+    }
+    return hit;
+}
+
 // (`word0`: the block's first bitmap word; fw holds the block's found bits)
 __device__ __forceinline__ void bu_mark(const BfsArgs& p, uint32_t* fw, uint32_t* level, uint32_t v,
                                         uint32_t next_level, uint32_t word0, uint32_t deg, Stats& st) {
@@ -424,7 +449,7 @@ __device__ __forceinline__ void bu_mark(const BfsArgs& p, uint32_t* fw, uint32_t
 }
 
 // Scan the deferred long lists with the whole wave, one candidate at a time,
-// 256 arcs per step, from where the lane left off (kLaneRounds x 4 arcs in).
+// 256 arcs per step, from where the lane left off.
 __device__ void bu_scan_long(const BfsArgs& p, WaveLds& wl, const uint32_t* cur, uint32_t* fw, uint32_t* level,
                              uint32_t next_level, uint32_t word0, uint32_t nlong, Stats& st) {
     const uint32_t l = lane_id();
@@ -432,12 +457,14 @@ __device__ void bu_scan_long(const BfsArgs& p, WaveLds& wl, const uint32_t* cur,
         const uint32_t vv = wl.lng[i];
         const uint32_t a0 = p.t.row_ptr[vv], a1 = p.t.row_ptr[vv + 1];
         bool found = false;
-        for (uint32_t kk = a0 + 4 * kLaneRounds; kk < a1 && !found; kk += 4 * kWave) {
+        // a lane's probes are aligned 4-arc chunks: after kLaneRounds of
+        // them it stopped at (a0 & ~3) + 4 kLaneRounds
+        for (uint32_t kk = (a0 & ~3u) + 4 * kLaneRounds; kk < a1 && !found; kk += 4 * kWave) {
             uint32_t u[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const uint32_t a = kk + j * kWave + l;
-                u[j] = a < a1 ? p.t.col[a] : 0xFFFFFFFFu;
+                u[j] = a < a1 ? p.col_bu[a] : 0xFFFFFFFFu;
             }
             bool h = false;
 #pragma unroll
@@ -502,21 +529,15 @@ __device__ void bfs_bottom_up(const BfsArgs& p, WaveLds& wl, const uint32_t* cur
                 }
             }
             if (!__ballot(act[0] || act[1])) break;
-            uint32_t u[2][4];
+            uint4 q[2];
 #pragma unroll
-            for (int c = 0; c < 2; ++c)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    u[c][j] = (act[c] && k[c] + j < e[c]) ? p.t.col[k[c] + j] : 0xFFFFFFFFu;
+            for (int c = 0; c < 2; ++c) q[c] = act[c] ? probe_chunk(p.col_bu, k[c]) : make_uint4(0, 0, 0, 0);
             bool defer[2] = {false, false};
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 if (!act[c]) continue;
-                bool hit = false;
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (u[c][j] != 0xFFFFFFFFu) hit |= ((cur[u[c][j] >> 5] >> (u[c][j] & 31)) & 1u) != 0;
-                const uint32_t got = e[c] - k[c] < 4 ? e[c] - k[c] : 4u;
+                uint32_t got;
+                const bool hit = probe_hits(cur, q[c], k[c], e[c], got);
                 st.arcs += got;
                 k[c] += got;
                 rounds[c] += 1;
@@ -622,21 +643,15 @@ __device__ void bfs_bottom_up_rp(const BfsArgs& p, WaveLds& wl, const uint32_t* 
                 }
             }
             if (!__ballot(act[0] || act[1])) break;
-            uint32_t u[2][4];
+            uint4 q[2];
 #pragma unroll
-            for (int c = 0; c < 2; ++c)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    u[c][j] = (act[c] && k[c] + j < e[c]) ? p.t.col[k[c] + j] : 0xFFFFFFFFu;
+            for (int c = 0; c < 2; ++c) q[c] = act[c] ? probe_chunk(p.col_bu, k[c]) : make_uint4(0, 0, 0, 0);
             bool defer[2] = {false, false};
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 if (!act[c]) continue;
-                bool hit = false;
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (u[c][j] != 0xFFFFFFFFu) hit |= ((cur[u[c][j] >> 5] >> (u[c][j] & 31)) & 1u) != 0;
-                const uint32_t got = e[c] - k[c] < 4 ? e[c] - k[c] : 4u;
+                uint32_t got;
+                const bool hit = probe_hits(cur, q[c], k[c], e[c], got);
                 st.arcs += got;
                 k[c] += got;
                 rounds[c] += 1;
