@@ -523,7 +523,7 @@ def batch_leg(rt, coop, gg, np, torch, stream):
                 reached = o["level"].cpu().numpy().view(np.uint32) != 0xFFFFFFFF
                 bfs_edges += float(g.degrees()[reached].sum()) / 2
         ta = time.time()
-        best, best_ms, def_ms = coop.coop_batch_autotune(rt.rt, items, stride=4, reps=3, opts=copts)
+        best, best_ms, def_ms = coop.coop_batch_autotune(rt.rt, items, stride=1, reps=3, opts=copts)
         tune_s = time.time() - ta
         res = {}
         for tname, tune in (("default", None), ("tuned", best)):
@@ -537,8 +537,8 @@ def batch_leg(rt, coop, gg, np, torch, stream):
         out[name] = {"ms_default": round(res["default"], 3), "ms_tuned": round(res["tuned"], 3),
                      "speedup_tuned": round(res["default"] / res["tuned"], 4),
                      "tuned": best.as_dict(), "tune_seconds": round(tune_s, 1),
-                     "subset_ms_default": round(def_ms, 3) if def_ms > 0 else None,
-                     "subset_ms_tuned": round(best_ms, 3)}
+                     "search_ms_default": round(def_ms, 3) if def_ms > 0 else None,
+                     "search_ms_tuned": round(best_ms, 3)}
         if name == "bfs":
             out[name]["gteps_default"] = round(bfs_edges / (res["default"] * 1e-3) / 1e9, 3)
             out[name]["gteps_tuned"] = round(bfs_edges / (res["tuned"] * 1e-3) / 1e9, 3)

@@ -439,9 +439,12 @@ int coop_batch_run(coop_rt* rt, const coop_batch_item* items, uint32_t count, co
  * taken if it is 2% faster. The result is cached, keyed by the device model
  * and the batch's shape (count, sum of n, sum of arcs, largest instance,
  * the union of the items' ops, the launch mode); a later call with the same
- * key returns the cached tune without timing (default_ms = -1). Outputs of
- * the subset are overwritten. best_ms (nullable) gets the winner's time on
- * the subset, default_ms (nullable) the default tune's. Not part of the
+ * key returns the cached tune without timing (default_ms = -1). With a
+ * subset (stride > 1) the winner is timed once more on the whole batch
+ * against the default tune and kept only if it is 2% faster there, so the
+ * result is never a schedule that only suits the smaller subset; best_ms
+ * and default_ms (nullable) are then the whole batch's times, else the
+ * subset's. Outputs of the timed items are overwritten. Not part of the
  * method of the paper: it picks the schedule of the batched launch. */
 int coop_batch_autotune(coop_rt* rt, const coop_batch_item* items, uint32_t count, uint32_t stride,
                         uint32_t reps, const coop_launch_opts* opts, coop_stream_t stream, coop_tune* best,

@@ -1348,11 +1348,11 @@ int coop_batch_autotune(coop_rt* rt, const coop_batch_item* items, uint32_t coun
     std::vector<coop_batch_item> sub;
     for (uint32_t i = 0; i < count; i += stride) sub.push_back(items[i]);
     int err = COOP_OK;
-    auto time_it = [&](const coop_tune& t) -> double {
+    auto time_on = [&](const coop_batch_item* its, uint32_t n_its, const coop_tune& t) -> double {
         std::vector<double> ms;
         for (uint32_t r = 0; r < reps; ++r) {
             coop_handle* h = nullptr;
-            int rc = coop_batch_run(rt, sub.data(), (uint32_t)sub.size(), &t, opts, stream, &h);
+            int rc = coop_batch_run(rt, its, n_its, &t, opts, stream, &h);
             coop_stats st{};
             if (rc == COOP_OK) rc = coop_wait(h, &st);
             if (rc != COOP_OK) {
@@ -1363,11 +1363,12 @@ int coop_batch_autotune(coop_rt* rt, const coop_batch_item* items, uint32_t coun
         }
         return percentile(ms, 0.5);
     };
+    auto time_it = [&](const coop_tune& t) { return time_on(sub.data(), (uint32_t)sub.size(), t); };
     coop_tune cur;
     coop_tune_default(&cur);
     double cur_ms = time_it(cur);
     if (err) return err;
-    const double def_ms = cur_ms;
+    double def_ms = cur_ms;
     // coordinate search, two passes: group size, workgroup count (as a share
     // of the resident workgroups), team work, team cap, BFS direction rule,
     // heavy-vertex threshold and strip; a candidate must beat the current
@@ -1425,6 +1426,22 @@ int coop_batch_autotune(coop_rt* rt, const coop_batch_item* items, uint32_t coun
         }
     }
     if (err) return err;
+    if (stride > 1) {
+        // the subset has a fraction of the batch's work, so settings sized
+        // to the work (workgroup count, team cap) can win there and lose on
+        // the batch: the winner must also beat the default on the batch
+        coop_tune dflt;
+        coop_tune_default(&dflt);
+        def_ms = time_on(items, count, dflt);
+        const double won = err ? 1e30 : time_on(items, count, cur);
+        if (err) return err;
+        if (won < def_ms * 0.98) {
+            cur_ms = won;
+        } else {
+            cur = dflt;
+            cur_ms = def_ms;
+        }
+    }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache[key] = std::make_pair(cur, cur_ms);
