@@ -135,7 +135,8 @@ struct alignas(256) CtxCore {
     uint32_t join_tail;       // next joiner slot
     uint32_t join_full;       // joiners that found the admission ring full and left
     uint32_t joined_grid;     // workgroups of joiner grids that started
-    uint32_t _pj[60];
+    uint32_t cohort;          // tickets the first barrier admitted as ids 0 .. cohort-1
+    uint32_t _pj[59];
     // ---- line: error and the host target as read by workgroup 0
     int32_t error;
     uint32_t T_seen;
@@ -295,6 +296,7 @@ struct BarrierLds {
     uint32_t drain_span, drained;      // ring slots checked for given-up joiners, and how many lead
     uint32_t offers;                   // task pattern: offer_kill calls so far (thread 0)
     uint32_t cut, tail_prev;           // admission: slots taken before the first new unannounced one
+    uint32_t m0;                       // members before this barrier's forks (the start-up admission's count)
     uint32_t valid[kMaxGroups / 32];   // admission: ring slots whose joiner was still waiting
     uint32_t xcnt[kMaxEngines];        // placed kill: members per engine, then victims per engine
     uint32_t wsum[kMaxWaves + 1];      // placed kill: survivors per wave of ids
@@ -451,10 +453,13 @@ __device__ inline Member join_queue(Ctx* c, const Cfg cfg) {
 }
 
 // Registration (thread 0 only). In a plain launch the workgroup id is the
-// block id and M is the grid size. In a cooperative launch ticket 0 becomes
-// logical 0 (M starts at 1); everybody else -- late-dispatched workgroups,
-// workgroups of a joiner grid, killed workgroups re-queued in park mode --
-// waits in the joiner queue.
+// block id and M is the grid size. In a cooperative launch the launch's own
+// workgroups draw tickets: ticket 0 becomes logical 0 (M starts at 1), and
+// every later ticket waits for the first release, whose master step admits
+// the tickets drawn before it as ids 0 .. cohort-1 (the start-up admission:
+// the Fork rule with the ids given in ticket order, no joiner ring and no
+// host reads). A later ticket, a workgroup of a joiner grid and a killed
+// workgroup re-queued in park mode wait in the joiner queue.
 __device__ inline Member register_member(Ctx* c, const Cfg cfg, bool plain, bool joiner_grid) {
     Member m{};
     if (plain) {
@@ -473,6 +478,23 @@ __device__ inline Member register_member(Ctx* c, const Cfg cfg, bool plain, bool
             st_relaxed(&c->engine_of[0], engine_id(cfg.ses));
             return m;
         }
+        const uint64_t r = wait_release(c, cfg, 0u);
+        fence_acquire();
+        if (rel_flags(r) & (kFlagAbort | kFlagDone)) {
+            m.alive = 0;
+            return m;
+        }
+        if (t < ld_relaxed(&c->cohort)) {
+            // admitted at the first barrier, which cannot release the next
+            // one without this member: r is that first release
+            m.id = t;
+            m.M = rel_M(r);
+            m.epoch = rel_epoch(r);
+            m.flags = rel_flags(r);
+            m.alive = 1;
+            st_relaxed(&c->engine_of[t], engine_id(cfg.ses));
+            return m;
+        }
     } else {
         add_relaxed(&c->joined_grid, 1u);
     }
@@ -480,10 +502,10 @@ __device__ inline Member register_member(Ctx* c, const Cfg cfg, bool plain, bool
 }
 
 // Start-up: in a cooperative launch ticket 0 waits briefly for the rest of
-// the grid to register, so the first barrier can admit them together.
+// the grid to draw tickets, so the first barrier can admit them together.
 __device__ inline void startup_wait(Ctx* c, const Cfg cfg) {
     const uint64_t t0 = now_ticks();
-    while (ld_relaxed(&c->join_tail) + 1 < gridDim.x && now_ticks() - t0 < cfg.epoch0_wait)
+    while (ld_relaxed(&c->ticket) < gridDim.x && now_ticks() - t0 < cfg.epoch0_wait)
         __builtin_amdgcn_s_sleep(2);
 }
 
@@ -552,16 +574,28 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
             if (cfg.mode & kModeRandomSched) {
                 const uint64_t h = splitmix64(cfg.sched_seed + (uint64_t)ne * 0x9E3779B97F4A7C15ull);
                 if ((uint32_t)(h & 0xFFFFu) < cfg.sched_p16) T_dev = 1u + (uint32_t)((h >> 16) % cfg.N);
-                T = T_dev;
+                T = T_dev ? T_dev : cfg.N;      // no draw yet: nothing competes
             } else if (cfg.host) {
                 T = T_seen;
             }
             if (T < 1u) T = 1u;
             if (T > cfg.N) T = cfg.N;
         }
+        // start-up admission (the first barrier of a cooperative launch):
+        // the launch's tickets drawn so far, at most the target, become ids
+        // 0 .. M0-1 (the members before this barrier's forks); each reads
+        // M0 after the release
+        uint32_t M0 = m.M;
+        if (live && m.epoch == 0) {
+            const uint32_t drawn = ld_relaxed(&c->ticket);
+            M0 = drawn < T ? drawn : T;
+            if (M0 < 1u) M0 = 1u;
+            st_relaxed(&c->cohort, M0);
+        }
+        b.m0 = M0;
         const uint32_t ready = tail - join_head;
-        const uint32_t room = cfg.N - m.M;
-        const uint32_t want = T > m.M ? T - m.M : 0u;
+        const uint32_t room = cfg.N - M0;
+        const uint32_t want = T > M0 ? T - M0 : 0u;
         uint32_t kmax = live ? ready : 0u;
         kmax = kmax < room ? kmax : room;
         kmax = kmax < want ? kmax : want;
@@ -587,6 +621,7 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
     // read it unsynchronised split its barriers between the threads that saw
     // DONE there and thread 0, and miscounted the arrivals)
     __syncthreads();
+    const uint32_t M0 = b.m0;
     uint32_t admitted = 0;
     if constexpr (Coop) {
         const uint32_t kmax = b.kmax, head = b.head;
@@ -624,7 +659,7 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
             // fork: admit ring slots head .. head+kcut-1 as ids M .. M+kcut-1
             for (uint32_t j = threadIdx.x; j < kcut; j += blockDim.x) {
                 const uint32_t slot = head + j;
-                if (ring_admit(&c->join_entry[slot % kJoinCap], slot, ne, m.M + j))
+                if (ring_admit(&c->join_entry[slot % kJoinCap], slot, ne, M0 + j))
                     atomicOr(&b.valid[j / 32], 1u << (j % 32));
             }
             __syncthreads();
@@ -637,7 +672,7 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
                 for (uint32_t q = 0; q < wj; ++q) rank += __popc(b.valid[q]);
                 if (rank != j) {
                     const uint32_t slot = head + j;
-                    __hip_atomic_store(&c->join_entry[slot % kJoinCap], admit_entry(slot, ne, m.M + rank),
+                    __hip_atomic_store(&c->join_entry[slot % kJoinCap], admit_entry(slot, ne, M0 + rank),
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
@@ -650,7 +685,7 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
     uint32_t W = 0;
     if constexpr (Coop) {
         if (!(b.flags & (kFlagDone | kFlagAbort))) {
-            const uint32_t M2 = m.M + admitted;
+            const uint32_t M2 = M0 + admitted;
             W = M2 > b.T ? M2 - b.T : 0u;
             if (W > M2 - 1) W = M2 - 1;
             // the regular barrier (section 4.2): one offer_kill per arrival,
@@ -673,7 +708,7 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
     if constexpr (Coop) {
         if (W && cfg.host && !(cfg.mode & kModeRandomSched) && cfg.engines > 1 && cfg.engines <= kMaxEngines) {
             renum = true;
-            const uint32_t M2 = m.M + admitted;
+            const uint32_t M2 = M0 + admitted;
             for (uint32_t t = threadIdx.x; t < M2; t += blockDim.x) b.xcd[t] = (uint8_t)ld_relaxed(&c->engine_of[t]);
             if (threadIdx.x < kMaxEngines) b.xcnt[threadIdx.x] = 0;
             __syncthreads();
@@ -738,9 +773,9 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
     // XCD yet, so the next interval arrives per workgroup (kFlagFlat)
     if constexpr (kGroupedArrival<C>) {
         const bool over = (b.flags & (kFlagDone | kFlagAbort)) != 0;
-        const uint32_t M2 = m.M + admitted;
+        const uint32_t M2 = M0 + admitted;
         const uint32_t Mn = renum ? Mn_sel : M2 - W;
-        if (!over && admitted == 0 && (m.epoch == 0 || (m.flags & kFlagFlat) || Mn != m.M || renum)) {
+        if (!over && admitted == 0 && M0 == m.M && (m.epoch == 0 || (m.flags & kFlagFlat) || Mn != m.M || renum)) {
             if (threadIdx.x < kMaxXcds) b.xcnt[threadIdx.x] = 0;
             __syncthreads();
             if (renum) {
@@ -766,16 +801,19 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
     if (threadIdx.x == 0) {
         // `flags` is still the value thread 0 shared as b.flags
         uint32_t Mn = m.M;
-        if (kGroupedArrival<C> && !(flags & (kFlagDone | kFlagAbort)) && admitted) flags |= kFlagFlat;
+        // newcomers (admitted or started up here) have not recorded their
+        // XCD yet: the next interval arrives per workgroup
+        const uint32_t newcomers = admitted + (M0 - m.M);
+        if (kGroupedArrival<C> && !(flags & (kFlagDone | kFlagAbort)) && newcomers) flags |= kFlagFlat;
         if (Coop && !(flags & (kFlagDone | kFlagAbort))) {
-            const uint32_t M2 = m.M + admitted;
+            const uint32_t M2 = M0 + admitted;
             const uint32_t Wk = renum ? M2 - Mn_sel : W;
             Mn = M2 - Wk;
             if (renum) flags |= kFlagRenum;
             if (kmax0) st_relaxed(&c->join_head, head0 + b.cut);
             else if (drain0 && b.drained) st_relaxed(&c->join_head, head0 + b.drained);
             if (cfg.mode & kModeRandomSched) c->T_dev = T_dev;
-            if (admitted) c->forks = forks + admitted;
+            if (newcomers) c->forks = forks + newcomers;
             if (Wk) c->kills = kills + Wk;
             if (Mn != m.M) c->resizes = resizes + 1;
             if (Mn < min_M) c->min_M = Mn;

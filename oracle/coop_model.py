@@ -48,8 +48,8 @@ from typing import Dict, List, Optional, Sequence, Tuple
 INF = 0xFFFFFFFF
 
 # workgroup program counters
-UNSTARTED, WORK, PROC, ARRIVE, WAIT, POST, JWAIT, EXITED = range(8)
-PC_NAMES = ["UNSTARTED", "WORK", "PROC", "ARRIVE", "WAIT", "POST", "JWAIT", "EXITED"]
+UNSTARTED, WORK, PROC, ARRIVE, WAIT, POST, JWAIT, EXITED, COHORT = range(9)
+PC_NAMES = ["UNSTARTED", "WORK", "PROC", "ARRIVE", "WAIT", "POST", "JWAIT", "EXITED", "COHORT"]
 
 
 @dataclass(frozen=True)
@@ -63,6 +63,8 @@ class WG:
     joinslot: int = -1     # position in the joiner queue
     mseen: int = 0         # active count read together with `seen`
     rn: bool = False       # the observed release renumbered: read the new id
+    grid: bool = True      # one of the launch's own workgroups (else of a joiner grid)
+    ticket: int = -1       # start-up ticket (launch's own workgroups)
 
 
 @dataclass(frozen=True)
@@ -86,6 +88,7 @@ class State:
     joiners_left: int               # remaining joiner workgroups the host may launch
     renum: Tuple[Tuple[int, int], ...] = ()    # per old id: (epoch, new id or -1)
     renum_epoch: int = -1           # epoch whose release carried a renumbering
+    cohort: int = 0                 # tickets the first barrier admitted as ids 0 .. cohort-1
 
 
 class ModelError(AssertionError):
@@ -137,7 +140,7 @@ class Model:
                 if t != s.T:
                     out.append((f"T={t}", _replace(s, T=t, t_changes=s.t_changes - 1)))
         if s.joiners_left > 0:
-            out.append(("launch-joiner", _replace(s, wgs=s.wgs + (WG(),),
+            out.append(("launch-joiner", _replace(s, wgs=s.wgs + (WG(grid=False),),
                                                    joiners_left=s.joiners_left - 1)))
         return out
 
@@ -152,15 +155,33 @@ class Model:
     def _step_wg(self, s: State, i: int, w: WG) -> Optional[State]:
         pc = w.pc
         if pc == UNSTARTED:
-            # registration: ticket 0 is logical workgroup 0 (M starts at 1);
-            # every later workgroup is a joiner, admitted at a barrier.
+            # registration: the launch's own workgroups draw tickets; ticket
+            # 0 is logical workgroup 0 (M starts at 1) and every later ticket
+            # waits for the first release, whose master admitted the tickets
+            # drawn before it as ids 0 .. cohort-1 (start-up admission); a
+            # later ticket, and every workgroup of a joiner grid, is a
+            # joiner, admitted at a barrier.
             if s.done:
                 return self._set(s, i, _w(w, pc=EXITED))
+            if not w.grid:
+                return self._set(s, i, _w(w, pc=JWAIT, joinslot=len(s.joinq)), joinq=s.joinq + (i,))
             if s.tickets == 0:
-                return self._set(s, i, _w(w, pc=WORK, logical=0, seen=s.epoch, level=s.level),
+                return self._set(s, i, _w(w, pc=WORK, logical=0, seen=s.epoch, level=s.level, ticket=0),
                                  tickets=1)
-            return self._set(s, i, _w(w, pc=JWAIT, joinslot=len(s.joinq)),
-                             tickets=s.tickets + 1, joinq=s.joinq + (i,))
+            return self._set(s, i, _w(w, pc=COHORT, ticket=s.tickets), tickets=s.tickets + 1)
+        if pc == COHORT:
+            if s.done:
+                return self._set(s, i, _w(w, pc=EXITED))
+            if s.epoch == 0:
+                return None             # waiting for the first release
+            if w.ticket < s.cohort:
+                # a member of the first interval: the next barrier needs it,
+                # so the first release is the one it sees
+                if s.epoch != 1:
+                    raise ModelError(f"start-up member saw epoch {s.epoch}")
+                return self._set(s, i, _w(w, pc=POST, logical=w.ticket, seen=s.epoch, mseen=s.Mnew,
+                                          level=s.level))
+            return self._set(s, i, _w(w, pc=JWAIT, joinslot=len(s.joinq)), joinq=s.joinq + (i,))
         if pc == JWAIT:
             if s.done:
                 return self._set(s, i, _w(w, pc=EXITED))
@@ -236,6 +257,12 @@ class Model:
         frontier = s.out
         level = s.level + 1
         done = len(frontier) == 0
+        # start-up admission (first barrier only): the tickets drawn so far,
+        # at most the target, become ids 0 .. cohort-1
+        cohort = s.cohort
+        if s.epoch == 0 and not done:
+            cohort = max(1, min(s.tickets, self.N, s.T))
+            M = cohort
         # fork: k in [0, N - M], bounded by waiting joiners and the target
         k = 0 if done else min(len(s.joinq), self.N - M, max(0, s.T - M))
         # admission records persist (tagged with their epoch) so a slow
@@ -253,7 +280,7 @@ class Model:
             raise ModelError("a barrier that admits joiners also kills")
         ne = s.epoch + 1
         base = dict(frontier=frontier, out=(), claim=0, level=level, done=done, arrive=0, M=Mnew,
-                    Mnew=Mnew, epoch=ne, joinq=joinq, admitted=admitted)
+                    Mnew=Mnew, epoch=ne, joinq=joinq, admitted=admitted, cohort=cohort)
         if self.victims == "top" or W == 0:
             s2 = _replace(s, **base)
             return [self._set(s2, i, _w(w, pc=POST, seen=ne, mseen=Mnew, level=level, rn=False))]

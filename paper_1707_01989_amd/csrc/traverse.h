@@ -117,6 +117,7 @@ struct BlockLds {
     uint32_t wave_base[kMaxWaves];
     uint64_t acc[8];            // per-workgroup statistics of the phase
     uint64_t red[8][kMaxWaves]; // master reductions
+    uint32_t mb[4];             // master step: values thread 0 shares with the workgroup
     WaveLds wave[kMaxWaves];
 };
 
@@ -783,6 +784,105 @@ __device__ __forceinline__ void bfs_phase(const BfsArgs& p, BlockLds& sh, uint32
     }
 }
 
+// Start source x.root() in the master step (all threads of the master
+// workgroup; `x` is thread 0's): the source gets level 0, and when its list
+// has at most one arc per thread the workgroup expands it at once -- every
+// neighbour claimed on the visited bitmap gets level 1 and a bit in the
+// next frontier -- so the source needs no top-down phase (and barrier) for
+// level 0. The marks are atomics, as every later claim of the same words is.
+// Returns the release flags (thread 0).
+__device__ uint32_t bfs_master_source(const BfsArgs& p, BlockLds& sh, CtxCore* c, XferR& x, const uint32_t* roots,
+                                      uint32_t* lvl_base) {
+    const TraversalArgs& t = p.t;
+    if (threadIdx.x == 0) {
+        const uint32_t src = roots[x.root()];
+        uint32_t a0 = 0, deg = 0;
+        if (src < t.n) {
+            a0 = t.row_ptr[src];
+            deg = t.row_ptr[src + 1] - a0;
+            uint32_t* lv = lvl_base + (size_t)x.root() * t.out_stride;
+            __builtin_nontemporal_store(0u, &lv[src]);
+            atomicOr(&p.vis[src >> 5], 1u << (src & 31));
+            atomicOr(&p.fb[0][src >> 5], 1u << (src & 31));
+        }
+        sh.mb[0] = src;
+        sh.mb[1] = a0;
+        sh.mb[2] = deg;
+        sh.mb[3] = x.root();
+    }
+    __syncthreads();
+    const uint32_t src = sh.mb[0], a0 = sh.mb[1], deg = sh.mb[2];
+    if (src >= t.n) {
+        // a source outside the graph ends the launch before anything is
+        // written for it (earlier sources are complete)
+        if (threadIdx.x == 0) raise_error(c, kErrInvalid);
+        return kFlagAbort;
+    }
+    const bool inline_l0 = deg <= blockDim.x;
+    uint64_t found = 0, mf = 0;
+    if (inline_l0) {
+        uint32_t* lv = lvl_base + (size_t)sh.mb[3] * t.out_stride;
+        if (threadIdx.x < deg) {
+            const uint32_t u = t.col[a0 + threadIdx.x];
+            const uint32_t bit = 1u << (u & 31);
+            if (!(atomicOr(&p.vis[u >> 5], bit) & bit)) {
+                __builtin_nontemporal_store(1u, &lv[u]);
+                atomicOr(&p.fb[1][u >> 5], bit);
+                found = 1;
+                mf = t.row_ptr[u + 1] - t.row_ptr[u];
+            }
+        }
+        const uint64_t wf = wave_sum64(found), wm = wave_sum64(mf);
+        if (lane_id() == 0) {
+            sh.red[0][wave_id()] = wf;
+            sh.red[1][wave_id()] = wm;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            found = mf = 0;
+            for (uint32_t w = 0; w < num_waves(); ++w) {
+                found += sh.red[0][w];
+                mf += sh.red[1][w];
+            }
+        }
+    }
+    uint32_t res = 0;
+    if (threadIdx.x == 0) {
+        x.level() = 0;
+        x.nf_prev() = 1;
+        x.m_visited_lo() = deg;
+        x.m_visited_hi() = 0;
+        x.lvl_found() = 0;
+        x.lvl_mf_lo() = x.lvl_mf_hi() = 0;
+        t.work->heavy_tail = 0;
+        if (!inline_l0) {
+            res = kPhTD;                        // rotation 0: current = fb[0]
+        } else {
+            x.levels_total() += 1;
+            x.td_levels() += 1;
+            // the level's work in the cumulative statistics (slot of id 0)
+            uint64_t* s0 = reinterpret_cast<uint64_t*>(t.slots);
+            add_nr64(&s0[kSlotArcs], deg);
+            add_nr64(&s0[kSlotRows], 1 + found);
+            if (found) add_nr64(&s0[kSlotFoundAll], found);
+            if (found == 0) {
+                x.root() += 1;
+                res = x.root() >= t.nroots ? kFlagDone : (kPhInit | kFlagAdv);
+            } else {
+                const uint64_t mv = (uint64_t)deg + mf;
+                x.m_visited_lo() = (uint32_t)mv;
+                x.m_visited_hi() = (uint32_t)(mv >> 32);
+                const uint64_t m_u = p.total_arcs > mv ? p.total_arcs - mv : 0;
+                const uint32_t nph = (p.direction_opt && mf * p.alpha > m_u) ? kPhBU : kPhTD;
+                x.nf_prev() = (uint32_t)found;
+                x.level() = 1;
+                res = nph | kFlagAdv | (1u << kRotShift);   // level 1: current = fb[1]
+            }
+        }
+    }
+    return res;
+}
+
 // BFS master step (all threads of the master workgroup): per-level
 // bookkeeping, HEAVY follow-up, direction of the next level (Beamer's
 // alpha/beta rule), next source or done. `roots` / `lvl_base`: the sources
@@ -802,33 +902,21 @@ __device__ __forceinline__ uint32_t bfs_master(const BfsArgs& p, BlockLds& sh, C
     }
     uint64_t tot[2];
     master_sum_slots(sh, t.slots, t.N, tot);
+    if (ph == kPhInit) {
+        const uint32_t res = bfs_master_source(p, sh, c, x, roots, lvl_base);
+        if (threadIdx.x == 0) {
+            wk->store_x(x);
+            sh.bar.flags = res;
+        }
+        __syncthreads();
+        return sh.bar.flags;
+    }
     if (threadIdx.x == 0) {
         uint32_t res = 0;
         const uint32_t r = (cur_flags & kRotMask) >> kRotShift;
         if (ph == kPhStart) {
             x.root() = 0;
             res = kPhInit;
-        } else if (ph == kPhInit) {
-            const uint32_t src = roots[x.root()];
-            if (src >= t.n) {
-                // a source outside the graph ends the launch before anything
-                // is written for it (earlier sources are complete)
-                raise_error(c, kErrInvalid);
-                res = kFlagAbort;
-            } else {
-                uint32_t* lv = lvl_base + (size_t)x.root() * t.out_stride;
-                __builtin_nontemporal_store(0u, &lv[src]);
-                p.vis[src >> 5] |= 1u << (src & 31);
-                p.fb[0][src >> 5] |= 1u << (src & 31);
-                x.level() = 0;
-                x.nf_prev() = 1;
-                x.m_visited_lo() = t.row_ptr[src + 1] - t.row_ptr[src];
-                x.m_visited_hi() = 0;
-                x.lvl_found() = 0;
-                x.lvl_mf_lo() = x.lvl_mf_hi() = 0;
-                wk->heavy_tail = 0;
-                res = kPhTD;                    // rotation 0: current = fb[0]
-            }
         } else {
             // level partials (a TD level may be followed by a HEAVY phase)
             const uint64_t mf_lvl = join64(x.lvl_mf_lo(), x.lvl_mf_hi()) + tot[1];
@@ -887,7 +975,7 @@ __device__ __forceinline__ void bfs_follow(uint32_t ph, uint32_t nflags, uint32_
         if (ph != kPhStart) root += 1;
         level = 0;
     } else if (ph == kPhInit) {
-        level = 0;
+        level = (nflags & kFlagAdv) ? 1u : 0u;   // ADV: the master step expanded level 0 itself
     } else if (nflags & kFlagAdv) {
         level += 1;
     }

@@ -189,3 +189,41 @@ def test_model_scripted_victim_reads_stale_entry():
     # the planted mistake: it takes that entry as its new id (a duplicate)
     with pytest.raises(cm.ModelError):
         _scripted(ReadsAnyRenumEntry(P8, 0, 3, **kw))
+
+
+class CohortRecorder(cm.Model):
+    """Records the largest start-up admission the search reaches."""
+    largest = 0
+
+    def check(self, s):
+        CohortRecorder.largest = max(CohortRecorder.largest, s.cohort)
+        super().check(s)
+
+
+def test_startup_admission_is_explored():
+    """The first barrier admits every ticket drawn before it (ids 0 ..
+    cohort-1); the search reaches admissions of the whole launch."""
+    CohortRecorder.largest = 0
+    m = CohortRecorder(STAR4, 0, 3, t_changes=1, joiners=1, park_killed=False)
+    r = cm.explore(m, max_states=400_000)
+    assert r.outputs == {BFS["star4"]}
+    assert CohortRecorder.largest == 3
+
+
+class CohortIgnoresBound(cm.Model):
+    """A planted mistake: a start-up workgroup takes its ticket as its id
+    even when the first barrier did not admit it (ticket >= cohort)."""
+
+    def _step_wg(self, s, i, w):
+        if w.pc == cm.COHORT and s.epoch >= 1 and w.ticket >= s.cohort and not s.done:
+            return self._set(s, i, cm._w(w, pc=cm.POST, logical=w.ticket, seen=s.epoch, mseen=s.Mnew,
+                                         level=s.level))
+        return super()._step_wg(s, i, w)
+
+
+def test_model_catches_startup_member_beyond_admission():
+    # a ticket drawn after the first barrier would share its id with the
+    # joiner-grid workgroup admitted there
+    m = CohortIgnoresBound(PATH4, 0, 3, t_changes=1, joiners=1, park_killed=False)
+    with pytest.raises(cm.ModelError):
+        cm.explore(m, max_states=400_000)
