@@ -136,7 +136,9 @@ typedef struct coop_launch_opts {
                                  start, work done, barrier arrival, release seen; NULL = off */
     uint32_t bu_alpha;        /* BFS direction rule (Beamer et al.): a top-down level is followed
                                  by a bottom-up one when its frontier's arcs x alpha exceed the
-                                 arcs not yet visited; 0 = 14 */
+                                 arcs not yet visited; 0 = 48 (Beamer et al. use 14 on CPUs;
+                                 a top-down claim here is a random atomic, so bottom-up pays
+                                 off sooner) */
     uint32_t bu_beta;         /* ... and a bottom-up level by a top-down one when the frontier x
                                  beta is below n and shrinking; 0 = 24 */
 } coop_launch_opts;

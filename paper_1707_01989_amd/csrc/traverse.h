@@ -57,6 +57,7 @@ constexpr uint32_t kFlagAdv = 1u << 9;            // this barrier advanced the l
 constexpr uint32_t kRotShift = 10;                // BFS: frontier bitmap rotation (0..2)
 constexpr uint32_t kRotMask = 3u << kRotShift;
 constexpr uint32_t kFlagEnd = 1u << 12;           // a served query finished (the team goes on)
+constexpr uint32_t kFlagPreSplit = 1u << 13;      // BFS top-down: the frontier's heavy vertices are strips already
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 __device__ __forceinline__ uint32_t wave_id() { return threadIdx.x / kWave; }
@@ -287,9 +288,11 @@ __device__ __forceinline__ void walk_strip(WaveLds& w, uint32_t pay0, uint32_t a
 
 // Expand one batch of up to 64 vertices (lane l holds vertex v if `act`):
 // heavy vertices are queued as strips, the rest are walked by this wave.
+// With `queue_heavy` false the heavy vertices are skipped: their strips
+// were queued already (and are walked in the same phase).
 template <class Visit>
 __device__ __forceinline__ void expand_batch(const TraversalArgs& a, Work* wk, WaveLds& w, bool act,
-                                             uint32_t v, Visit& visit, Stats& st) {
+                                             uint32_t v, Visit& visit, Stats& st, bool queue_heavy = true) {
     uint32_t s0 = 0, deg = 0, pay = 0;
     if (act) {
         s0 = a.row_ptr[v];
@@ -298,7 +301,8 @@ __device__ __forceinline__ void expand_batch(const TraversalArgs& a, Work* wk, W
         st.rows += 1;
     }
     const bool heavy = deg > a.heavy_th;
-    const uint64_t hmask = __ballot(heavy);
+    if (!queue_heavy && heavy) deg = 0;
+    const uint64_t hmask = queue_heavy ? __ballot(heavy) : 0ull;
     if (hmask) {
         const uint32_t ns = heavy ? (deg + a.strip - 1) / a.strip : 0u;
         const uint32_t incl = wave_incl_scan(ns);
@@ -698,7 +702,7 @@ __device__ void bfs_bottom_up_rp(const BfsArgs& p, WaveLds& wl, const uint32_t* 
 // expands them 64 vertices per batch.
 template <class Visit>
 __device__ void expand_bitmap(const TraversalArgs& a, Work* wk, WaveLds& w, const uint32_t* cur, uint32_t words,
-                              uint32_t gw, uint32_t W, Visit& vis, Stats& st) {
+                              uint32_t gw, uint32_t W, Visit& vis, Stats& st, bool queue_heavy = true) {
     const uint32_t l = lane_id();
     uint32_t* list = w.out;             // up to 32 x 32 = 1024 vertices
     for (uint32_t k = 0; gw + k * W < words; k += 32) {
@@ -718,15 +722,15 @@ __device__ void expand_bitmap(const TraversalArgs& a, Work* wk, WaveLds& w, cons
         for (uint32_t base = 0; base < total; base += kWave) {
             const uint32_t i = base + l;
             const bool act = i < total;
-            expand_batch(a, wk, w, act, act ? list[i] : 0u, vis, st);
+            expand_batch(a, wk, w, act, act ? list[i] : 0u, vis, st, queue_heavy);
         }
         __builtin_amdgcn_wave_barrier();
     }
 }
 
 __device__ void bfs_top_down(const BfsArgs& p, Work* wk, WaveLds& w, const uint32_t* cur, BfsTopDown& vis,
-                             uint32_t gw, uint32_t W, Stats& st) {
-    expand_bitmap(p.t, wk, w, cur, p.words, gw, W, vis, st);
+                             uint32_t gw, uint32_t W, Stats& st, bool queue_heavy = true) {
+    expand_bitmap(p.t, wk, w, cur, p.words, gw, W, vis, st, queue_heavy);
 }
 
 // Clear a bitmap share: words gw*64 + lane, then + W*64 ...
@@ -768,7 +772,9 @@ __device__ __forceinline__ void bfs_phase(const BfsArgs& p, BlockLds& sh, uint32
         WaveLds& w = sh.wave[wave_id()];
         if (ph == kPhTD) {
             clear_share(spare, p.words, gw, W);
-            bfs_top_down(p, wk, w, cur, vis, gw, W, st);
+            const bool pre = (flags & kFlagPreSplit) != 0;
+            if (pre) heavy_phase(t, wk->x.in_size, gw, W, w, vis, st);   // the master step's strips
+            bfs_top_down(p, wk, w, cur, vis, gw, W, st, !pre);
         } else {
             heavy_phase(t, wk->x.in_size, gw, W, w, vis, st);
         }
@@ -819,7 +825,7 @@ __device__ uint32_t bfs_master_source(const BfsArgs& p, BlockLds& sh, CtxCore* c
         return kFlagAbort;
     }
     const bool inline_l0 = deg <= blockDim.x;
-    uint64_t found = 0, mf = 0;
+    uint64_t found = 0, mf = 0, strips = 0;
     if (inline_l0) {
         uint32_t* lv = lvl_base + (size_t)sh.mb[3] * t.out_stride;
         if (threadIdx.x < deg) {
@@ -829,20 +835,35 @@ __device__ uint32_t bfs_master_source(const BfsArgs& p, BlockLds& sh, CtxCore* c
                 __builtin_nontemporal_store(1u, &lv[u]);
                 atomicOr(&p.fb[1][u >> 5], bit);
                 found = 1;
-                mf = t.row_ptr[u + 1] - t.row_ptr[u];
+                const uint32_t u0 = t.row_ptr[u], du = t.row_ptr[u + 1] - u0;
+                mf = du;
+                if (du > t.heavy_th) {
+                    // a heavy vertex of level 1: its strips are queued now,
+                    // so level 1's own phase walks them (no HEAVY phase)
+                    const uint32_t ns = (du + t.strip - 1) / t.strip;
+                    const uint32_t b = add_relaxed(&t.work->heavy_tail, ns);
+                    for (uint32_t j = 0; j < ns; ++j) {
+                        const uint32_t off = j * t.strip;
+                        if (b + j < t.heavy_cap)
+                            t.heavy[b + j] = make_uint4(0u, u0 + off, du - off < t.strip ? du - off : t.strip, u);
+                    }
+                    strips = ns;
+                }
             }
         }
-        const uint64_t wf = wave_sum64(found), wm = wave_sum64(mf);
+        const uint64_t wf = wave_sum64(found), wm = wave_sum64(mf), ws = wave_sum64(strips);
         if (lane_id() == 0) {
             sh.red[0][wave_id()] = wf;
             sh.red[1][wave_id()] = wm;
+            sh.red[2][wave_id()] = ws;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            found = mf = 0;
+            found = mf = strips = 0;
             for (uint32_t w = 0; w < num_waves(); ++w) {
                 found += sh.red[0][w];
                 mf += sh.red[1][w];
+                strips += sh.red[2][w];
             }
         }
     }
@@ -877,6 +898,16 @@ __device__ uint32_t bfs_master_source(const BfsArgs& p, BlockLds& sh, CtxCore* c
                 x.nf_prev() = (uint32_t)found;
                 x.level() = 1;
                 res = nph | kFlagAdv | (1u << kRotShift);   // level 1: current = fb[1]
+                if (strips) {
+                    // the strips stay queued for a top-down level 1 (a
+                    // bottom-up one does not walk the frontier's lists)
+                    x.in_size() = (uint32_t)strips;
+                    if (nph == kPhTD) res |= kFlagPreSplit;
+                    if (strips > t.heavy_cap) {
+                        raise_error(c, kErrInternal);
+                        res |= kFlagAbort;
+                    }
+                }
             }
         }
     }
