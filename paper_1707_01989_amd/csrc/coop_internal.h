@@ -124,6 +124,8 @@ struct BfsArgs {
     uint32_t bu_prefetch;      // bottom-up levels stage each block's row ranges in LDS
     const uint32_t* col_bu;    // bottom-up probe order: every list by decreasing neighbour degree,
                                // 16-byte aligned and padded by 4 words (the graph's copy)
+    const uint2* first2;       // skewed graphs: per vertex its first two neighbours in probe order
+                               // (0xFFFFFFFF: none); null otherwise
 };
 
 struct SsspArgs {
@@ -374,6 +376,10 @@ hipError_t launch_copy_status(const CtxCore* c, int32_t* out, hipStream_t s);
 // waits for `s`.
 hipError_t build_degree_order(const uint32_t* row_ptr, const uint32_t* col, uint32_t n, uint64_t arcs,
                               uint32_t max_deg, uint32_t* out, hipStream_t s);
+// first2[v] = the first two entries of v's list in `col_bu` (0xFFFFFFFF past
+// its end), n entries; waits for `s`.
+hipError_t build_first_two(const uint32_t* row_ptr, const uint32_t* col_bu, uint32_t n, uint2* first2,
+                           hipStream_t s);
 hipError_t launch_deg0_bitmap(const uint32_t* row_ptr, uint32_t n, uint32_t* bits, uint32_t words, hipStream_t s);
 // Count (into *bad, cleared first) the column indices that are >= n.
 hipError_t launch_check_cols(const uint32_t* col, uint64_t arcs, uint32_t n, uint32_t* bad, hipStream_t s);

@@ -85,6 +85,7 @@ struct coop_graph {
     uint32_t max_deg;
     uint32_t* deg0 = nullptr;                            // device bitmap: vertices without arcs
     uint32_t* col_bu = nullptr;                          // bottom-up probe order (arcs + 4 words)
+    uint2* first2 = nullptr;                             // skewed graphs: first two neighbours of every vertex in that order
     uint32_t words = 0;                                  // bitmap words (multiple of 64)
     std::vector<uint32_t> deg;                           // host copy of the degrees
     std::map<std::pair<uint32_t, uint32_t>, uint64_t> strips;   // (threshold, strip) -> capacity
@@ -645,11 +646,18 @@ int coop_graph_wrap(coop_rt* rt, const uint32_t* d_row_ptr, const uint32_t* d_co
         // degree (the first arc mostly decides a bottom-up probe)
         if (rc == COOP_OK) {
             hipError_t e = hipMalloc(&g->col_bu, (size_t)(arcs + 4) * 4);
+            // a graph whose maximum degree exceeds 16 x its average has hubs
+            // that decide most bottom-up probes on the first arcs
+            const bool skewed = arcs > 0 && (uint64_t)g->max_deg * n > 16ull * arcs;
+            if (e == hipSuccess && skewed) e = hipMalloc(&g->first2, (size_t)n * sizeof(uint2));
             if (e == hipSuccess)
                 e = coop::build_degree_order(d_row_ptr, d_col, n, arcs, g->max_deg, g->col_bu, rt->cotask_stream);
+            if (e == hipSuccess && skewed)
+                e = coop::build_first_two(d_row_ptr, g->col_bu, n, g->first2, rt->cotask_stream);
             if (e != hipSuccess) rc = e == hipErrorOutOfMemory ? COOP_E_OOM : hip_fail(rt, e);
         }
         if (rc != COOP_OK) {
+            if (g->first2) (void)hipFree(g->first2);
             if (g->col_bu) (void)hipFree(g->col_bu);
             if (g->deg0) (void)hipFree(g->deg0);
             delete g;
@@ -665,6 +673,7 @@ int coop_graph_release(coop_graph* g) {
     if (g->deg0 || g->col_bu) (void)hipDeviceSynchronize();
     if (g->deg0) (void)hipFree(g->deg0);
     if (g->col_bu) (void)hipFree(g->col_bu);
+    if (g->first2) (void)hipFree(g->first2);
     delete g;
     return COOP_OK;
 }
@@ -701,6 +710,7 @@ int coop_bfs(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_t
     a.total_arcs = g->arcs;
     a.bu_prefetch = (opts && (opts->flags & (1u << 31))) ? 1u : 0u;
     a.col_bu = g->col_bu;
+    a.first2 = g->first2;
     if (!a.vis || !a.fb[0] || !a.fb[1] || !a.fb[2]) { handle_free(h); return COOP_E_OOM; }
     (void)hipEventRecord(h->ev_init, s);
     (void)hipEventRecord(h->ev_start, s);
@@ -764,6 +774,7 @@ int coop_bfs_noalloc(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, 
     a.total_arcs = g->arcs;
     a.bu_prefetch = (opts && (opts->flags & (1u << 31))) ? 1u : 0u;
     a.col_bu = g->col_bu;
+    a.first2 = g->first2;
     // the array keeps the previous call's contents: the context and the
     // slots are cleared here, the bitmaps by the kernel's per-source init
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -1253,6 +1264,7 @@ int coop_batch_run(coop_rt* rt, const coop_batch_item* items, uint32_t count, co
             I.bfs.beta = 24;
             I.bfs.total_arcs = g->arcs;
             I.bfs.col_bu = g->col_bu;
+            I.bfs.first2 = g->first2;
         }
         // colouring / MIS
         I.col.t = t;
@@ -1787,6 +1799,7 @@ int coop_server_create(coop_rt* rt, const coop_graph* const* graphs, uint32_t ng
             D.bfs.beta = 24;
             D.bfs.total_arcs = g->arcs;
             D.bfs.col_bu = g->col_bu;
+            D.bfs.first2 = g->first2;
             D.sssp.t = t;
             for (int k = 0; k < 3; ++k) D.sssp.fb[k] = D.bfs.fb[k];
             D.sssp.lowered = reinterpret_cast<uint32_t*>(st + 4 * wb);

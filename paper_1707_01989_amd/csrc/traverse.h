@@ -110,6 +110,7 @@ struct WaveLds {
     uint32_t out_n;             // entries in the output buffer
     uint32_t out[kOutCap];
     uint32_t lng[2 * kWave];    // bottom-up: candidates with long lists, scanned by the whole wave
+    uint32_t lngk[2 * kWave];   // ... and the arc where the lane's probes stopped
 };
 
 struct BlockLds {
@@ -454,7 +455,7 @@ __device__ __forceinline__ void bu_mark(const BfsArgs& p, uint32_t* fw, uint32_t
 }
 
 // Scan the deferred long lists with the whole wave, one candidate at a time,
-// 256 arcs per step, from where the lane left off.
+// 256 arcs per step, from where the lane left off (lngk).
 __device__ void bu_scan_long(const BfsArgs& p, WaveLds& wl, const uint32_t* cur, uint32_t* fw, uint32_t* level,
                              uint32_t next_level, uint32_t word0, uint32_t nlong, Stats& st) {
     const uint32_t l = lane_id();
@@ -462,9 +463,7 @@ __device__ void bu_scan_long(const BfsArgs& p, WaveLds& wl, const uint32_t* cur,
         const uint32_t vv = wl.lng[i];
         const uint32_t a0 = p.t.row_ptr[vv], a1 = p.t.row_ptr[vv + 1];
         bool found = false;
-        // a lane's probes are aligned 4-arc chunks: after kLaneRounds of
-        // them it stopped at (a0 & ~3) + 4 kLaneRounds
-        for (uint32_t kk = (a0 & ~3u) + 4 * kLaneRounds; kk < a1 && !found; kk += 4 * kWave) {
+        for (uint32_t kk = wl.lngk[i]; kk < a1 && !found; kk += 4 * kWave) {
             uint32_t u[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -514,7 +513,9 @@ __device__ void bfs_bottom_up(const BfsArgs& p, WaveLds& wl, const uint32_t* cur
         // instead of waiting for the slowest lane of a batch.
         uint32_t next = 0, nlong = 0;
         uint32_t v[2] = {0, 0}, k[2] = {0, 0}, e[2] = {0, 0}, s0[2] = {0, 0}, rounds[2] = {0, 0};
-        bool act[2] = {false, false};
+        uint2 f2[2] = {make_uint2(0, 0), make_uint2(0, 0)};
+        const bool dense = p.first2 != nullptr;     // skewed graphs only (see graph_prep)
+        bool act[2] = {false, false}, fresh[2] = {false, false};
         for (;;) {
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
@@ -525,24 +526,39 @@ __device__ void bfs_bottom_up(const BfsArgs& p, WaveLds& wl, const uint32_t* cur
                     if (need && idx < total) {
                         v[c] = list[idx];
                         act[c] = true;
-                        rounds[c] = 0;
                         s0[c] = k[c] = p.t.row_ptr[v[c]];
                         e[c] = p.t.row_ptr[v[c] + 1];
+                        rounds[c] = 0;
+                        fresh[c] = dense;                // the dense first-two probe comes first
+                        if (dense) f2[c] = p.first2[v[c]];
                         st.rows += 1;
                     }
                     next += (uint32_t)__popcll(mask);
                 }
             }
             if (!__ballot(act[0] || act[1])) break;
+            // on a skewed graph a candidate's first round probes its first
+            // two neighbours from the dense array (the candidates of a block
+            // sit side by side there); every other round probes an aligned
+            // 4-arc chunk of col_bu
             uint4 q[2];
 #pragma unroll
-            for (int c = 0; c < 2; ++c) q[c] = act[c] ? probe_chunk(p.col_bu, k[c]) : make_uint4(0, 0, 0, 0);
+            for (int c = 0; c < 2; ++c)
+                q[c] = (act[c] && !fresh[c]) ? probe_chunk(p.col_bu, k[c]) : make_uint4(0, 0, 0, 0);
             bool defer[2] = {false, false};
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 if (!act[c]) continue;
                 uint32_t got;
-                const bool hit = probe_hits(cur, q[c], k[c], e[c], got);
+                bool hit;
+                if (fresh[c]) {
+                    fresh[c] = false;
+                    got = e[c] - k[c] < 2 ? e[c] - k[c] : 2u;
+                    hit = ((cur[f2[c].x >> 5] >> (f2[c].x & 31)) & 1u) != 0;
+                    if (got == 2) hit |= ((cur[f2[c].y >> 5] >> (f2[c].y & 31)) & 1u) != 0;
+                } else {
+                    hit = probe_hits(cur, q[c], k[c], e[c], got);
+                }
                 st.arcs += got;
                 k[c] += got;
                 rounds[c] += 1;
@@ -559,7 +575,10 @@ __device__ void bfs_bottom_up(const BfsArgs& p, WaveLds& wl, const uint32_t* cur
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const uint64_t mask = __ballot(defer[c]);
-                if (defer[c]) wl.lng[nlong + mbcnt(mask)] = v[c];
+                if (defer[c]) {
+                    wl.lng[nlong + mbcnt(mask)] = v[c];
+                    wl.lngk[nlong + mbcnt(mask)] = k[c];
+                }
                 nlong += (uint32_t)__popcll(mask);
             }
             if (nlong) {                             // at most 2 x 64 deferrals: the list's capacity
@@ -673,7 +692,10 @@ __device__ void bfs_bottom_up_rp(const BfsArgs& p, WaveLds& wl, const uint32_t* 
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const uint64_t mask = __ballot(defer[c]);
-                if (defer[c]) wl.lng[nlong + mbcnt(mask)] = v0 + o[c];
+                if (defer[c]) {
+                    wl.lng[nlong + mbcnt(mask)] = v0 + o[c];
+                    wl.lngk[nlong + mbcnt(mask)] = k[c];
+                }
                 nlong += (uint32_t)__popcll(mask);
             }
             if (nlong) {
