@@ -297,6 +297,7 @@ struct BarrierLds {
     uint32_t offers;                   // task pattern: offer_kill calls so far (thread 0)
     uint32_t cut, tail_prev;           // admission: slots taken before the first new unannounced one
     uint32_t m0;                       // members before this barrier's forks (the start-up admission's count)
+    uint32_t quiet;                    // the master step changes nothing but the epoch
     uint32_t valid[kMaxGroups / 32];   // admission: ring slots whose joiner was still waiting
     uint32_t xcnt[kMaxEngines];        // placed kill: members per engine, then victims per engine
     uint32_t wsum[kMaxWaves + 1];      // placed kill: survivors per wave of ids
@@ -612,6 +613,12 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
         const uint32_t span = ready < blockDim.x ? ready : blockDim.x;
         drain0 = (live && kmax == 0 && span >= kDrainMin) ? span : 0u;
         b.drain_span = drain0;
+        // the common barrier: nothing to admit, drain or kill, no recount
+        // of the members per XCD, the kernel goes on (the Kill-No-Op rule
+        // and a fork of k = 0); only the bookkeeping below runs
+        b.quiet = (m.epoch != 0 && nb != 0 && !(m.flags & kFlagFlat) &&
+                   !(flags & (kFlagDone | kFlagAbort | kFlagRenum | kFlagFlat)) && kmax == 0 && drain0 == 0 &&
+                   T >= m.M && T_dev == pre.T_dev) ? 1u : 0u;
     }
     // every thread reads what thread 0 just shared (b.flags decides below
     // whether the whole workgroup recounts the members per XCD, a block with
@@ -621,6 +628,24 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
     // read it unsynchronised split its barriers between the threads that saw
     // DONE there and thread 0, and miscounted the arrivals)
     __syncthreads();
+    if (b.quiet) {
+        if (threadIdx.x == 0) {
+            c->barriers = nb + 1;
+            if (Coop) c->tail_prev = pre.tail;
+            if (cfg.trace && nb < cfg.trace_cap) {
+                cfg.trace[2 * nb] = t_in;
+                cfg.trace[2 * nb + 1] = (now_ticks() & 0xFFFFFFFFFFFFull) | ((uint64_t)(flags & 0xFFFFu) << 48);
+            }
+            st_release64(&c->release, make_release(ne, m.M, flags));
+            Member n = m;
+            n.epoch = ne;
+            n.flags = flags;
+            n.alive = 1u;
+            b.member = n;
+            b.killed = 0u;
+        }
+        return;
+    }
     const uint32_t M0 = b.m0;
     uint32_t admitted = 0;
     if constexpr (Coop) {
