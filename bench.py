@@ -257,25 +257,37 @@ def main():
             if rc != 0:
                 raise RuntimeError(coop.coop_strerror(rc))
             return st
-        for _ in range(3):
-            run_e(coop_opts)
-            run_e(plain_opts)
-        ec, ep = [], []
-        for _ in range(args.er_reps):            # interleaved, so drift hits both alike
-            ec.append(run_e(coop_opts))
-            ep.append(run_e(plain_opts))
-        mc = float(np.median([s["kernel_ms"] for s in ec]))
-        mp = float(np.median([s["kernel_ms"] for s in ep]))
-        dc = float(np.median([s["device_ms"] for s in ec]))
-        dp = float(np.median([s["device_ms"] for s in ep]))
+
+        def er_pair(flags):
+            oc = coop.make_opts(coop.COOP_MODE_COOP, flags=coop.COOP_F_HOST_SCHEDULE | flags)
+            op = coop.make_opts(coop.COOP_MODE_PLAIN, flags=flags)
+            for _ in range(3):
+                run_e(oc)
+                run_e(op)
+            ec, ep = [], []
+            for _ in range(args.er_reps):            # interleaved, so drift hits both alike
+                ec.append(run_e(oc))
+                ep.append(run_e(op))
+            mc = float(np.median([s["kernel_ms"] for s in ec]))
+            mp = float(np.median([s["kernel_ms"] for s in ep]))
+            dc = float(np.median([s["device_ms"] for s in ec]))
+            dp = float(np.median([s["device_ms"] for s in ep]))
+            return {
+                "levels": ec[0]["levels"], "barriers": ec[0]["barriers"],
+                "ms_coop": round(mc, 4), "ms_plain": round(mp, 4), "coop_overhead": round(mc / mp, 4),
+                "gteps_coop": round(e_edges / (mc * 1e-3) / 1e9, 4),
+                "gteps_plain": round(e_edges / (mp * 1e-3) / 1e9, 4),
+                "ns_per_barrier_coop": round(dc * 1e6 / ec[0]["barriers"], 1),
+                "ns_per_barrier_plain": round(dp * 1e6 / ep[0]["barriers"], 1),
+            }
+        # the configuration as stated: a global barrier after every level
         result["er4096"] = {
-            "workload": "BFS from vertex 0, ER G(n=4096, m=16384) (seed 1), one persistent launch per run",
-            "reps": args.er_reps, "levels": ec[0]["levels"], "barriers": ec[0]["barriers"],
-            "ms_coop": round(mc, 4), "ms_plain": round(mp, 4), "coop_overhead": round(mc / mp, 4),
-            "gteps_coop": round(e_edges / (mc * 1e-3) / 1e9, 4), "gteps_plain": round(e_edges / (mp * 1e-3) / 1e9, 4),
-            "ns_per_barrier_coop": round(dc * 1e6 / ec[0]["barriers"], 1),
-            "ns_per_barrier_plain": round(dp * 1e6 / ep[0]["barriers"], 1),
+            "workload": "BFS from vertex 0, ER G(n=4096, m=16384) (seed 1), one persistent launch per run, "
+                        "every level a phase of all workgroups followed by a global barrier",
+            "reps": args.er_reps, **er_pair(coop.COOP_F_LEVEL_BARRIERS),
             "note": "ns per barrier = device time from the first barrier on / barriers (one level's work plus its barrier)",
+            # the library's default: the master step runs small top-down levels itself
+            "master_step_levels": er_pair(0),
         }
         log(f"er4096: {result['er4096']}")
         dge.release()

@@ -103,9 +103,13 @@ enum {
     COOP_F_RANDOM_SCHEDULE = 2u,  /* seeded device-side kill/fork schedule */
     COOP_F_HOST_SCHEDULE = 4u,    /* barrier reads the host-written target (coop_set_target) */
     COOP_F_TOP_DOWN_ONLY = 8u,    /* BFS: never switch to bottom-up levels */
-    COOP_F_REGULAR_BARRIER = 16u  /* the paper's regular resizing barrier: at most one workgroup
+    COOP_F_REGULAR_BARRIER = 16u, /* the paper's regular resizing barrier: at most one workgroup
                                      leaves per barrier, instead of the query barrier's W at
                                      once (section 4.2); for gather-time comparisons */
+    COOP_F_LEVEL_BARRIERS = 32u   /* BFS: every level is a phase of all workgroups with its own
+                                     barrier; by default a master step runs small levels itself,
+                                     top-down (frontier of at most 2048 vertices and 4 arcs per
+                                     thread), with the same result */
 };
 
 typedef struct coop_launch_opts {

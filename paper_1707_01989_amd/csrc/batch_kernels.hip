@@ -42,11 +42,11 @@ __device__ __forceinline__ void bfs_team(const BfsArgs& p, BlockLds& sh, uint32_
         bfs_phase(p, sh, ph, m.flags, level, root, m.id, m.M, p.level_out);
         const uint32_t cur_flags = m.flags, cur_ph = ph;
         team_barrier(c, p.t.cfg, m, sh.bar,
-                     [&](uint32_t, uint32_t) -> uint32_t {
-                         return bfs_master(p, sh, c, cur_ph, cur_flags, p.t.roots, p.level_out);
+                     [&](uint32_t M, uint32_t) -> uint32_t {
+                         return bfs_master(p, sh, c, cur_ph, cur_flags, p.t.roots, p.level_out, M);
                      });
         if (!m.alive) return;
-        bfs_follow(ph, m.flags, level, root);
+        bfs_follow(ph, m.flags, level, root, p.t.work);
         ph = m.flags & kPhMask;
     }
 }
@@ -67,7 +67,7 @@ __device__ __forceinline__ void color_team(const ColorArgs& p, BlockLds& sh, uin
 }
 
 template <bool Coop>
-__device__ void batch_body(const BatchArgs& a, bool joiner) {
+__device__ __forceinline__ void batch_body(const BatchArgs& a, bool joiner) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     BlockLds& sh = *reinterpret_cast<BlockLds*>(lds_raw);
     BatchCtl* ctl = a.ctl;

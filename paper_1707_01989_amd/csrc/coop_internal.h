@@ -81,6 +81,7 @@ static_assert(sizeof(Xfer) == 64, "transmit block is four 16-byte words");
 // counter on the hot path. The master step reads and clears the per-level
 // fields; the cumulative ones are summed by the host after the launch.
 constexpr uint32_t kSlotWords = 16;     // 8 uint64 fields
+constexpr uint32_t kFlWgHost = 64;      // BFS found-list entries per workgroup (the kernels' kFlWg)
 enum SlotField : uint32_t {
     kSlotFound = 0,       // per level: vertices reached / queued
     kSlotMf = 1,          // per level: sum of their degrees (BFS direction rule)
@@ -126,6 +127,9 @@ struct BfsArgs {
                                // 16-byte aligned and padded by 4 words (the graph's copy)
     const uint2* first2;       // skewed graphs: per vertex its first two neighbours in probe order
                                // (0xFFFFFFFF: none); null otherwise
+    uint32_t* flist;           // N x (1 + kFlWgHost) words: per workgroup the count and first 64 vertices it
+                               // found in the last phase; null: no lists
+    uint32_t inline_on;        // 1: the master step runs small levels itself (top-down)
 };
 
 struct SsspArgs {

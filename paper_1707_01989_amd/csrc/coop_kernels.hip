@@ -38,8 +38,8 @@ namespace {
 // joiner takes over is the Work block's transmit words, written by the
 // barrier's single step.
 
-template <bool Coop>
-__device__ void bfs_body(const BfsArgs& p, bool joiner_grid) {
+template <bool Coop, bool Small>
+__device__ __forceinline__ void bfs_body(const BfsArgs& p, bool joiner_grid) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     BlockLds& sh = *reinterpret_cast<BlockLds*>(lds_raw);
     const TraversalArgs& t = p.t;
@@ -53,6 +53,7 @@ __device__ void bfs_body(const BfsArgs& p, bool joiner_grid) {
         sh.level = joined ? wk->x.level : 0u;
         sh.root = joined ? wk->x.root : 0u;
         for (int i = 0; i < 8; ++i) sh.acc[i] = 0;
+        sh.fl_n = 0;
     }
     __syncthreads();
     uint32_t level = sh.level, root = sh.root;
@@ -75,19 +76,19 @@ __device__ void bfs_body(const BfsArgs& p, bool joiner_grid) {
         const uint32_t id = coop_get_group_id(g), M = coop_get_num_groups(g);
         fresh = false;
         wg_trace(t.cfg, g.bar.member.epoch, id, kTrStart);
-        bfs_phase(p, sh, ph, cur_flags, level, root, id, M, p.level_out);
+        bfs_phase<Small>(p, sh, ph, cur_flags, level, root, id, M, p.level_out);
         wg_trace(t.cfg, g.bar.member.epoch, id, kTrWorkDone);
-        coop_resizing_global_barrier<Coop>(g, [&](uint32_t, uint32_t) -> uint32_t {
-            return bfs_master(p, sh, c, ph, cur_flags, t.roots, p.level_out);
+        coop_resizing_global_barrier<Coop>(g, [&](uint32_t M_now, uint32_t) -> uint32_t {
+            return bfs_master<Small>(p, sh, c, ph, cur_flags, t.roots, p.level_out, M_now);
         });
-        bfs_follow(ph, coop_flags(g), level, root);
+        bfs_follow(ph, coop_flags(g), level, root, wk);
     }
 }
 
 // ----------------------------------------------------------------- SSSP
 
 template <bool Coop>
-__device__ void sssp_body(const SsspArgs& p, bool joiner_grid) {
+__device__ __forceinline__ void sssp_body(const SsspArgs& p, bool joiner_grid) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     BlockLds& sh = *reinterpret_cast<BlockLds*>(lds_raw);
     const TraversalArgs& t = p.t;
@@ -129,7 +130,7 @@ __device__ void sssp_body(const SsspArgs& p, bool joiner_grid) {
 }
 
 template <bool Coop>
-__device__ void color_body(const ColorArgs& p, bool joiner_grid) {
+__device__ __forceinline__ void color_body(const ColorArgs& p, bool joiner_grid) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     BlockLds& sh = *reinterpret_cast<BlockLds*>(lds_raw);
     const TraversalArgs& t = p.t;
@@ -182,7 +183,11 @@ __device__ void barrier_bench_body(const BarrierBenchArgs& p, bool joiner_grid) 
 #define COOP_KERNEL_BOUNDS __launch_bounds__(1024)
 
 template <bool Coop>
-__global__ void COOP_KERNEL_BOUNDS bfs_kernel(BfsArgs a, int joiner) { bfs_body<Coop>(a, joiner != 0); }
+__global__ void COOP_KERNEL_BOUNDS bfs_kernel(BfsArgs a, int joiner) { bfs_body<Coop, true>(a, joiner != 0); }
+// ... built without the master step's small levels, for launches that give
+// every level its own phase and barrier (BfsArgs::inline_on = 0)
+template <bool Coop>
+__global__ void COOP_KERNEL_BOUNDS bfs_levels_kernel(BfsArgs a, int joiner) { bfs_body<Coop, false>(a, joiner != 0); }
 template <bool Coop>
 __global__ void COOP_KERNEL_BOUNDS sssp_kernel(SsspArgs a, int joiner) { sssp_body<Coop>(a, joiner != 0); }
 template <bool Coop>
@@ -320,6 +325,9 @@ static hipError_t launch_persistent(K kern_coop, K kern_plain, const A& a, bool 
 
 hipError_t launch_bfs(const BfsArgs& a, bool coop, bool joiner_grid, uint32_t grid, uint32_t block,
                       uint32_t lds_bytes, hipStream_t s) {
+    if (!a.inline_on)
+        return launch_persistent(bfs_levels_kernel<true>, bfs_levels_kernel<false>, a, coop, joiner_grid, grid,
+                                 block, lds_bytes, s);
     return launch_persistent(bfs_kernel<true>, bfs_kernel<false>, a, coop, joiner_grid, grid, block,
                              lds_bytes, s);
 }

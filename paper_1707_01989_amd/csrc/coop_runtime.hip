@@ -711,7 +711,13 @@ int coop_bfs(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_t
     a.bu_prefetch = (opts && (opts->flags & (1u << 31))) ? 1u : 0u;
     a.col_bu = g->col_bu;
     a.first2 = g->first2;
-    if (!a.vis || !a.fb[0] || !a.fb[1] || !a.fb[2]) { handle_free(h); return COOP_E_OOM; }
+    a.inline_on = (opts && (opts->flags & COOP_F_LEVEL_BARRIERS)) ? 0u : 1u;
+    a.flist = a.inline_on ? static_cast<uint32_t*>(scratch_buf(h, (size_t)sz.grid * (coop::kFlWgHost + 1) * 4))
+                          : nullptr;
+    if (!a.vis || !a.fb[0] || !a.fb[1] || !a.fb[2] || (a.inline_on && !a.flist)) {
+        handle_free(h);
+        return COOP_E_OOM;
+    }
     (void)hipEventRecord(h->ev_init, s);
     (void)hipEventRecord(h->ev_start, s);
     return finish_launch(rt, h, relaunch(h, false, h->grid, s), out);
@@ -736,11 +742,13 @@ int coop_bfs_noalloc(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, 
     }
     if (hs > 0xFFFFFFFFull) return COOP_E_TOO_BIG;
     // the array's layout for this call: context | transmit block | slots |
-    // heavy strips | visited, frontier x 3
+    // found lists | heavy strips | visited, frontier x 3
     const size_t slot_words = (size_t)sz.grid * coop::kSlotWords;
+    const bool inline_on = !(opts && (opts->flags & COOP_F_LEVEL_BARRIERS));
     const size_t o_work = align_up(sizeof(Ctx));
     const size_t o_slots = o_work + align_up(sizeof(Work));
-    const size_t o_heavy = o_slots + align_up(slot_words * 4);
+    const size_t o_flist = o_slots + align_up(slot_words * 4);
+    const size_t o_heavy = o_flist + (inline_on ? align_up((size_t)sz.grid * (coop::kFlWgHost + 1) * 4) : 0);
     const size_t o_bits = o_heavy + align_up(hs * sizeof(uint4));
     const size_t bm = align_up((size_t)g->words * 4);
     const size_t total = o_bits + 4 * bm;
@@ -775,6 +783,8 @@ int coop_bfs_noalloc(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, 
     a.bu_prefetch = (opts && (opts->flags & (1u << 31))) ? 1u : 0u;
     a.col_bu = g->col_bu;
     a.first2 = g->first2;
+    a.inline_on = inline_on ? 1u : 0u;
+    a.flist = inline_on ? reinterpret_cast<uint32_t*>(base + o_flist) : nullptr;
     // the array keeps the previous call's contents: the context and the
     // slots are cleared here, the bitmaps by the kernel's per-source init
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);

@@ -138,13 +138,13 @@ __device__ __forceinline__ uint32_t serve_bfs(const ServeArgs& a, const BfsArgs&
     for (;;) {
         bfs_phase(p, sh, ph, m.flags, level, root, m.id, m.M, out);
         const uint32_t cur_flags = m.flags, cur_ph = ph;
-        serve_barrier<Coop>(a, c, p.t.cfg, m, sh.bar, p.t.slots, [&](uint32_t, uint32_t) -> uint32_t {
-            uint32_t f = bfs_master(p, sh, c, cur_ph, cur_flags, roots, out);
+        serve_barrier<Coop>(a, c, p.t.cfg, m, sh.bar, p.t.slots, [&](uint32_t M, uint32_t) -> uint32_t {
+            uint32_t f = bfs_master(p, sh, c, cur_ph, cur_flags, roots, out, M);
             return (f & kFlagDone) ? ((f & ~kFlagDone) | kFlagEnd) : f;
         });
         if (!m.alive) return 0;
         if (m.flags & kFlagEnd) return m.M;
-        bfs_follow(ph, m.flags, level, root);
+        bfs_follow(ph, m.flags, level, root, p.t.work);
         ph = m.flags & kPhMask;
     }
 }
@@ -260,7 +260,7 @@ __device__ uint32_t serve_next_ticket(const ServeArgs& a, Group& g, uint32_t& k,
 }
 
 template <bool Coop>
-__device__ void serve_body(const ServeArgs& a, bool joiner) {
+__device__ __forceinline__ void serve_body(const ServeArgs& a, bool joiner) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     BlockLds& sh = *reinterpret_cast<BlockLds*>(lds_raw);
     ServeCtl* ctl = a.ctl;

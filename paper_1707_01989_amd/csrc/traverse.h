@@ -58,6 +58,10 @@ constexpr uint32_t kRotShift = 10;                // BFS: frontier bitmap rotati
 constexpr uint32_t kRotMask = 3u << kRotShift;
 constexpr uint32_t kFlagEnd = 1u << 12;           // a served query finished (the team goes on)
 constexpr uint32_t kFlagPreSplit = 1u << 13;      // BFS top-down: the frontier's heavy vertices are strips already
+constexpr uint32_t kFlagJump = 1u << 14;          // BFS: the master step ran levels itself; the level is x.level
+constexpr uint32_t kFlagRecord = 1u << 15;        // BFS: the phase lists what it finds (a small level may follow)
+constexpr uint64_t kRecordArcs = 1u << 16;        // ... when the frontier has at most this many arcs
+constexpr uint32_t kFlWg = coop::kFlWgHost;       // BFS: found vertices a workgroup lists per level
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 __device__ __forceinline__ uint32_t wave_id() { return threadIdx.x / kWave; }
@@ -120,6 +124,11 @@ struct BlockLds {
     uint64_t acc[8];            // per-workgroup statistics of the phase
     uint64_t red[8][kMaxWaves]; // master reductions
     uint32_t mb[4];             // master step: values thread 0 shares with the workgroup
+    uint32_t fl_n;              // BFS: vertices this workgroup found in the phase
+    uint32_t fl[kFlWg];         // ... the first kFlWg of them
+    uint32_t il_c[2], il_go;    // BFS master step: small-level list lengths, whether to run them
+    uint32_t il_v[6];           // ... values thread 0 shares with the workgroup
+    XferR il_x;                 // BFS master step: thread 0's copy of the transmit block
     WaveLds wave[kMaxWaves];
 };
 
@@ -346,6 +355,23 @@ __device__ void heavy_phase(const TraversalArgs& a, uint32_t nstrips, uint32_t g
 
 // ------------------------------------------------------------------ BFS
 
+// Count the wave's found vertices (`c` per lane) into the workgroup's LDS
+// list; `emit(pos)` writes a lane's vertices from list position pos on
+// (positions at or past kFlWg are dropped). `on` (wave-uniform) turns off once
+// the count passes kFlWg: it then only tells the master step that the list
+// overflowed (the master also checks the counts against the level's total).
+template <class Emit>
+__device__ __forceinline__ void fl_record(uint32_t* fl_n, bool& on, uint32_t c, Emit&& emit) {
+    const uint32_t incl = wave_incl_scan(c);
+    const uint32_t tot = bcast(incl, kWave - 1);
+    if (tot == 0) return;
+    uint32_t base = 0;
+    if (lane_id() == kWave - 1) base = atomicAdd(fl_n, tot);
+    base = bcast(base, kWave - 1);
+    if (base + tot > kFlWg) on = false;
+    if (c && base + incl - c < kFlWg) emit(base + incl - c);
+}
+
 struct BfsTopDown {
     uint32_t* vis;
     uint32_t* nxt;
@@ -353,6 +379,9 @@ struct BfsTopDown {
     const uint32_t* row_ptr;
     uint32_t next_level;
     uint32_t count_mf;
+    uint32_t* fl_n = nullptr;   // LDS found list of the workgroup (null: none kept)
+    uint32_t* fl = nullptr;
+    bool fl_on = false;
 
     __device__ __forceinline__ uint32_t payload(uint32_t) const { return 0; }
     __device__ __forceinline__ uint32_t strip_payload(uint32_t p, uint32_t) const { return p; }
@@ -385,6 +414,19 @@ struct BfsTopDown {
                 __hip_atomic_fetch_or(&nxt[u[j] >> 5], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 st.found += 1;
             }
+        }
+        if (fl_on) {
+            uint32_t c = 0;
+#pragma unroll
+            for (uint32_t j = 0; j < kUnroll; ++j) c += won[j] ? 1u : 0u;
+            fl_record(fl_n, fl_on, c, [&](uint32_t pos) {
+#pragma unroll
+                for (uint32_t j = 0; j < kUnroll; ++j)
+                    if (won[j]) {
+                        if (pos < kFlWg) fl[pos] = u[j];
+                        ++pos;
+                    }
+            });
         }
         if (count_mf) {
             uint32_t r0[kUnroll], r1[kUnroll];
@@ -483,7 +525,9 @@ __device__ void bu_scan_long(const BfsArgs& p, WaveLds& wl, const uint32_t* cur,
 }
 
 __device__ void bfs_bottom_up(const BfsArgs& p, WaveLds& wl, const uint32_t* cur, uint32_t* nxt,
-                              uint32_t* level, uint32_t next_level, uint32_t gw, uint32_t W, Stats& st) {
+                              uint32_t* level, uint32_t next_level, uint32_t gw, uint32_t W, Stats& st,
+                              uint32_t* fl_n, uint32_t* fl) {
+    bool fl_on = fl_n != nullptr;
     constexpr uint32_t kBlockWords = 32;
     const uint32_t blocks = p.words / kBlockWords;
     const uint32_t l = lane_id();
@@ -595,6 +639,12 @@ __device__ void bfs_bottom_up(const BfsArgs& p, WaveLds& wl, const uint32_t* cur
                 nxt[wi] = f;
             }
         }
+        if (fl_on) {
+            const uint32_t f = l < 32 ? fw[l] : 0u;
+            fl_record(fl_n, fl_on, __popc(f), [&](uint32_t pos) {
+                for (uint32_t m = f; m && pos < kFlWg; m &= m - 1) fl[pos++] = wi * 32u + (uint32_t)(__ffs(m) - 1);
+            });
+        }
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -608,7 +658,9 @@ __device__ void bfs_bottom_up(const BfsArgs& p, WaveLds& wl, const uint32_t* cur
 // comes from LDS, so its dependent chain is column -> frontier bit (two
 // global round trips instead of three).
 __device__ void bfs_bottom_up_rp(const BfsArgs& p, WaveLds& wl, const uint32_t* cur, uint32_t* nxt,
-                                 uint32_t* level, uint32_t next_level, uint32_t gw, uint32_t W, Stats& st) {
+                                 uint32_t* level, uint32_t next_level, uint32_t gw, uint32_t W, Stats& st,
+                                 uint32_t* fl_n, uint32_t* fl) {
+    bool fl_on = fl_n != nullptr;
     constexpr uint32_t kBlockWords = 16, kBlockV = kBlockWords * 32;
     const uint32_t blocks = p.words / kBlockWords;
     const uint32_t l = lane_id();
@@ -712,6 +764,12 @@ __device__ void bfs_bottom_up_rp(const BfsArgs& p, WaveLds& wl, const uint32_t* 
                 nxt[wi] = f;
             }
         }
+        if (fl_on) {
+            const uint32_t f = l < 16 ? fw[l] : 0u;
+            fl_record(fl_n, fl_on, __popc(f), [&](uint32_t pos) {
+                for (uint32_t m = f; m && pos < kFlWg; m &= m - 1) fl[pos++] = wi * 32u + (uint32_t)(__ffs(m) - 1);
+            });
+        }
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -764,6 +822,7 @@ __device__ __forceinline__ void clear_share(uint32_t* bm, uint32_t words, uint32
 // One BFS phase for member `id` of `M` (the interval's membership):
 // INIT clears the per-source state, TD/HEAVY expand the frontier, BU probes
 // the unvisited vertices. Statistics go to the member's slot.
+template <bool Small = false>
 __device__ __forceinline__ void bfs_phase(const BfsArgs& p, BlockLds& sh, uint32_t ph, uint32_t flags,
                                           uint32_t level, uint32_t root, uint32_t id, uint32_t M,
                                           uint32_t* lvl_base) {
@@ -791,6 +850,11 @@ __device__ __forceinline__ void bfs_phase(const BfsArgs& p, BlockLds& sh, uint32
         }
     } else if (ph == kPhTD || ph == kPhHeavy) {
         BfsTopDown vis{p.vis, nxt, lvl, t.row_ptr, level + 1, p.direction_opt};
+        if (Small && p.flist && (flags & kFlagRecord)) {
+            vis.fl_n = &sh.fl_n;
+            vis.fl = sh.fl;
+            vis.fl_on = true;
+        }
         WaveLds& w = sh.wave[wave_id()];
         if (ph == kPhTD) {
             clear_share(spare, p.words, gw, W);
@@ -802,14 +866,295 @@ __device__ __forceinline__ void bfs_phase(const BfsArgs& p, BlockLds& sh, uint32
         }
     } else if (ph == kPhBU) {
         clear_share(spare, p.words, gw, W);
-        if (p.bu_prefetch) bfs_bottom_up_rp(p, sh.wave[wave_id()], cur, nxt, lvl, level + 1, gw, W, st);
-        else bfs_bottom_up(p, sh.wave[wave_id()], cur, nxt, lvl, level + 1, gw, W, st);
+        uint32_t* fn = (Small && p.flist && (flags & kFlagRecord)) ? &sh.fl_n : nullptr;
+        if (p.bu_prefetch) bfs_bottom_up_rp(p, sh.wave[wave_id()], cur, nxt, lvl, level + 1, gw, W, st, fn, sh.fl);
+        else bfs_bottom_up(p, sh.wave[wave_id()], cur, nxt, lvl, level + 1, gw, W, st, fn, sh.fl);
     }
     if (ph != kPhStart && ph != kPhInit) {
         stats_to_lds(sh, st);
         __syncthreads();
         acc_to_slot(sh, t.slots, id);
+        if (Small && p.flist && (flags & kFlagRecord) && threadIdx.x < kWave) {
+            // the phase's found list, for a master step that may run the
+            // next levels itself: count, then up to kFlWg vertices (wave 0
+            // reads the count before lane 0 clears it for the next phase)
+            const uint32_t nf = sh.fl_n;
+            uint32_t* dst = p.flist + (size_t)id * (kFlWg + 1);
+            if (threadIdx.x < nf && threadIdx.x < kFlWg) dst[1 + threadIdx.x] = sh.fl[threadIdx.x];
+            if (threadIdx.x == 0) {
+                dst[0] = nf;
+                sh.fl_n = 0;
+            }
+        }
     }
+}
+
+// ------------------------------------------- small levels in the master step
+//
+// A level whose frontier is small costs far more in its phase's start and
+// end (every workgroup scans its share of the frontier bitmap, then meets at
+// the barrier) than in its arcs. The master workgroup runs such levels
+// itself, one after another, inside the master step: on R-MAT the first
+// level after a low-degree source and the last one or two levels of every
+// traversal touch a few thousand arcs at most. A level qualifies when its
+// frontier fits the master's LDS lists (il_cap) and its arcs are at most
+// kInlineArcs per thread; it is walked top-down whatever the direction rule
+// would pick for a phase. The results are those of the phases: the same
+// claims on the visited bitmap, the same levels, the same next frontier in
+// the bitmap the next phase reads.
+//
+// The lists live in the master's wave output buffers (idle in a master
+// step): two frontier lists, the first arc of each vertex and its degree
+// (then degree prefix), each il_cap entries, indexed through il_at.
+constexpr uint32_t kInlineArcs = 4;      // arcs per thread of the master workgroup per level
+constexpr uint32_t kInlineLevels = 16;   // levels per master step at most (a barrier, and its
+                                         // offer_kill, still comes after that many)
+
+__device__ __forceinline__ uint32_t il_cap(uint32_t nw) {
+    const uint32_t c = (nw * kOutCap - 1) / 6;
+    return c < 2048u ? c : 2048u;
+}
+__device__ __forceinline__ uint32_t& il_at(BlockLds& sh, uint32_t i) { return sh.wave[i / kOutCap].out[i % kOutCap]; }
+
+// Exclusive prefix sum of entries [base, base + n) in place; returns the
+// total (all threads).
+__device__ __forceinline__ uint32_t il_scan(BlockLds& sh, uint32_t base, uint32_t n) {
+    const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
+    const uint32_t i0 = threadIdx.x * per;
+    uint32_t loc = 0;
+    for (uint32_t j = 0; j < per; ++j)
+        if (i0 + j < n) loc += il_at(sh, base + i0 + j);
+    const uint32_t incl = wave_incl_scan(loc);
+    if (lane_id() == kWave - 1) sh.wave_base[wave_id()] = incl;
+    __syncthreads();
+    uint32_t run = incl - loc, tot = 0;
+    for (uint32_t w = 0; w < num_waves(); ++w) {
+        const uint32_t b = sh.wave_base[w];
+        run += w < wave_id() ? b : 0u;
+        tot += b;
+    }
+    for (uint32_t j = 0; j < per; ++j)
+        if (i0 + j < n) {
+            uint32_t& e = il_at(sh, base + i0 + j);
+            const uint32_t d = e;
+            e = run;
+            run += d;
+        }
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(tot);
+}
+
+// The last index i < n whose prefix entry [base + i] is <= k.
+__device__ __forceinline__ uint32_t il_owner(BlockLds& sh, uint32_t base, uint32_t n, uint32_t k) {
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (il_at(sh, base + mid) <= k) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// The found lists of the phase just ended (members 0 .. M-1, nf vertices
+// in all) into frontier list 0, with each vertex's first arc and degree.
+// False (all threads) if a workgroup found more than it could list.
+__device__ __forceinline__ bool il_gather(BlockLds& sh, const uint32_t* flist, const uint32_t* row_ptr, uint32_t M,
+                                          uint32_t nf) {
+    const uint32_t F = il_cap(num_waves());
+    if (M > 5 * F || nf > F) return false;
+    const uint32_t T0 = F;                     // the M counts, then their offsets
+    if (threadIdx.x == 0) sh.il_go = 1u;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < M; i += blockDim.x) {
+        const uint32_t c = flist[(size_t)i * (kFlWg + 1)];
+        il_at(sh, T0 + i) = c;
+        if (c > kFlWg) sh.il_go = 0u;
+    }
+    __syncthreads();
+    const uint32_t tot = il_scan(sh, T0, M);
+    if (!__builtin_amdgcn_readfirstlane(sh.il_go) || tot != nf) return false;
+    for (uint32_t k = threadIdx.x; k < nf; k += blockDim.x) {
+        const uint32_t i = il_owner(sh, T0, M, k);
+        il_at(sh, k) = flist[(size_t)i * (kFlWg + 1) + 1 + (k - il_at(sh, T0 + i))];
+    }
+    __syncthreads();
+    uint32_t arcs = 0;
+    for (uint32_t k = threadIdx.x; k < nf; k += blockDim.x) {
+        const uint32_t v = il_at(sh, k);
+        const uint32_t a0 = row_ptr[v];
+        const uint32_t d = row_ptr[v + 1] - a0;
+        il_at(sh, 2 * F + k) = a0;
+        il_at(sh, 4 * F + k) = d;
+        arcs += d;
+    }
+    // the level's arcs (the phases only sum them when they choose directions)
+    const uint64_t wa = wave_sum64(arcs);
+    if (lane_id() == 0) sh.red[0][wave_id()] = wa;
+    __syncthreads();
+    uint64_t all = 0;
+    for (uint32_t w = 0; w < num_waves(); ++w) all += sh.red[0][w];
+    __syncthreads();
+    return all <= (uint64_t)kInlineArcs * blockDim.x;
+}
+
+// One round of a master-step level: arcs e0 .. e0 + kInlineArcs * blockDim.x
+// - 1 of the frontier in list region LA/SA/PA (PA: degree prefix). Claimed
+// neighbours get level lvl + 1 and their bit in bm, and go to list region
+// LB/SB/PB (counted in *len); returns the lane's sum of their degrees.
+__device__ __forceinline__ uint64_t il_round(BlockLds& sh, uint32_t* vis, uint32_t* bm, uint32_t* lv,
+                                             const uint32_t* col, const uint32_t* row_ptr, uint32_t lvl, uint32_t e0,
+                                             uint32_t total, uint32_t nf, uint32_t SA, uint32_t PA, uint32_t LB,
+                                             uint32_t SB, uint32_t PB, uint32_t F, uint32_t* len) {
+    uint32_t u[kInlineArcs], s[kInlineArcs], d[kInlineArcs];
+    bool won[kInlineArcs];
+    // all loads of a step are issued before their results are used
+#pragma unroll
+    for (uint32_t j = 0; j < kInlineArcs; ++j) {
+        const uint32_t e = e0 + threadIdx.x + j * blockDim.x;
+        u[j] = 0xFFFFFFFFu;
+        if (e < total) {
+            const uint32_t i = il_owner(sh, PA, nf, e);
+            u[j] = col[il_at(sh, SA + i) + (e - il_at(sh, PA + i))];
+        }
+    }
+    // claims without a filtering load first (at most a few thousand arcs:
+    // one round trip less per level)
+#pragma unroll
+    for (uint32_t j = 0; j < kInlineArcs; ++j) {
+        const uint32_t bit = 1u << (u[j] & 31);
+        uint32_t old = ~0u;
+        if (u[j] != 0xFFFFFFFFu)
+            old = __hip_atomic_fetch_or(&vis[u[j] >> 5], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        won[j] = !(old & bit);
+    }
+    uint32_t cnt = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kInlineArcs; ++j) {
+        s[j] = d[j] = 0;
+        if (won[j]) {
+            __builtin_nontemporal_store(lvl + 1, &lv[u[j]]);
+            __hip_atomic_fetch_or(&bm[u[j] >> 5], 1u << (u[j] & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s[j] = row_ptr[u[j]];
+            d[j] = row_ptr[u[j] + 1];
+            ++cnt;
+        }
+    }
+    const uint32_t incl = wave_incl_scan(cnt);
+    const uint32_t wtot = bcast(incl, kWave - 1);
+    uint32_t base = 0;
+    if (lane_id() == kWave - 1 && wtot) base = atomicAdd(len, wtot);
+    base = bcast(base, kWave - 1);
+    uint32_t pos = base + incl - cnt;
+    uint64_t mf = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kInlineArcs; ++j)
+        if (won[j]) {
+            d[j] -= s[j];
+            mf += d[j];
+            if (pos < F) {
+                il_at(sh, LB + pos) = u[j];
+                il_at(sh, SB + pos) = s[j];
+                il_at(sh, PB + pos) = d[j];
+            }
+            ++pos;
+        }
+    return mf;
+}
+
+struct IlArgs {                  // what the master-step levels read, by value (no kernel-argument address)
+    uint32_t* vis;
+    uint32_t* bm;                // the frontier bitmap the levels keep current
+    const uint32_t* col;
+    const uint32_t* row_ptr;
+    uint32_t* slots;
+    uint32_t* lv;                // the source's level array
+    uint64_t total_arcs;
+    uint32_t alpha, direction_opt, nroots, record;
+};
+
+// Run levels in the master step (all threads). On entry frontier list 0
+// holds the nf vertices of level `lvl` with their first arcs and degrees;
+// their bits are all of fb[(r + 1) % 3], and fb[(r + 2) % 3] is clear (the
+// state after a phase at rotation r). Each level claims the frontier's
+// unvisited neighbours on the visited bitmap, gives them level lvl + 1 and
+// sets their bits in the same bitmap while clearing the frontier's, so the
+// bitmap always holds exactly the current frontier. It stops when the
+// source is finished, when the next level is too large, or after
+// kInlineLevels levels; the next phase then runs at rotation (r + 1) % 3
+// (current = that bitmap, next = the clear one), in the direction the rule
+// picks. `x` and the returned release flags are thread 0's.
+__device__ __forceinline__ uint32_t bfs_inline_levels(const IlArgs& q, BlockLds& sh, XferR& x, uint32_t nf,
+                                                      uint32_t lvl, uint32_t r) {
+    const uint32_t F = il_cap(num_waves());
+    const uint32_t round = kInlineArcs * blockDim.x;
+    uint32_t* bm = q.bm;
+    uint32_t* lv = q.lv;
+    uint64_t arcs_all = 0, rows_all = 0, found_all = 0;
+    uint32_t a = 0, res = 0;
+    for (uint32_t done = 1;; ++done) {
+        const uint32_t LA = a * F, SA = (2 + a) * F, PA = (4 + a) * F;
+        const uint32_t LB = (1 - a) * F, SB = (3 - a) * F, PB = (5 - a) * F;
+        // the next list's length (last read two levels ago; the scan's
+        // workgroup barriers order the reset before any append)
+        if (threadIdx.x == 0) sh.il_c[1 - a] = 0;
+        const uint32_t total = il_scan(sh, PA, nf);      // degrees -> first arc of each vertex in the level's arcs
+        // one round per level under the entry conditions; a longer level
+        // (a frontier whose arcs the phases did not count) takes more
+        uint64_t mf = 0;
+        for (uint32_t e0 = 0; e0 < total; e0 += round)
+            mf += il_round(sh, q.vis, bm, lv, q.col, q.row_ptr, lvl, e0, total, nf, SA, PA, LB, SB, PB, F,
+                           &sh.il_c[1 - a]);
+        // the level's own bits leave the bitmap (the winners are other vertices)
+        for (uint32_t i = threadIdx.x; i < nf; i += blockDim.x) {
+            const uint32_t v = il_at(sh, LA + i);
+            __hip_atomic_fetch_and(&bm[v >> 5], ~(1u << (v & 31)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const uint64_t wmf = wave_sum64(mf);
+        if (lane_id() == 0) sh.red[0][wave_id()] = wmf;
+        __syncthreads();                           // every claim, mark and clear has completed
+        const uint32_t nb = __builtin_amdgcn_readfirstlane(sh.il_c[1 - a]);
+        if (threadIdx.x == 0) {
+            uint64_t mfb = 0;
+            for (uint32_t w = 0; w < num_waves(); ++w) mfb += sh.red[0][w];
+            arcs_all += total;
+            rows_all += nf + nb;
+            found_all += nb;
+            x.levels_total() += 1;
+            x.td_levels() += 1;
+            uint32_t go = 0;
+            if (nb == 0) {
+                x.root() += 1;
+                res = x.root() >= q.nroots ? kFlagDone : (kPhInit | kFlagAdv);
+            } else {
+                const uint64_t mv = join64(x.m_visited_lo(), x.m_visited_hi()) + mfb;
+                x.m_visited_lo() = (uint32_t)mv;
+                x.m_visited_hi() = (uint32_t)(mv >> 32);
+                const uint64_t m_u = q.total_arcs > mv ? q.total_arcs - mv : 0;
+                const uint32_t nph = (q.direction_opt && mfb * q.alpha > m_u) ? kPhBU : kPhTD;
+                x.level() = lvl + 1;
+                x.nf_prev() = nb;
+                // a level this small goes here whatever the direction rule
+                // says (the rule picks the cheaper walk for a phase of all
+                // workgroups; either gives the same levels)
+                go = (nb <= F && mfb <= round && done < kInlineLevels) ? 1u : 0u;
+                if (!go)
+                    res = nph | kFlagAdv | kFlagJump | (((r + 1) % 3) << kRotShift) |
+                          (q.record && mfb <= kRecordArcs ? kFlagRecord : 0u);
+            }
+            sh.il_go = go;
+        }
+        __syncthreads();
+        if (!__builtin_amdgcn_readfirstlane(sh.il_go)) break;
+        nf = nb;
+        lvl += 1;
+        a = 1 - a;
+    }
+    if (threadIdx.x == 0) {
+        uint64_t* s0 = reinterpret_cast<uint64_t*>(q.slots);
+        add_nr64(&s0[kSlotArcs], arcs_all);
+        add_nr64(&s0[kSlotRows], rows_all);
+        if (found_all) add_nr64(&s0[kSlotFoundAll], found_all);
+    }
+    return res;
 }
 
 // Start source x.root() in the master step (all threads of the master
@@ -819,6 +1164,7 @@ __device__ __forceinline__ void bfs_phase(const BfsArgs& p, BlockLds& sh, uint32
 // next frontier -- so the source needs no top-down phase (and barrier) for
 // level 0. The marks are atomics, as every later claim of the same words is.
 // Returns the release flags (thread 0).
+template <bool Small>
 __device__ uint32_t bfs_master_source(const BfsArgs& p, BlockLds& sh, CtxCore* c, XferR& x, const uint32_t* roots,
                                       uint32_t* lvl_base) {
     const TraversalArgs& t = p.t;
@@ -837,40 +1183,57 @@ __device__ uint32_t bfs_master_source(const BfsArgs& p, BlockLds& sh, CtxCore* c
         sh.mb[1] = a0;
         sh.mb[2] = deg;
         sh.mb[3] = x.root();
+        sh.il_c[0] = 0;
     }
     __syncthreads();
     const uint32_t src = sh.mb[0], a0 = sh.mb[1], deg = sh.mb[2];
     if (src >= t.n) {
         // a source outside the graph ends the launch before anything is
         // written for it (earlier sources are complete)
-        if (threadIdx.x == 0) raise_error(c, kErrInvalid);
+        if (threadIdx.x == 0) {
+            raise_error(c, kErrInvalid);
+            sh.il_go = 0;
+        }
         return kFlagAbort;
     }
     const bool inline_l0 = deg <= blockDim.x;
     uint64_t found = 0, mf = 0, strips = 0;
+    uint32_t* lv = lvl_base + (size_t)sh.mb[3] * t.out_stride;
+    uint32_t u = 0, u0 = 0, du = 0;
+    bool won = false;
     if (inline_l0) {
-        uint32_t* lv = lvl_base + (size_t)sh.mb[3] * t.out_stride;
         if (threadIdx.x < deg) {
-            const uint32_t u = t.col[a0 + threadIdx.x];
+            u = t.col[a0 + threadIdx.x];
             const uint32_t bit = 1u << (u & 31);
             if (!(atomicOr(&p.vis[u >> 5], bit) & bit)) {
                 __builtin_nontemporal_store(1u, &lv[u]);
                 atomicOr(&p.fb[1][u >> 5], bit);
+                won = true;
                 found = 1;
-                const uint32_t u0 = t.row_ptr[u], du = t.row_ptr[u + 1] - u0;
+                u0 = t.row_ptr[u];
+                du = t.row_ptr[u + 1] - u0;
                 mf = du;
-                if (du > t.heavy_th) {
-                    // a heavy vertex of level 1: its strips are queued now,
-                    // so level 1's own phase walks them (no HEAVY phase)
-                    const uint32_t ns = (du + t.strip - 1) / t.strip;
-                    const uint32_t b = add_relaxed(&t.work->heavy_tail, ns);
-                    for (uint32_t j = 0; j < ns; ++j) {
-                        const uint32_t off = j * t.strip;
-                        if (b + j < t.heavy_cap)
-                            t.heavy[b + j] = make_uint4(0u, u0 + off, du - off < t.strip ? du - off : t.strip, u);
-                    }
-                    strips = ns;
-                }
+                // a heavy vertex of level 1: unless the master step runs
+                // level 1 itself, its strips are queued below, so level 1's
+                // own phase walks them (no HEAVY phase)
+                if (du > t.heavy_th) strips = (du + t.strip - 1) / t.strip;
+            }
+        }
+        if (Small && p.inline_on) {
+            // level 1 as frontier list 0 of the master-step levels (at most
+            // one vertex per thread, within il_cap)
+            const uint32_t F = il_cap(num_waves());
+            const uint32_t cw = won ? 1u : 0u;
+            const uint32_t incl = wave_incl_scan(cw);
+            const uint32_t wtot = bcast(incl, kWave - 1);
+            uint32_t base = 0;
+            if (lane_id() == kWave - 1 && wtot) base = atomicAdd(&sh.il_c[0], wtot);
+            base = bcast(base, kWave - 1);
+            if (won) {
+                const uint32_t pos = base + incl - 1;
+                il_at(sh, pos) = u;
+                il_at(sh, 2 * F + pos) = u0;
+                il_at(sh, 4 * F + pos) = du;
             }
         }
         const uint64_t wf = wave_sum64(found), wm = wave_sum64(mf), ws = wave_sum64(strips);
@@ -890,6 +1253,7 @@ __device__ uint32_t bfs_master_source(const BfsArgs& p, BlockLds& sh, CtxCore* c
         }
     }
     uint32_t res = 0;
+    bool il = false;
     if (threadIdx.x == 0) {
         x.level() = 0;
         x.nf_prev() = 1;
@@ -919,8 +1283,10 @@ __device__ uint32_t bfs_master_source(const BfsArgs& p, BlockLds& sh, CtxCore* c
                 const uint32_t nph = (p.direction_opt && mf * p.alpha > m_u) ? kPhBU : kPhTD;
                 x.nf_prev() = (uint32_t)found;
                 x.level() = 1;
-                res = nph | kFlagAdv | (1u << kRotShift);   // level 1: current = fb[1]
-                if (strips) {
+                res = nph | kFlagAdv | (1u << kRotShift) |   // level 1: current = fb[1]
+                      (Small && p.flist && (mf <= kRecordArcs || !p.direction_opt) ? kFlagRecord : 0u);
+                il = Small && p.inline_on && mf <= (uint64_t)kInlineArcs * blockDim.x;
+                if (strips && !il) {
                     // the strips stay queued for a top-down level 1 (a
                     // bottom-up one does not walk the frontier's lists)
                     x.in_size() = (uint32_t)strips;
@@ -932,8 +1298,54 @@ __device__ uint32_t bfs_master_source(const BfsArgs& p, BlockLds& sh, CtxCore* c
                 }
             }
         }
+        // level 1 is small: the master step runs it (and what follows),
+        // from frontier list 0 (the caller runs the levels)
+        sh.il_go = il ? 1u : 0u;
+        sh.il_v[0] = 0;             // strips placed so far (positions from 0: the list is empty)
+        sh.il_v[1] = 1;             // the list's level
+        sh.il_v[2] = 0;             // rotation: level 1 is all of fb[1], fb[2] is clear
+        sh.il_v[3] = sh.mb[3];      // source index
+        sh.il_v[4] = 0;             // no found lists to gather
+    }
+    __syncthreads();
+    if (!sh.il_go && won && du > t.heavy_th) {
+        const uint32_t ns = (du + t.strip - 1) / t.strip;
+        const uint32_t b = atomicAdd(&sh.il_v[0], ns);
+        for (uint32_t j = 0; j < ns; ++j) {
+            const uint32_t off = j * t.strip;
+            if (b + j < t.heavy_cap) t.heavy[b + j] = make_uint4(0u, u0 + off, du - off < t.strip ? du - off : t.strip, u);
+        }
     }
     return res;
+}
+
+// The small levels a master step runs (all threads of the master
+// workgroup; the way in is in sh.il_*: the frontier in list 0 or in the
+// phase's found lists, its level, rotation and source). Thread 0 publishes
+// the release flags and the transmit block; a gather that cannot take the
+// lists changes nothing. Only the BFS kernel built with small levels runs
+// it: its code in a kernel costs the phases' loops some registers (a few
+// percent on R-MAT), so launches that give every level a barrier use a
+// build without it.
+__device__ __forceinline__ void bfs_small_levels(BlockLds& sh, uint32_t M, uint32_t* vis, uint32_t* fb0, uint32_t* fb1,
+                                              uint32_t* fb2, const uint32_t* col, const uint32_t* row_ptr,
+                                              uint32_t* slots, const uint32_t* flist, uint32_t* lvl_base,
+                                              uint32_t out_stride, uint64_t total_arcs, uint32_t alpha,
+                                              uint32_t direction_opt, uint32_t nroots, Work* work) {
+    const uint32_t nf = __builtin_amdgcn_readfirstlane(sh.il_c[0]);
+    const uint32_t lvl = __builtin_amdgcn_readfirstlane(sh.il_v[1]);
+    const uint32_t r = __builtin_amdgcn_readfirstlane(sh.il_v[2]);
+    const uint32_t root = __builtin_amdgcn_readfirstlane(sh.il_v[3]);
+    const bool gather = __builtin_amdgcn_readfirstlane(sh.il_v[4]) != 0;
+    if (gather && !il_gather(sh, flist, row_ptr, M, nf)) return;
+    const IlArgs q{vis, r == 0 ? fb1 : (r == 1 ? fb2 : fb0), col, row_ptr, slots,
+                   lvl_base + (size_t)root * out_stride, total_arcs, alpha, direction_opt, nroots,
+                   flist != nullptr ? 1u : 0u};
+    const uint32_t res = bfs_inline_levels(q, sh, sh.il_x, nf, lvl, r);
+    if (threadIdx.x == 0) {
+        sh.bar.flags = res;
+        work->store_x(sh.il_x);
+    }
 }
 
 // BFS master step (all threads of the master workgroup): per-level
@@ -941,8 +1353,10 @@ __device__ uint32_t bfs_master_source(const BfsArgs& p, BlockLds& sh, CtxCore* c
 // alpha/beta rule), next source or done. `roots` / `lvl_base`: the sources
 // and the output (the launch's, or a served query's). Returns the release
 // flags.
+template <bool Small = false>
 __device__ __forceinline__ uint32_t bfs_master(const BfsArgs& p, BlockLds& sh, CtxCore* c, uint32_t ph,
-                                               uint32_t cur_flags, const uint32_t* roots, uint32_t* lvl_base) {
+                                               uint32_t cur_flags, const uint32_t* roots, uint32_t* lvl_base,
+                                               uint32_t M) {
     const TraversalArgs& t = p.t;
     Work* wk = t.work;
     // thread 0 loads the transmit block before the slot sums, so both round
@@ -956,15 +1370,15 @@ __device__ __forceinline__ uint32_t bfs_master(const BfsArgs& p, BlockLds& sh, C
     uint64_t tot[2];
     master_sum_slots(sh, t.slots, t.N, tot);
     if (ph == kPhInit) {
-        const uint32_t res = bfs_master_source(p, sh, c, x, roots, lvl_base);
+        const uint32_t res = bfs_master_source<Small>(p, sh, c, x, roots, lvl_base);
         if (threadIdx.x == 0) {
-            wk->store_x(x);
             sh.bar.flags = res;
+            wk->store_x(x);
+            if (sh.il_go) sh.il_x = x;
         }
-        __syncthreads();
-        return sh.bar.flags;
     }
-    if (threadIdx.x == 0) {
+    bool il = false;
+    if (ph != kPhInit && threadIdx.x == 0) {
         uint32_t res = 0;
         const uint32_t r = (cur_flags & kRotMask) >> kRotShift;
         if (ph == kPhStart) {
@@ -1011,22 +1425,52 @@ __device__ __forceinline__ uint32_t bfs_master(const BfsArgs& p, BlockLds& sh, C
                     x.nf_prev() = nf_lvl;
                     x.level() += 1;
                     res = nph | kFlagAdv | (((r + 1) % 3) << kRotShift);
+                    // a frontier with few arcs finds few vertices: its phase
+                    // lists them (top-down-only launches do not sum mf and
+                    // always list)
+                    if (Small && p.flist && (mf_lvl <= kRecordArcs || !p.direction_opt)) res |= kFlagRecord;
+                    // a small level next: the master step may run it (the
+                    // phase's found lists hold the frontier; a HEAVY phase
+                    // rewrote them with its own finds only). The gather
+                    // checks the arcs that top-down-only launches do not sum.
+                    il = Small && p.inline_on && p.flist && (cur_flags & kFlagRecord) && ph != kPhHeavy &&
+                         nf_lvl <= il_cap(num_waves()) && mf_lvl <= (uint64_t)kInlineArcs * blockDim.x;
+                    sh.il_c[0] = nf_lvl;
+                    sh.il_v[1] = x.level();
+                    sh.il_v[2] = r;
+                    sh.il_v[3] = x.root();
+                    sh.il_v[4] = 1;     // the frontier is in the phase's found lists
                 }
             }
         }
-        wk->store_x(x);
         sh.bar.flags = res;
+        sh.il_go = il ? 1u : 0u;
+        // the transmit block as it stands; the levels below work on an
+        // LDS copy (no registers held through them) and store it again
+        wk->store_x(x);
+        if (il) sh.il_x = x;
     }
     __syncthreads();
+    if constexpr (Small) {
+        // small levels in the master step (one call site for both ways in)
+        if (sh.il_go)
+            bfs_small_levels(sh, M, p.vis, p.fb[0], p.fb[1], p.fb[2], t.col, t.row_ptr, t.slots, p.flist,
+                             lvl_base, t.out_stride, p.total_arcs, p.alpha, p.direction_opt, t.nroots, wk);
+        __syncthreads();
+    }
     return sh.bar.flags;
 }
 
-// Follow the transmitted BFS state locally after a barrier.
-__device__ __forceinline__ void bfs_follow(uint32_t ph, uint32_t nflags, uint32_t& level, uint32_t& root) {
+// Follow the transmitted BFS state locally after a barrier (JUMP: the
+// master step ran levels itself, the level is the transmit block's).
+__device__ __forceinline__ void bfs_follow(uint32_t ph, uint32_t nflags, uint32_t& level, uint32_t& root,
+                                           const Work* wk) {
     const uint32_t nph = nflags & kPhMask;
     if (nph == kPhInit) {
         if (ph != kPhStart) root += 1;
         level = 0;
+    } else if (nflags & kFlagJump) {
+        level = __hip_atomic_load(&wk->x.level, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else if (ph == kPhInit) {
         level = (nflags & kFlagAdv) ? 1u : 0u;   // ADV: the master step expanded level 0 itself
     } else if (nflags & kFlagAdv) {

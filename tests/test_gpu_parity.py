@@ -60,6 +60,7 @@ def modes(coop):
         "coop": coop.make_opts(coop.COOP_MODE_COOP),
         "coop_host": coop.make_opts(coop.COOP_MODE_COOP, flags=coop.COOP_F_HOST_SCHEDULE),
         "coop_topdown": coop.make_opts(coop.COOP_MODE_COOP, flags=coop.COOP_F_TOP_DOWN_ONLY),
+        "coop_levels": coop.make_opts(coop.COOP_MODE_COOP, flags=coop.COOP_F_LEVEL_BARRIERS),
     }
 
 
@@ -113,6 +114,35 @@ def test_bfs_rmat_heavy_strips(rt, coop_mod, gg, th, strip):
         assert rc == 0, coop_mod.coop_strerror(rc)
         assert np.array_equal(as_u32(lv), exp), mode
         say(f"  {mode}: td={st['td_levels']} bu={st['bu_levels']} heavy={st['heavy_phases']} arcs={st['arcs']}")
+    dg.release()
+
+
+@pytest.mark.parametrize("name", ["path", "tree", "er4096", "grid", "rmat14", "rmat16"])
+def test_bfs_master_step_levels(rt, coop_mod, gg, name):
+    """Small top-down levels run by the master step give the levels of the
+    launch that gives every level its own phase and barrier, for every
+    source, with the same level count and fewer barriers; narrow launches
+    (small LDS lists, more workgroups than the master can gather) too."""
+    c = coop_mod
+    g = {"path": gg.path(3000), "tree": gg.binary_tree(4095), "er4096": gg.er(4096, 8, 1),
+         "grid": gg.grid(40, 50), "rmat14": gg.rmat(14, 16, seed=3), "rmat16": gg.rmat(16, 16, seed=6)}[name]
+    roots = gg.sources(g, 11, 6)
+    say(f"bfs master-step levels {name} roots={roots.tolist()}")
+    dg = rt.graph(g)
+    for mode in (c.COOP_MODE_PLAIN, c.COOP_MODE_COOP):
+        for ng, gs in ((0, 1024), (0, 256), (24, 64)):
+            res = {}
+            for flags in (0, c.COOP_F_LEVEL_BARRIERS):
+                o = c.make_opts(mode, flags=flags, num_groups=ng, group_size=gs)
+                rc, lv, st = rt.bfs(dg, roots, o)
+                assert rc == 0, c.coop_strerror(rc)
+                check_rows(lv.reshape(-1), roots, g)
+                res[flags] = st
+            a, b = res[0], res[c.COOP_F_LEVEL_BARRIERS]
+            say(f"  mode={mode} groups={ng}x{gs}: levels {a['levels']} / {b['levels']}, "
+                f"barriers {a['barriers']} / {b['barriers']}")
+            assert a["levels"] == b["levels"]
+            assert a["barriers"] <= b["barriers"]
     dg.release()
 
 
