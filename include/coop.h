@@ -106,10 +106,15 @@ enum {
     COOP_F_REGULAR_BARRIER = 16u, /* the paper's regular resizing barrier: at most one workgroup
                                      leaves per barrier, instead of the query barrier's W at
                                      once (section 4.2); for gather-time comparisons */
-    COOP_F_LEVEL_BARRIERS = 32u   /* BFS: every level is a phase of all workgroups with its own
+    COOP_F_LEVEL_BARRIERS = 32u,  /* BFS: every level is a phase of all workgroups with its own
                                      barrier; by default a master step runs small levels itself,
                                      top-down (frontier of at most 2048 vertices and 4 arcs per
                                      thread), with the same result */
+    COOP_F_TEST_LOSE_ONE = 64u    /* test of the barrier's bounded wait (coop_barrier_bench only):
+                                     the last workgroup leaves after the first barrier without
+                                     being killed, as a lost workgroup would, so the others'
+                                     waits run out after watchdog_ns and the launch ends with
+                                     COOP_E_TIMEOUT (every workgroup exits normally) */
 };
 
 typedef struct coop_launch_opts {

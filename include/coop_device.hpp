@@ -60,6 +60,7 @@ constexpr uint32_t kModePark = 2u;          // killed workgroups re-queue as joi
 constexpr uint32_t kModeRandomSched = 4u;   // device-side seeded kill/fork schedule
 constexpr uint32_t kModeRegular = 8u;       // regular resizing barrier: at most one kill per barrier
 constexpr uint32_t kModeRelayTarget = 16u;  // the host target is relayed into Ctx::T_seen by the kernel itself
+constexpr uint32_t kModeLoseOne = 32u;      // test: the barrier benchmark's last workgroup goes missing
 
 // error codes written to ctx->error (match COOP_E_* of coop.h)
 constexpr int32_t kErrInvalid = -1;

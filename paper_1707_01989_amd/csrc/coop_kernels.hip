@@ -169,10 +169,15 @@ __device__ void barrier_bench_body(const BarrierBenchArgs& p, bool joiner_grid) 
     Ctx* c = p.ctx;
     Group g(c, p.cfg, sh.bar);
     if (!coop_start<Coop>(g, joiner_grid)) return;
+    bool first = true;
     while (coop_resizing_global_barrier<Coop>(g, [&](uint32_t, uint32_t ne) -> uint32_t {
         if (ne == 1 && threadIdx.x == 0) c->t_start = now_ticks();
         return ne > p.iters ? kFlagDone : 0u;
     })) {
+        // test of the bounded wait: the last member goes missing (no kill,
+        // no leave): the others' next waits run out on the watchdog
+        if ((p.cfg.mode & kModeLoseOne) && first && coop_get_group_id(g) + 1 == coop_get_num_groups(g)) return;
+        first = false;
     }
 }
 

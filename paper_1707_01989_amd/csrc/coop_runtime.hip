@@ -319,6 +319,7 @@ int size_launch(coop_rt* rt, const coop_launch_opts* o, Sizing* s, uint32_t min_
         if (o->flags & COOP_F_RANDOM_SCHEDULE) s->mode |= coop::kModeRandomSched;
         if (o->flags & COOP_F_REGULAR_BARRIER) s->mode |= coop::kModeRegular;
     }
+    if (o->flags & COOP_F_TEST_LOSE_ONE) s->mode |= coop::kModeLoseOne;
     s->sched_p16 = (uint32_t)std::lround(std::min(1.0, std::max(0.0, o->sched_p)) * 65536.0);
     const uint64_t wd = o->watchdog_ns ? o->watchdog_ns : kDefaultWatchdogNs;
     s->watchdog_ticks = wd * (uint64_t)rt->wall_khz / 1000000ull;

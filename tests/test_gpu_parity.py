@@ -5,6 +5,7 @@ equality, under plain launches, cooperative launches, and cooperative
 launches under seeded kill/fork schedules (any schedule must give the
 never-resizing schedule's result)."""
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -432,6 +433,27 @@ def test_barrier_bench(rt, coop_mod, mode):
     say(f"  {ns:.0f} ns/barrier, grid={st['grid']} M={st['final_groups']}")
     assert st["barriers"] == 2001 and ns > 0
     assert st["final_groups"] == st["grid"]
+
+
+@pytest.mark.parametrize("mode", ["plain", "coop"])
+def test_barrier_watchdog_ends_a_launch_that_lost_a_workgroup(rt, coop_mod, mode):
+    """A workgroup that goes missing (the last one leaves after the first
+    barrier, made to from the host) must not hang the launch: every other
+    workgroup's bounded wait runs out after the watchdog time, the launch
+    ends with COOP_E_TIMEOUT, and the runtime goes on working."""
+    c = coop_mod
+    m = c.COOP_MODE_PLAIN if mode == "plain" else c.COOP_MODE_COOP
+    o = c.make_opts(m, flags=c.COOP_F_TEST_LOSE_ONE, num_groups=16, group_size=256, watchdog_ns=50_000_000)
+    say(f"barrier watchdog {mode}")
+    t0 = time.time()
+    with pytest.raises(c.CoopError) as ei:
+        c.coop_barrier_bench(rt.rt, 100, o)
+    took = time.time() - t0
+    say(f"  {ei.value} after {took:.3f} s")
+    assert ei.value.code == c.COOP_E_TIMEOUT
+    assert took < 5.0
+    ns, st = c.coop_barrier_bench(rt.rt, 50, c.make_opts(m, num_groups=16, group_size=256))
+    assert st["barriers"] == 51 and st["error"] == 0
 
 
 def test_plain_single_step_without_flags_in_lds(rt, coop_mod, gg):
