@@ -183,8 +183,10 @@ typedef struct coop_stats {
  * another inside one persistent launch. Levels alternate between top-down
  * (expand the frontier) and bottom-up (unvisited vertices look for a parent
  * in the frontier) by the edge-count rule of Beamer et al. (SC 2012) unless
- * COOP_F_TOP_DOWN_ONLY is set; the result is the same either way. d_roots holds nroots source
- * vertices (device memory). d_level receives, for source r, n levels at
+ * COOP_F_TOP_DOWN_ONLY is set; the result is the same either way. A level
+ * small enough for one workgroup runs inside a barrier's master step unless
+ * COOP_F_LEVEL_BARRIERS is set (again the same result; fewer barriers).
+ * d_roots holds nroots source vertices (device memory). d_level receives, for source r, n levels at
  * d_level + r * out_stride (out_stride = 0: every source overwrites the same
  * n entries). Unreached vertices get 0xFFFFFFFF. The kernel checks each source
  * when it starts it: a source >= n fails the launch with COOP_E_INVALID before
@@ -200,8 +202,9 @@ int coop_bfs(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_t
  * this:
  *  - Nothing is allocated (no device or pinned memory, no events, no
  *    handle). Every scratch buffer of the launch (context, transmit block,
- *    per-workgroup statistics, heavy-strip list, visited and three frontier
- *    bitmaps: about n/2 bytes plus 130 KiB) lives in one static device array
+ *    per-workgroup statistics and found lists, heavy-strip list, visited and
+ *    three frontier bitmaps: about n/2 bytes plus 200 KiB at 256
+ *    workgroups) lives in one static device array
  *    of COOP_NOALLOC_SCRATCH_BYTES per GPU, whose address coop_init looks up.
  *    A call needing more returns COOP_E_TOO_BIG and enqueues nothing (up to
  *    about 60 million vertices fit).
