@@ -27,7 +27,8 @@ struct Xfer {
     uint32_t td_levels;        // BFS levels run top-down
     uint32_t bu_levels;        // BFS levels run bottom-up
     uint32_t heavy_phases;     // HEAVY phases
-    uint32_t pad[2];
+    uint32_t sum_found;        // BFS: the slots' found / mf sums (low 32 bits) the last master step saw
+    uint32_t sum_mf;
 };
 
 __host__ __device__ inline uint64_t join64(uint32_t lo, uint32_t hi) { return ((uint64_t)hi << 32) | lo; }
@@ -51,6 +52,8 @@ struct XferR {
     __device__ uint32_t& td_levels() { return c.w; }
     __device__ uint32_t& bu_levels() { return d.x; }
     __device__ uint32_t& heavy_phases() { return d.y; }
+    __device__ uint32_t& sum_found() { return d.z; }
+    __device__ uint32_t& sum_mf() { return d.w; }
 };
 
 // Per-launch work counters and the transmit block, on separate cache lines.

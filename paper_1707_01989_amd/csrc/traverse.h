@@ -147,9 +147,10 @@ __device__ void stats_to_lds(BlockLds& sh, const Stats& s) {
 }
 
 // Add the workgroup's phase statistics to its slot (after a __syncthreads);
-// fire-and-forget atomics, so nobody waits for the round trip. Fields 0 and 1
-// are per level and only kept when the master step reads them (BFS);
-// fields 2, 3, 4 and the found total are cumulative.
+// fire-and-forget atomics, so nobody waits for the round trip. Every field
+// only grows: fields 0 and 1 (found, mf) are kept only when the master step
+// reads them (BFS), which takes a level's values as the difference from
+// the sums it saw at the previous level.
 __device__ void acc_to_slot(BlockLds& sh, uint32_t* slots, uint32_t id, bool per_level = true) {
     if (threadIdx.x < 5) {
         uint64_t* s = reinterpret_cast<uint64_t*>(slots + (size_t)id * kSlotWords);
@@ -162,20 +163,16 @@ __device__ void acc_to_slot(BlockLds& sh, uint32_t* slots, uint32_t id, bool per
     }
 }
 
-// Master step helper: sum the per-level fields (found, mf) of every slot
-// (all N logical ids) and clear them. Called by all threads of the master
-// workgroup; tot[0..1] valid in all.
-__device__ void master_sum_slots(BlockLds& sh, uint32_t* slots, uint32_t N, uint64_t* tot) {
+// Master step helper: sum fields 0 and 1 (found, mf) of every slot (all N
+// logical ids). They are never cleared (a clear would leave dirty lines for
+// the release to write back); the caller subtracts the previous sums.
+// Called by all threads of the master workgroup; tot[0..1] valid in all.
+__device__ void master_sum_slots(BlockLds& sh, const uint32_t* slots, uint32_t N, uint64_t* tot) {
     uint64_t part[2] = {0, 0};
     for (uint32_t i = threadIdx.x; i < N; i += blockDim.x) {
-        uint64_t* s = reinterpret_cast<uint64_t*>(slots + (size_t)i * kSlotWords);
-        const uint64_t a = s[0], b = s[1];
-        if (a | b) {
-            part[0] += a;
-            part[1] += b;
-            s[0] = 0;
-            s[1] = 0;
-        }
+        const uint64_t* s = reinterpret_cast<const uint64_t*>(slots + (size_t)i * kSlotWords);
+        part[0] += s[0];
+        part[1] += s[1];
     }
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
@@ -1385,9 +1382,15 @@ __device__ __forceinline__ uint32_t bfs_master(const BfsArgs& p, BlockLds& sh, C
             x.root() = 0;
             res = kPhInit;
         } else {
-            // level partials (a TD level may be followed by a HEAVY phase)
-            const uint64_t mf_lvl = join64(x.lvl_mf_lo(), x.lvl_mf_hi()) + tot[1];
-            const uint32_t nf_lvl = x.lvl_found() + (uint32_t)tot[0];
+            // this phase's finds: the growth of the slot sums (modulo 2^32:
+            // a level finds fewer vertices and arcs than that); level
+            // partials (a TD level may be followed by a HEAVY phase)
+            const uint32_t d_found = (uint32_t)tot[0] - x.sum_found();
+            const uint32_t d_mf = (uint32_t)tot[1] - x.sum_mf();
+            x.sum_found() = (uint32_t)tot[0];
+            x.sum_mf() = (uint32_t)tot[1];
+            const uint64_t mf_lvl = join64(x.lvl_mf_lo(), x.lvl_mf_hi()) + d_mf;
+            const uint32_t nf_lvl = x.lvl_found() + d_found;
             if (ph == kPhTD && hs > 0) {
                 x.in_size() = hs;
                 wk->heavy_tail = 0;
