@@ -549,57 +549,97 @@ __device__ void bfs_bottom_up(const BfsArgs& p, WaveLds& wl, const uint32_t* cur
             cand &= cand - 1;
         }
         __builtin_amdgcn_wave_barrier();
+        const bool dense = p.first2 != nullptr;     // skewed graphs only (see graph_prep)
+        uint32_t pend = total;                      // candidates left for the probe slots
+        if (dense) {
+            // first pass on a skewed graph: every candidate's first two
+            // neighbours from the dense array, 4 x 64 candidates at a time
+            // (consecutive candidates read adjacent entries, and the loads
+            // of the four are in flight together); most candidates end
+            // here, the others go back to the list for the probe slots,
+            // which start at their third arc
+            uint32_t nrem = 0;
+            for (uint32_t base = 0; base < total; base += 4 * kWave) {
+                uint32_t vv[4], a0[4], a1[4];
+                uint2 f[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t i = base + j * kWave + l;
+                    vv[j] = i < total ? list[i] : 0xFFFFFFFFu;
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    a0[j] = a1[j] = 0;
+                    f[j] = make_uint2(0, 0);
+                    if (vv[j] != 0xFFFFFFFFu) {
+                        f[j] = p.first2[vv[j]];
+                        a0[j] = p.t.row_ptr[vv[j]];
+                        a1[j] = p.t.row_ptr[vv[j] + 1];
+                    }
+                }
+                bool hit[4], more[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t d = a1[j] - a0[j];        // >= 1 for a candidate
+                    hit[j] = false;
+                    more[j] = false;
+                    if (vv[j] != 0xFFFFFFFFu) {
+                        hit[j] = ((cur[f[j].x >> 5] >> (f[j].x & 31)) & 1u) != 0;
+                        if (d > 1) hit[j] |= ((cur[f[j].y >> 5] >> (f[j].y & 31)) & 1u) != 0;
+                        more[j] = !hit[j] && d > 2;
+                        st.arcs += d < 2 ? d : 2u;
+                        st.rows += 1;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (hit[j]) bu_mark(p, fw, level, vv[j], next_level, b * kBlockWords, a1[j] - a0[j], st);
+                    // the misses with more arcs, in list order; the entries
+                    // written lie below the ones this round has read
+                    const uint64_t mask = __ballot(more[j]);
+                    if (more[j]) list[nrem + mbcnt(mask)] = vv[j];
+                    nrem += (uint32_t)__popcll(mask);
+                }
+            }
+            pend = nrem;
+            __builtin_amdgcn_wave_barrier();
+        }
         // Two probe slots per lane; a slot that resolves its candidate takes
         // the next one from the list, so the wave keeps 128 chains busy
         // instead of waiting for the slowest lane of a batch.
         uint32_t next = 0, nlong = 0;
         uint32_t v[2] = {0, 0}, k[2] = {0, 0}, e[2] = {0, 0}, s0[2] = {0, 0}, rounds[2] = {0, 0};
-        uint2 f2[2] = {make_uint2(0, 0), make_uint2(0, 0)};
-        const bool dense = p.first2 != nullptr;     // skewed graphs only (see graph_prep)
-        bool act[2] = {false, false}, fresh[2] = {false, false};
+        bool act[2] = {false, false};
         for (;;) {
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const bool need = !act[c];
                 const uint64_t mask = __ballot(need);
-                if (next < total && mask) {
+                if (next < pend && mask) {
                     const uint32_t idx = next + mbcnt(mask);
-                    if (need && idx < total) {
+                    if (need && idx < pend) {
                         v[c] = list[idx];
                         act[c] = true;
                         s0[c] = k[c] = p.t.row_ptr[v[c]];
                         e[c] = p.t.row_ptr[v[c] + 1];
+                        if (dense) k[c] += 2;            // the first pass probed two arcs
                         rounds[c] = 0;
-                        fresh[c] = dense;                // the dense first-two probe comes first
-                        if (dense) f2[c] = p.first2[v[c]];
                         st.rows += 1;
                     }
                     next += (uint32_t)__popcll(mask);
                 }
             }
             if (!__ballot(act[0] || act[1])) break;
-            // on a skewed graph a candidate's first round probes its first
-            // two neighbours from the dense array (the candidates of a block
-            // sit side by side there); every other round probes an aligned
-            // 4-arc chunk of col_bu
+            // every round probes an aligned 4-arc chunk of col_bu
             uint4 q[2];
 #pragma unroll
-            for (int c = 0; c < 2; ++c)
-                q[c] = (act[c] && !fresh[c]) ? probe_chunk(p.col_bu, k[c]) : make_uint4(0, 0, 0, 0);
+            for (int c = 0; c < 2; ++c) q[c] = act[c] ? probe_chunk(p.col_bu, k[c]) : make_uint4(0, 0, 0, 0);
             bool defer[2] = {false, false};
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 if (!act[c]) continue;
                 uint32_t got;
-                bool hit;
-                if (fresh[c]) {
-                    fresh[c] = false;
-                    got = e[c] - k[c] < 2 ? e[c] - k[c] : 2u;
-                    hit = ((cur[f2[c].x >> 5] >> (f2[c].x & 31)) & 1u) != 0;
-                    if (got == 2) hit |= ((cur[f2[c].y >> 5] >> (f2[c].y & 31)) & 1u) != 0;
-                } else {
-                    hit = probe_hits(cur, q[c], k[c], e[c], got);
-                }
+                const bool hit = probe_hits(cur, q[c], k[c], e[c], got);
                 st.arcs += got;
                 k[c] += got;
                 rounds[c] += 1;
