@@ -285,6 +285,13 @@ __device__ __forceinline__ bool counts_changed(const Member& m, const Member& n)
     return m.epoch == 0 || (m.flags & kFlagFlat) || n.M != m.M || (n.flags & kFlagRenum);
 }
 
+// The scheduler words a master step reads (loaded while the algorithm's
+// master step runs).
+struct MasterPre {
+    int32_t err;
+    uint32_t tail, T_seen, join_head, T_dev, nb, kills, forks, resizes, min_M, max_M, tail_prev;
+};
+
 // Workgroup-shared state of the barrier.
 struct BarrierLds {
     Member member;
@@ -511,17 +518,24 @@ __device__ inline void startup_wait(Ctx* c, const Cfg cfg) {
         __builtin_amdgcn_s_sleep(2);
 }
 
-// Inputs of the scheduler part of the master step, loaded by thread 0 as
-// soon as its workgroup knows it is the master, so that their round trip
+// The thread that loads the scheduler words and runs the scheduler's
+// decisions. In a cooperative launch: the last wave's first lane, a wave the
+// algorithms' master steps leave idle (a wave waits for its loads in issue
+// order, so from thread 0 the dozen scheduler loads held up the master
+// step's own: 0.4 us of each SSSP round). A plain launch loads two words and
+// keeps thread 0 (one wave fewer between the master step and the release).
+template <bool Coop>
+__device__ __forceinline__ uint32_t sched_thread() {
+    return Coop ? blockDim.x - 64u : 0u;
+}
+
+// Inputs of the scheduler part of the master step, loaded by the
+// scheduling thread as soon as its workgroup knows it is the master, so
+// that their round trip
 // overlaps the algorithm's own master step. An error raised by another
 // workgroup after this load is caught at the next barrier (the error word
 // stays set); the algorithm's master step reports its own errors in the
 // flags it returns.
-struct MasterPre {
-    int32_t err;
-    uint32_t tail, T_seen, join_head, T_dev, nb, kills, forks, resizes, min_M, max_M, tail_prev;
-};
-
 template <bool Coop, class C>
 __device__ __forceinline__ MasterPre master_prefetch(C* c, const Cfg cfg, bool relay_self) {
     MasterPre p;
@@ -554,8 +568,11 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
                                        uint64_t t_in, const MasterPre& pre, bool resize) {
     const uint32_t ne = m.epoch + 1;
     uint32_t T_dev = 0, nb = 0, kills = 0, forks = 0, resizes = 0, min_M = 0, max_M = 0;
-    uint32_t kmax0 = 0, head0 = 0, drain0 = 0;     // thread 0's copies of what it shares in LDS
-    if (threadIdx.x == 0) {
+    uint32_t kmax0 = 0, head0 = 0, drain0 = 0;     // the scheduling thread's copies of what it shares in LDS
+    // one thread decides and publishes: the thread that loaded the
+    // scheduler words (MasterPre) while the algorithm's master step ran
+    const uint32_t sched = sched_thread<Coop>();
+    if (threadIdx.x == sched) {
         const int32_t err = pre.err;
         const uint32_t tail = pre.tail;
         const uint32_t T_seen = pre.T_seen;
@@ -621,7 +638,7 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
                    !(flags & (kFlagDone | kFlagAbort | kFlagRenum | kFlagFlat)) && kmax == 0 && drain0 == 0 &&
                    T >= m.M && T_dev == pre.T_dev) ? 1u : 0u;
     }
-    // every thread reads what thread 0 just shared (b.flags decides below
+    // every thread reads what the scheduling thread just shared (b.flags decides below
     // whether the whole workgroup recounts the members per XCD, a block with
     // workgroup barriers inside): in every launch mode, since an
     // algorithm's single step need not have left the flags in b.flags, and
@@ -630,7 +647,7 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
     // DONE there and thread 0, and miscounted the arrivals)
     __syncthreads();
     if (b.quiet) {
-        if (threadIdx.x == 0) {
+        if (threadIdx.x == sched) {
             c->barriers = nb + 1;
             if (Coop) c->tail_prev = pre.tail;
             if (cfg.trace && nb < cfg.trace_cap) {
@@ -813,7 +830,9 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
                     atomicAdd(&b.xcnt[(ld_relaxed(&c->engine_of[t]) / cfg.ses) % kMaxXcds], 1u);
             }
             __syncthreads();
-            if (threadIdx.x == 0) {
+            // the scheduling thread stores the counts: its release below
+            // orders its own stores only
+            if (threadIdx.x == sched) {
                 Ctx* cx = reinterpret_cast<Ctx*>(c);
                 uint32_t groups = 0;
                 for (uint32_t x = 0; x < kMaxXcds; ++x) {
@@ -824,8 +843,8 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
             }
         }
     }
-    if (threadIdx.x == 0) {
-        // `flags` is still the value thread 0 shared as b.flags
+    if (threadIdx.x == sched) {
+        // `flags` is still the value the scheduling thread shared as b.flags
         uint32_t Mn = m.M;
         // newcomers (admitted or started up here) have not recorded their
         // XCD yet: the next interval arrives per workgroup
@@ -928,8 +947,8 @@ __device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, Ma
     if (b.is_master) {
         // master step: everybody else is parked in the barrier
         const uint64_t t_in = now_ticks();
-        MasterPre pre;                          // thread 0's
-        if (threadIdx.x == 0) pre = master_prefetch<Coop>(c, cfg, m.M == 1);
+        MasterPre pre;
+        if (threadIdx.x == sched_thread<Coop>()) pre = master_prefetch<Coop>(c, cfg, m.M == 1);
         const uint32_t flags = master_fn(m.M, m.epoch + 1);
         master_schedule<Coop, C>(c, cfg, m, b, flags, t_in, pre, resize);
     } else if (Coop && cfg.host && m.id == 0 && threadIdx.x == kRelayThread) {
