@@ -1713,6 +1713,11 @@ __device__ __forceinline__ uint64_t key_hash(uint64_t seed, uint32_t v) {
     return splitmix64(seed + (uint64_t)v * kGamma);
 }
 
+// Arcs a lane takes at a time in the colouring walks: their loads are all
+// issued before any is used (a lane's walk of a 32-arc list is then four
+// round trips per step instead of thirty-two).
+constexpr uint32_t kColorBatch = 8;
+
 // Decide one vertex whose higher-priority neighbours are all final: colour =
 // smallest colour none of them has (or MIS membership).
 __device__ __forceinline__ void color_vertex(const ColorArgs& p, uint32_t v, bool valid, Stats& st) {
@@ -1723,20 +1728,39 @@ __device__ __forceinline__ void color_vertex(const ColorArgs& p, uint32_t v, boo
     st.arcs += a1 - a0;
     if (p.mis) {
         bool blocked = false;
-        for (uint32_t e = a0; e < a1 && !blocked; ++e) {
-            const uint32_t u = p.t.col[e];
-            if (key_higher(key_hash(p.prio_seed, u), u, hv, v)) blocked = p.in_set_out[u] != 0;
+        for (uint32_t e0 = a0; e0 < a1 && !blocked; e0 += kColorBatch) {
+            uint32_t u[kColorBatch];
+            uint8_t in[kColorBatch];
+#pragma unroll
+            for (uint32_t j = 0; j < kColorBatch; ++j) u[j] = e0 + j < a1 ? p.t.col[e0 + j] : 0xFFFFFFFFu;
+#pragma unroll
+            for (uint32_t j = 0; j < kColorBatch; ++j) {
+                in[j] = 0;
+                if (u[j] != 0xFFFFFFFFu && key_higher(key_hash(p.prio_seed, u[j]), u[j], hv, v))
+                    in[j] = p.in_set_out[u[j]];
+            }
+#pragma unroll
+            for (uint32_t j = 0; j < kColorBatch; ++j) blocked |= in[j] != 0;
         }
         p.in_set_out[v] = blocked ? 0 : 1;
     } else {
         uint32_t base = 0, c = 0;
         for (;;) {
             uint64_t used = 0;
-            for (uint32_t e = a0; e < a1; ++e) {
-                const uint32_t u = p.t.col[e];
-                if (key_higher(key_hash(p.prio_seed, u), u, hv, v)) {
-                    const uint32_t cu = p.colour_out[u] - base;
-                    if (cu < 64) used |= 1ull << cu;
+            for (uint32_t e0 = a0; e0 < a1; e0 += kColorBatch) {
+                uint32_t u[kColorBatch], cu[kColorBatch];
+#pragma unroll
+                for (uint32_t j = 0; j < kColorBatch; ++j) u[j] = e0 + j < a1 ? p.t.col[e0 + j] : 0xFFFFFFFFu;
+#pragma unroll
+                for (uint32_t j = 0; j < kColorBatch; ++j) {
+                    cu[j] = 0xFFFFFFFFu;           // no colour is that large
+                    if (u[j] != 0xFFFFFFFFu && key_higher(key_hash(p.prio_seed, u[j]), u[j], hv, v))
+                        cu[j] = p.colour_out[u[j]];
+                }
+#pragma unroll
+                for (uint32_t j = 0; j < kColorBatch; ++j) {
+                    const uint32_t d = cu[j] - base;
+                    if (cu[j] != 0xFFFFFFFFu && d < 64) used |= 1ull << d;
                 }
             }
             if (~used) {
@@ -1750,7 +1774,9 @@ __device__ __forceinline__ void color_vertex(const ColorArgs& p, uint32_t v, boo
 }
 
 // Release the lower-priority neighbours of v; one whose count of undecided
-// higher neighbours reaches 0 is queued for the next round.
+// higher neighbours reaches 0 is queued for the next round. A lane takes
+// kColorBatch arcs at a time: their loads, then their decrements, issued
+// back to back.
 __device__ __forceinline__ void release_lower(const ColorArgs& p, uint32_t v, bool valid, WaveLds& w,
                                               uint32_t* out_tail, uint32_t* out, Stats& st) {
     const uint64_t hv = valid ? key_hash(p.prio_seed, v) : 0;
@@ -1759,20 +1785,25 @@ __device__ __forceinline__ void release_lower(const ColorArgs& p, uint32_t v, bo
     for (;;) {
         const bool more = e < a1;
         if (!__ballot(more)) break;
-        bool win = false;
-        uint32_t u = 0;
-        if (more) {
-            u = p.t.col[e];
-            if (!key_higher(key_hash(p.prio_seed, u), u, hv, v)) {
-                const uint32_t old = __hip_atomic_fetch_sub(&p.pending[u], 1u, __ATOMIC_RELAXED,
-                                                            __HIP_MEMORY_SCOPE_AGENT);
-                win = old == 1;
-            }
-            ++e;
+        uint32_t u[kColorBatch], old[kColorBatch];
+        bool lower[kColorBatch];
+#pragma unroll
+        for (uint32_t j = 0; j < kColorBatch; ++j) u[j] = e + j < a1 ? p.t.col[e + j] : 0xFFFFFFFFu;
+#pragma unroll
+        for (uint32_t j = 0; j < kColorBatch; ++j) {
+            lower[j] = u[j] != 0xFFFFFFFFu && !key_higher(key_hash(p.prio_seed, u[j]), u[j], hv, v);
+            old[j] = 0;
+            if (lower[j])
+                old[j] = __hip_atomic_fetch_sub(&p.pending[u[j]], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        st.found += win ? 1u : 0u;
-        wave_push(w, win, u);
-        if (w.out_n > kFlushAt) wave_flush(w, out_tail, out);
+#pragma unroll
+        for (uint32_t j = 0; j < kColorBatch; ++j) {
+            const bool win = lower[j] && old[j] == 1;
+            st.found += win ? 1u : 0u;
+            wave_push(w, win, u[j]);
+            if (w.out_n > kFlushAt) wave_flush(w, out_tail, out);
+        }
+        e += kColorBatch;
     }
 }
 
@@ -1802,9 +1833,14 @@ __device__ __forceinline__ void color_phase(const ColorArgs& p, BlockLds& sh, ui
             uint32_t cnt = 0;
             if (valid) {
                 const uint64_t hv = key_hash(p.prio_seed, v);
-                for (uint32_t e = t.row_ptr[v]; e < t.row_ptr[v + 1]; ++e) {
-                    const uint32_t x = t.col[e];
-                    cnt += key_higher(key_hash(p.prio_seed, x), x, hv, v) ? 1u : 0u;
+                const uint32_t a1 = t.row_ptr[v + 1];
+                for (uint32_t e0 = t.row_ptr[v]; e0 < a1; e0 += kColorBatch) {
+                    uint32_t x[kColorBatch];
+#pragma unroll
+                    for (uint32_t j = 0; j < kColorBatch; ++j) x[j] = e0 + j < a1 ? t.col[e0 + j] : 0xFFFFFFFFu;
+#pragma unroll
+                    for (uint32_t j = 0; j < kColorBatch; ++j)
+                        cnt += (x[j] != 0xFFFFFFFFu && key_higher(key_hash(p.prio_seed, x[j]), x[j], hv, v)) ? 1u : 0u;
                 }
                 p.pending[v] = cnt;
             }
