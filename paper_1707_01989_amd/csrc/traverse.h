@@ -943,7 +943,7 @@ __device__ __forceinline__ void bfs_phase(const BfsArgs& p, BlockLds& sh, uint32
 // The lists live in the master's wave output buffers (idle in a master
 // step): two frontier lists, the first arc of each vertex and its degree
 // (then degree prefix), each il_cap entries, indexed through il_at.
-constexpr uint32_t kInlineArcs = 4;      // arcs per thread of the master workgroup per level
+constexpr uint32_t kInlineArcs = 3;      // arcs per thread of the master workgroup per level
 constexpr uint32_t kInlineLevels = 16;   // levels per master step at most (a barrier, and its
                                          // offer_kill, still comes after that many)
 
