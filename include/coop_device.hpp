@@ -290,6 +290,10 @@ __device__ __forceinline__ bool counts_changed(const Member& m, const Member& n)
 struct MasterPre {
     int32_t err;
     uint32_t tail, T_seen, join_head, T_dev, nb, kills, forks, resizes, min_M, max_M, tail_prev;
+    // the scheduler's decision for a barrier after which the kernel goes on
+    // (master_decide); master_schedule sets it aside when the algorithm's
+    // flags end the kernel
+    uint32_t T, T_dev_new, M0, kmax, drain, quiet;
 };
 
 // Workgroup-shared state of the barrier.
@@ -560,84 +564,106 @@ __device__ __forceinline__ MasterPre master_prefetch(C* c, const Cfg cfg, bool r
     return p;
 }
 
+// The scheduler's decision (scheduling thread, from the words master_prefetch
+// loaded) for a barrier after which the kernel goes on: the target, the
+// start-up cohort, how many waiting joiners to admit or pass, and whether
+// the barrier is quiet. In a cooperative launch the scheduling thread, in
+// a wave the algorithms' master steps leave idle, takes it while their
+// master step runs (its loads are the first thing it waits for); a plain
+// launch decides little and keeps it after the master step, in thread 0.
+template <bool Coop, class C>
+__device__ __forceinline__ void master_decide(C* c, const Cfg cfg, const Member& m, MasterPre& p, bool resize) {
+    const uint32_t ne = m.epoch + 1;
+    // a barrier that may not resize is one whose fork admits nobody and
+    // whose kill claims nobody (k = 0 and the Kill-No-Op rule)
+    const bool live = Coop && resize && !p.err;
+    uint32_t T_dev = p.T_dev;
+    uint32_t T = cfg.N;
+    if (live) {
+        if (cfg.mode & kModeRandomSched) {
+            const uint64_t h = splitmix64(cfg.sched_seed + (uint64_t)ne * 0x9E3779B97F4A7C15ull);
+            if ((uint32_t)(h & 0xFFFFu) < cfg.sched_p16) T_dev = 1u + (uint32_t)((h >> 16) % cfg.N);
+            T = T_dev ? T_dev : cfg.N;      // no draw yet: nothing competes
+        } else if (cfg.host) {
+            T = p.T_seen;
+        }
+        if (T < 1u) T = 1u;
+        if (T > cfg.N) T = cfg.N;
+    }
+    // start-up admission (the first barrier of a cooperative launch): the
+    // launch's tickets drawn so far (every arrival drew one before it
+    // arrived), at most the target, become ids 0 .. M0-1 (the members
+    // before this barrier's forks); each reads M0 after the release
+    uint32_t M0 = m.M;
+    if (live && m.epoch == 0) {
+        const uint32_t drawn = ld_relaxed(&c->ticket);
+        M0 = drawn < T ? drawn : T;
+        if (M0 < 1u) M0 = 1u;
+    }
+    const uint32_t ready = p.tail - p.join_head;
+    const uint32_t room = cfg.N - M0;
+    const uint32_t want = T > M0 ? T - M0 : 0u;
+    uint32_t kmax = live ? ready : 0u;
+    kmax = kmax < room ? kmax : room;
+    kmax = kmax < want ? kmax : want;
+    // with no room, pass the slots at the head whose joiners have given up
+    // already, so that they do not fill the ring's window (never at a
+    // barrier that admits: see the ring's comment)
+    const uint32_t span = ready < blockDim.x ? ready : blockDim.x;
+    const uint32_t drain = (live && kmax == 0 && span >= kDrainMin) ? span : 0u;
+    p.T = T;
+    p.T_dev_new = T_dev;
+    p.M0 = M0;
+    p.kmax = kmax;
+    p.drain = drain;
+    // the common barrier: nothing to admit, drain or kill, no recount of
+    // the members per XCD (the algorithm's flags may still rule it out),
+    // the kernel goes on (the Kill-No-Op rule and a fork of k = 0); only
+    // the bookkeeping in master_schedule runs
+    p.quiet = (m.epoch != 0 && p.nb != 0 && !(m.flags & kFlagFlat) && kmax == 0 && drain == 0 && T >= m.M &&
+               T_dev == p.T_dev) ? 1u : 0u;
+}
+
 // Scheduler part of the master step, run by every thread of the master
 // workgroup: fork (admit waiting joiners, in parallel), query (the target)
 // and kill (the top ids). Thread 0 then publishes the release word.
 template <bool Coop, class C>
 __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLds& b, uint32_t flags,
-                                       uint64_t t_in, const MasterPre& pre, bool resize) {
-    const uint32_t ne = m.epoch + 1;
+                                       uint64_t t_in, MasterPre& pre, bool resize) {
     uint32_t T_dev = 0, nb = 0, kills = 0, forks = 0, resizes = 0, min_M = 0, max_M = 0;
     uint32_t kmax0 = 0, head0 = 0, drain0 = 0;     // the scheduling thread's copies of what it shares in LDS
     // one thread decides and publishes: the thread that loaded the
     // scheduler words (MasterPre) while the algorithm's master step ran
     const uint32_t sched = sched_thread<Coop>();
     if (threadIdx.x == sched) {
-        const int32_t err = pre.err;
-        const uint32_t tail = pre.tail;
-        const uint32_t T_seen = pre.T_seen;
-        const uint32_t join_head = pre.join_head;
-        T_dev = pre.T_dev;
+        if constexpr (!Coop) master_decide<Coop>(c, cfg, m, pre, resize);
         nb = pre.nb;
         kills = pre.kills;
         forks = pre.forks;
         resizes = pre.resizes;
         min_M = pre.min_M;
         max_M = pre.max_M;
-        if (err) flags |= kFlagAbort;
-        // a barrier that may not resize is one whose fork admits nobody and
-        // whose kill claims nobody (k = 0 and the Kill-No-Op rule)
+        if (pre.err) flags |= kFlagAbort;
+        // the decision stands unless the algorithm ended the kernel: then
+        // nothing is admitted, drained or killed
         const bool live = Coop && resize && !(flags & (kFlagDone | kFlagAbort));
-        uint32_t T = cfg.N;
-        if (live) {
-            if (cfg.mode & kModeRandomSched) {
-                const uint64_t h = splitmix64(cfg.sched_seed + (uint64_t)ne * 0x9E3779B97F4A7C15ull);
-                if ((uint32_t)(h & 0xFFFFu) < cfg.sched_p16) T_dev = 1u + (uint32_t)((h >> 16) % cfg.N);
-                T = T_dev ? T_dev : cfg.N;      // no draw yet: nothing competes
-            } else if (cfg.host) {
-                T = T_seen;
-            }
-            if (T < 1u) T = 1u;
-            if (T > cfg.N) T = cfg.N;
-        }
-        // start-up admission (the first barrier of a cooperative launch):
-        // the launch's tickets drawn so far, at most the target, become ids
-        // 0 .. M0-1 (the members before this barrier's forks); each reads
-        // M0 after the release
-        uint32_t M0 = m.M;
-        if (live && m.epoch == 0) {
-            const uint32_t drawn = ld_relaxed(&c->ticket);
-            M0 = drawn < T ? drawn : T;
-            if (M0 < 1u) M0 = 1u;
-            st_relaxed(&c->cohort, M0);
-        }
+        T_dev = live ? pre.T_dev_new : pre.T_dev;
+        const uint32_t M0 = live ? pre.M0 : m.M;
+        if (live && m.epoch == 0) st_relaxed(&c->cohort, M0);
         b.m0 = M0;
-        const uint32_t ready = tail - join_head;
-        const uint32_t room = cfg.N - M0;
-        const uint32_t want = T > M0 ? T - M0 : 0u;
-        uint32_t kmax = live ? ready : 0u;
-        kmax = kmax < room ? kmax : room;
-        kmax = kmax < want ? kmax : want;
+        const uint32_t kmax = live ? pre.kmax : 0u;
         kmax0 = kmax;
-        head0 = join_head;
-        b.head = join_head;
+        head0 = pre.join_head;
+        b.head = pre.join_head;
         b.kmax = kmax;
-        b.T = T;
+        b.T = live ? pre.T : cfg.N;
         b.flags = flags;
         b.tail_prev = pre.tail_prev;
-        // with no room, pass the slots at the head whose joiners have given
-        // up already, so that they do not fill the ring's window (never at
-        // a barrier that admits: see the ring's comment)
-        const uint32_t span = ready < blockDim.x ? ready : blockDim.x;
-        drain0 = (live && kmax == 0 && span >= kDrainMin) ? span : 0u;
+        drain0 = live ? pre.drain : 0u;
         b.drain_span = drain0;
-        // the common barrier: nothing to admit, drain or kill, no recount
-        // of the members per XCD, the kernel goes on (the Kill-No-Op rule
-        // and a fork of k = 0); only the bookkeeping below runs
-        b.quiet = (m.epoch != 0 && nb != 0 && !(m.flags & kFlagFlat) &&
-                   !(flags & (kFlagDone | kFlagAbort | kFlagRenum | kFlagFlat)) && kmax == 0 && drain0 == 0 &&
-                   T >= m.M && T_dev == pre.T_dev) ? 1u : 0u;
+        b.quiet = (pre.quiet && !(flags & (kFlagDone | kFlagAbort | kFlagRenum | kFlagFlat))) ? 1u : 0u;
     }
+    const uint32_t ne = m.epoch + 1;
     // every thread reads what the scheduling thread just shared (b.flags decides below
     // whether the whole workgroup recounts the members per XCD, a block with
     // workgroup barriers inside): in every launch mode, since an
@@ -948,7 +974,10 @@ __device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, Ma
         // master step: everybody else is parked in the barrier
         const uint64_t t_in = now_ticks();
         MasterPre pre;
-        if (threadIdx.x == sched_thread<Coop>()) pre = master_prefetch<Coop>(c, cfg, m.M == 1);
+        if (threadIdx.x == sched_thread<Coop>()) {
+            pre = master_prefetch<Coop>(c, cfg, m.M == 1);
+            if constexpr (Coop) master_decide<Coop>(c, cfg, m, pre, resize);
+        }
         const uint32_t flags = master_fn(m.M, m.epoch + 1);
         master_schedule<Coop, C>(c, cfg, m, b, flags, t_in, pre, resize);
     } else if (Coop && cfg.host && m.id == 0 && threadIdx.x == kRelayThread) {
