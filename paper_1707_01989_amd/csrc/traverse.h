@@ -935,7 +935,9 @@ __device__ __forceinline__ void bfs_phase(const BfsArgs& p, BlockLds& sh, uint32
 // level after a low-degree source and the last one or two levels of every
 // traversal touch a few thousand arcs at most. A level qualifies when its
 // frontier fits the master's LDS lists (il_cap) and its arcs are at most
-// kInlineArcs per thread; it is walked top-down whatever the direction rule
+// kInlineLevelArcs per thread (walked in rounds of kInlineArcs per thread:
+// the smaller round costs the kernel's phases fewer registers); it is
+// walked top-down whatever the direction rule
 // would pick for a phase. The results are those of the phases: the same
 // claims on the visited bitmap, the same levels, the same next frontier in
 // the bitmap the next phase reads.
@@ -943,7 +945,8 @@ __device__ __forceinline__ void bfs_phase(const BfsArgs& p, BlockLds& sh, uint32
 // The lists live in the master's wave output buffers (idle in a master
 // step): two frontier lists, the first arc of each vertex and its degree
 // (then degree prefix), each il_cap entries, indexed through il_at.
-constexpr uint32_t kInlineArcs = 3;      // arcs per thread of the master workgroup per level
+constexpr uint32_t kInlineArcs = 3;      // arcs per thread of the master workgroup per round
+constexpr uint32_t kInlineLevelArcs = 4; // arcs per thread of a level the master step takes (more rounds)
 constexpr uint32_t kInlineLevels = 16;   // levels per master step at most (a barrier, and its
                                          // offer_kill, still comes after that many)
 
@@ -1030,7 +1033,7 @@ __device__ __forceinline__ bool il_gather(BlockLds& sh, const uint32_t* flist, c
     uint64_t all = 0;
     for (uint32_t w = 0; w < num_waves(); ++w) all += sh.red[0][w];
     __syncthreads();
-    return all <= (uint64_t)kInlineArcs * blockDim.x;
+    return all <= (uint64_t)kInlineLevelArcs * blockDim.x;
 }
 
 // One round of a master-step level: arcs e0 .. e0 + kInlineArcs * blockDim.x
@@ -1172,7 +1175,7 @@ __device__ __forceinline__ uint32_t bfs_inline_levels(const IlArgs& q, BlockLds&
                 // a level this small goes here whatever the direction rule
                 // says (the rule picks the cheaper walk for a phase of all
                 // workgroups; either gives the same levels)
-                go = (nb <= F && mfb <= round && done < kInlineLevels) ? 1u : 0u;
+                go = (nb <= F && mfb <= (uint64_t)kInlineLevelArcs * blockDim.x && done < kInlineLevels) ? 1u : 0u;
                 if (!go)
                     res = nph | kFlagAdv | kFlagJump | (((r + 1) % 3) << kRotShift) |
                           (q.record && mfb <= kRecordArcs ? kFlagRecord : 0u);
@@ -1322,7 +1325,7 @@ __device__ uint32_t bfs_master_source(const BfsArgs& p, BlockLds& sh, CtxCore* c
                 x.level() = 1;
                 res = nph | kFlagAdv | (1u << kRotShift) |   // level 1: current = fb[1]
                       (Small && p.flist && (mf <= kRecordArcs || !p.direction_opt) ? kFlagRecord : 0u);
-                il = Small && p.inline_on && mf <= (uint64_t)kInlineArcs * blockDim.x;
+                il = Small && p.inline_on && mf <= (uint64_t)kInlineLevelArcs * blockDim.x;
                 if (strips && !il) {
                     // the strips stay queued for a top-down level 1 (a
                     // bottom-up one does not walk the frontier's lists)
@@ -1477,7 +1480,7 @@ __device__ __forceinline__ uint32_t bfs_master(const BfsArgs& p, BlockLds& sh, C
                     // rewrote them with its own finds only). The gather
                     // checks the arcs that top-down-only launches do not sum.
                     il = Small && p.inline_on && p.flist && (cur_flags & kFlagRecord) && ph != kPhHeavy &&
-                         nf_lvl <= il_cap(num_waves()) && mf_lvl <= (uint64_t)kInlineArcs * blockDim.x;
+                         nf_lvl <= il_cap(num_waves()) && mf_lvl <= (uint64_t)kInlineLevelArcs * blockDim.x;
                     sh.il_c[0] = nf_lvl;
                     sh.il_v[1] = x.level();
                     sh.il_v[2] = r;
