@@ -150,7 +150,16 @@ struct ColorArgs {
     uint32_t* colour_out;      // n colours (COLOR) or null
     uint8_t* in_set_out;       // n flags (MIS) or null
     uint32_t mis;              // 0: greedy colouring, 1: greedy MIS
+    uint32_t lanes;            // lanes per frontier vertex in a round: 1, 2, 4 or 8
 };
+
+// Lanes per frontier vertex in a colouring / MIS round for a graph of `arcs`
+// arcs on `n` vertices: a vertex's list is split over about one lane per
+// four arcs of the average degree, at most 8.
+inline uint32_t color_lanes(uint64_t arcs, uint32_t n) {
+    const uint64_t avg = n ? arcs / n : 0;
+    return avg >= 24 ? 8u : avg >= 12 ? 4u : avg >= 6 ? 2u : 1u;
+}
 
 struct CotaskArgs {
     uint64_t busy_ticks;       // how long each workgroup holds its compute unit

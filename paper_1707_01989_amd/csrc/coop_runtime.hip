@@ -843,6 +843,7 @@ static int color_or_mis(coop_rt* rt, const coop_graph* g, uint64_t seed, uint32_
     a.colour_out = colour;
     a.in_set_out = in_set;
     a.mis = in_set ? 1u : 0u;
+    a.lanes = coop::color_lanes(g->arcs, g->n);
     if (!a.pending) { handle_free(h); return COOP_E_OOM; }
     (void)hipEventRecord(h->ev_init, s);
     (void)hipEventRecord(h->ev_start, s);
@@ -1291,6 +1292,7 @@ int coop_batch_run(coop_rt* rt, const coop_batch_item* items, uint32_t count, co
             I.col.colour_out = it.d_colour;
             I.col.in_set_out = it.d_in_set;
             I.col.mis = (it.ops & COOP_BATCH_MIS) ? 1u : 0u;
+            I.col.lanes = coop::color_lanes(g->arcs, g->n);
         }
     }
     if ((size_t)(p - base) > head + bytes) { handle_free(h); return COOP_E_INTERNAL; }

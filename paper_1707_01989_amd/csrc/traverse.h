@@ -1721,21 +1721,40 @@ __device__ __forceinline__ uint64_t key_hash(uint64_t seed, uint32_t v) {
 // round trips per step instead of thirty-two).
 constexpr uint32_t kColorBatch = 8;
 
-// Decide one vertex whose higher-priority neighbours are all final: colour =
-// smallest colour none of them has (or MIS membership).
-__device__ __forceinline__ void color_vertex(const ColorArgs& p, uint32_t v, bool valid, Stats& st) {
-    if (!valid) return;
-    const uint64_t hv = key_hash(p.prio_seed, v);
-    const uint32_t a0 = p.t.row_ptr[v], a1 = p.t.row_ptr[v + 1];
-    st.rows += 1;
-    st.arcs += a1 - a0;
+// OR of x over a lane group: G consecutive lanes, G a power of two that
+// divides the wave.
+__device__ __forceinline__ uint32_t group_or32(uint32_t x, uint32_t G) {
+    for (uint32_t o = 1; o < G; o <<= 1) x |= __shfl_xor(x, o, kWave);
+    return x;
+}
+__device__ __forceinline__ uint64_t group_or64(uint64_t x, uint32_t G) {
+    for (uint32_t o = 1; o < G; o <<= 1) x |= __shfl_xor(x, o, kWave);
+    return x;
+}
+
+// Decide frontier vertex v (its higher-priority neighbours are all decided):
+// the smallest colour none of them has, or (MIS) whether none of them is in
+// the set. The vertex's G lanes (consecutive lanes, G a power of two) take
+// its arcs sub, sub + G, ... kColorBatch at a time (their loads in flight
+// together) and OR their findings across the group; the group's first lane
+// writes the result. Every lane of the wave makes the call (`valid` false:
+// no vertex), so the group reductions see all of their lanes.
+__device__ __forceinline__ void color_vertex(const ColorArgs& p, uint32_t v, bool valid, uint32_t sub, uint32_t G,
+                                             Stats& st) {
+    const uint64_t hv = valid ? key_hash(p.prio_seed, v) : 0;
+    const uint32_t a0 = valid ? p.t.row_ptr[v] : 0, a1 = valid ? p.t.row_ptr[v + 1] : 0;
+    if (valid && sub == 0) {
+        st.rows += 1;
+        st.arcs += a1 - a0;
+    }
+    const uint32_t step = G * kColorBatch;
     if (p.mis) {
-        bool blocked = false;
-        for (uint32_t e0 = a0; e0 < a1 && !blocked; e0 += kColorBatch) {
+        uint32_t blocked = 0;
+        for (uint32_t e0 = a0 + sub; e0 < a1 && !blocked; e0 += step) {
             uint32_t u[kColorBatch];
             uint8_t in[kColorBatch];
 #pragma unroll
-            for (uint32_t j = 0; j < kColorBatch; ++j) u[j] = e0 + j < a1 ? p.t.col[e0 + j] : 0xFFFFFFFFu;
+            for (uint32_t j = 0; j < kColorBatch; ++j) u[j] = e0 + j * G < a1 ? p.t.col[e0 + j * G] : 0xFFFFFFFFu;
 #pragma unroll
             for (uint32_t j = 0; j < kColorBatch; ++j) {
                 in[j] = 0;
@@ -1743,17 +1762,18 @@ __device__ __forceinline__ void color_vertex(const ColorArgs& p, uint32_t v, boo
                     in[j] = p.in_set_out[u[j]];
             }
 #pragma unroll
-            for (uint32_t j = 0; j < kColorBatch; ++j) blocked |= in[j] != 0;
+            for (uint32_t j = 0; j < kColorBatch; ++j) blocked |= in[j] != 0 ? 1u : 0u;
         }
-        p.in_set_out[v] = blocked ? 0 : 1;
+        blocked = group_or32(blocked, G);
+        if (valid && sub == 0) p.in_set_out[v] = blocked ? 0 : 1;
     } else {
         uint32_t base = 0, c = 0;
         for (;;) {
             uint64_t used = 0;
-            for (uint32_t e0 = a0; e0 < a1; e0 += kColorBatch) {
+            for (uint32_t e0 = a0 + sub; e0 < a1; e0 += step) {
                 uint32_t u[kColorBatch], cu[kColorBatch];
 #pragma unroll
-                for (uint32_t j = 0; j < kColorBatch; ++j) u[j] = e0 + j < a1 ? p.t.col[e0 + j] : 0xFFFFFFFFu;
+                for (uint32_t j = 0; j < kColorBatch; ++j) u[j] = e0 + j * G < a1 ? p.t.col[e0 + j * G] : 0xFFFFFFFFu;
 #pragma unroll
                 for (uint32_t j = 0; j < kColorBatch; ++j) {
                     cu[j] = 0xFFFFFFFFu;           // no colour is that large
@@ -1766,24 +1786,26 @@ __device__ __forceinline__ void color_vertex(const ColorArgs& p, uint32_t v, boo
                     if (cu[j] != 0xFFFFFFFFu && d < 64) used |= 1ull << d;
                 }
             }
-            if (~used) {
-                c = base + (uint32_t)__ffsll((long long)~used) - 1;
-                break;
-            }
-            base += 64;
+            // the whole wave takes the same number of windows: a group that
+            // still needs one more keeps every lane of the wave in the loop
+            used = group_or64(used, G);
+            const bool need = ~used == 0;
+            if (!need) c = base + (uint32_t)__ffsll((long long)~used) - 1;
+            if (!__ballot(valid && need)) break;
+            if (need) base += 64;
         }
-        p.colour_out[v] = c;
+        if (valid && sub == 0) p.colour_out[v] = c;
     }
 }
 
 // Release the lower-priority neighbours of v; one whose count of undecided
-// higher neighbours reaches 0 is queued for the next round. A lane takes
-// kColorBatch arcs at a time: their loads, then their decrements, issued
-// back to back.
-__device__ __forceinline__ void release_lower(const ColorArgs& p, uint32_t v, bool valid, WaveLds& w,
-                                              uint32_t* out_tail, uint32_t* out, Stats& st) {
+// higher neighbours reaches 0 is queued for the next round. The vertex's G
+// lanes take its arcs as in color_vertex, kColorBatch at a time: their
+// loads, then their decrements, issued back to back.
+__device__ __forceinline__ void release_lower(const ColorArgs& p, uint32_t v, bool valid, uint32_t sub, uint32_t G,
+                                              WaveLds& w, uint32_t* out_tail, uint32_t* out, Stats& st) {
     const uint64_t hv = valid ? key_hash(p.prio_seed, v) : 0;
-    uint32_t e = valid ? p.t.row_ptr[v] : 0;
+    uint32_t e = valid ? p.t.row_ptr[v] + sub : 0;
     const uint32_t a1 = valid ? p.t.row_ptr[v + 1] : 0;
     for (;;) {
         const bool more = e < a1;
@@ -1791,7 +1813,7 @@ __device__ __forceinline__ void release_lower(const ColorArgs& p, uint32_t v, bo
         uint32_t u[kColorBatch], old[kColorBatch];
         bool lower[kColorBatch];
 #pragma unroll
-        for (uint32_t j = 0; j < kColorBatch; ++j) u[j] = e + j < a1 ? p.t.col[e + j] : 0xFFFFFFFFu;
+        for (uint32_t j = 0; j < kColorBatch; ++j) u[j] = e + j * G < a1 ? p.t.col[e + j * G] : 0xFFFFFFFFu;
 #pragma unroll
         for (uint32_t j = 0; j < kColorBatch; ++j) {
             lower[j] = u[j] != 0xFFFFFFFFu && !key_higher(key_hash(p.prio_seed, u[j]), u[j], hv, v);
@@ -1806,7 +1828,7 @@ __device__ __forceinline__ void release_lower(const ColorArgs& p, uint32_t v, bo
             wave_push(w, win, u[j]);
             if (w.out_n > kFlushAt) wave_flush(w, out_tail, out);
         }
-        e += kColorBatch;
+        e += G * kColorBatch;
     }
 }
 
@@ -1855,13 +1877,18 @@ __device__ __forceinline__ void color_phase(const ColorArgs& p, BlockLds& sh, ui
         if (threadIdx.x == 0) sh.in_size = wk->x.in_size;
         __syncthreads();
         const uint32_t size = sh.in_size;
-        const uint32_t units = (size + kWave - 1) / kWave;
+        // G consecutive lanes per frontier vertex (G divides the wave)
+        const uint32_t G = p.lanes == 2 || p.lanes == 4 || p.lanes == 8 ? p.lanes : 1u;
+        const uint32_t lg = __builtin_ctz(G);
+        const uint32_t per = kWave >> lg;
+        const uint32_t units = (size + per - 1) >> (6 - lg);
         for (uint32_t u = gw; u < units; u += W) {
-            const uint32_t i = u * kWave + lane_id();
+            const uint32_t i = u * per + (lane_id() >> lg);
+            const uint32_t sub = lane_id() & (G - 1);
             const bool valid = i < size;
             const uint32_t v = valid ? in[i] : 0u;
-            color_vertex(p, v, valid, st);
-            release_lower(p, v, valid, w, &wk->out_tail, out, st);
+            color_vertex(p, v, valid, sub, G, st);
+            release_lower(p, v, valid, sub, G, w, &wk->out_tail, out, st);
         }
         wg_flush(sh, &wk->out_tail, out);
         stats_to_lds(sh, st);

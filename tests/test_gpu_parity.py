@@ -369,9 +369,12 @@ def test_bfs_random_schedule_with_joiner_grid(rt, coop_mod, gg):
 
 # ------------------------------------------------------ colouring / MIS
 
-@pytest.mark.parametrize("name", ["er", "rmat", "complete", "empty"])
+# lanes per frontier vertex by average degree: grid 1, er8 2, er and rmat 4,
+# rmat14 and complete 8 (complete(70) also needs colours past 64)
+@pytest.mark.parametrize("name", ["er", "er8", "grid", "rmat", "rmat14", "complete", "empty"])
 def test_color_and_mis(rt, coop_mod, gg, name):
-    g = {"er": lambda: gg.er(6000, 16, 8), "rmat": lambda: gg.rmat(12, 8, seed=2),
+    g = {"er": lambda: gg.er(6000, 16, 8), "er8": lambda: gg.er(5000, 8, 4), "grid": lambda: gg.grid(60, 70),
+         "rmat": lambda: gg.rmat(12, 8, seed=2), "rmat14": lambda: gg.rmat(14, 16, seed=4),
          "complete": lambda: gg.complete(70), "empty": lambda: gg.empty(100)}[name]()
     say(f"color/mis {name}")
     dg = rt.graph(g)
