@@ -937,10 +937,10 @@ __device__ __forceinline__ void bfs_phase(const BfsArgs& p, BlockLds& sh, uint32
 // frontier fits the master's LDS lists (il_cap) and its arcs are at most
 // kInlineLevelArcs per thread (walked in rounds of kInlineArcs per thread:
 // the smaller round costs the kernel's phases fewer registers); it is
-// walked top-down whatever the direction rule
-// would pick for a phase. The results are those of the phases: the same
-// claims on the visited bitmap, the same levels, the same next frontier in
-// the bitmap the next phase reads.
+// walked top-down whatever the direction rule would pick for a phase. The
+// results are those of the phases: the same claims on the visited bitmap,
+// the same levels, the same next frontier in the bitmap the next phase
+// reads.
 //
 // The lists live in the master's wave output buffers (idle in a master
 // step): two frontier lists, the first arc of each vertex and its degree
