@@ -110,11 +110,15 @@ enum {
                                      barrier; by default a master step runs small levels itself,
                                      top-down (frontier of at most 2048 vertices and 4 arcs per
                                      thread), with the same result */
-    COOP_F_TEST_LOSE_ONE = 64u    /* test of the barrier's bounded wait (coop_barrier_bench only):
+    COOP_F_TEST_LOSE_ONE = 64u,   /* test of the barrier's bounded wait (coop_barrier_bench only):
                                      the last workgroup leaves after the first barrier without
                                      being killed, as a lost workgroup would, so the others'
                                      waits run out after watchdog_ns and the launch ends with
                                      COOP_E_TIMEOUT (every workgroup exits normally) */
+    COOP_F_SLOT_SUMS = 128u       /* BFS: the master step sums every workgroup's statistics slot
+                                     for a level's counts; by default (graphs with n < 2^24 and
+                                     fewer than 2^28 arcs) the counts come with the barrier
+                                     arrivals; the same result either way */
 };
 
 typedef struct coop_launch_opts {

@@ -125,9 +125,10 @@ __device__ __forceinline__ void wg_trace(const Cfg cfg, uint32_t epoch, uint32_t
 // inside a batched launch uses one of these on its own (no joiners).
 struct alignas(256) CtxCore {
     // ---- line: barrier arrival counter (per workgroup, or per group of
-    //      workgroups in a resizable launch)
-    uint32_t arrive;
-    uint32_t _pa[63];
+    //      workgroups in a resizable launch), with the arrivals' sums
+    //      (arrive_sums)
+    uint64_t arrive;
+    uint32_t _pa[62];
     // ---- line: release word {epoch:32 (lo) | M:16 | flags:16 (hi)}
     uint64_t release;
     uint64_t _pr[31];
@@ -173,9 +174,25 @@ struct alignas(256) CtxCore {
 // joiners have not recorded their XCD yet; that interval arrives per
 // workgroup with release-acquire as before.
 struct alignas(256) ArriveLine {
-    uint32_t count;
-    uint32_t _p[63];
+    uint64_t count;           // arrivals, with their sums (arrive_sums)
+    uint32_t _p[62];
 };
+
+// A barrier arrival adds one to its counter and, in the same atomic, two
+// counts the workgroup brings (an algorithm's per-phase totals, e.g. the
+// vertices a BFS level found and their degree sum): the count of arrivals
+// in the low 12 bits, a 24-bit and a 28-bit sum above it. The last arrival
+// of an XCD gets its XCD's sums from the value its add returns and passes
+// them on with its arrival on the top counter, so the master step receives
+// the totals of all members without reading anything. The launch must keep
+// the sums in range (the host only enables them when they cannot overflow).
+constexpr uint32_t kArriveCountBits = 12;                      // up to kMaxGroups arrivals
+constexpr uint64_t kArriveCount = (1ull << kArriveCountBits) - 1;
+__device__ __forceinline__ uint64_t arrive_payload(uint64_t a24, uint64_t b28) {
+    return (a24 << kArriveCountBits) | (b28 << (kArriveCountBits + 24));
+}
+__device__ __forceinline__ uint32_t sums_a(uint64_t sums) { return (uint32_t)(sums & 0xFFFFFFu); }
+__device__ __forceinline__ uint32_t sums_b(uint64_t sums) { return (uint32_t)(sums >> 24); }
 struct alignas(256) XcdCounts {
     uint32_t members[kMaxXcds];   // members of this interval per XCD
     uint32_t groups;              // XCDs with members
@@ -299,6 +316,7 @@ struct MasterPre {
 // Workgroup-shared state of the barrier.
 struct BarrierLds {
     Member member;
+    uint64_t sums;          // master: the arrivals' sums (sums_a / sums_b)
     uint32_t killed;        // this workgroup left because the scheduler claimed it
     uint32_t is_master;     // this workgroup runs the master step
     uint32_t flags;         // master step result (broadcast inside the master)
@@ -927,7 +945,7 @@ __device__ inline void master_schedule(C* c, const Cfg cfg, Member& m, BarrierLd
 // arrives.
 template <bool Coop, class C, class MasterFn>
 __device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, MasterFn&& master_fn,
-                               bool resize = true) {
+                               bool resize = true, uint64_t payload = 0) {
     // by XCD: every wave's memory operations must have reached the L2 that
     // its XCD's last arriver writes back
     const bool by_xcd = kGroupedArrival<C> && m.epoch != 0 && !(m.flags & kFlagFlat);
@@ -953,21 +971,26 @@ __device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, Ma
             }
             const uint32_t members = m.xm, groups = m.xg;
             __builtin_amdgcn_s_waitcnt(0);       // our T_seen store is in the L2 too
-            const uint32_t o = __hip_atomic_fetch_add(&cx->xcd_arrive[x].count, 1u, __ATOMIC_RELAXED,
+            const uint64_t o = __hip_atomic_fetch_add(&cx->xcd_arrive[x].count, 1ull + payload, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
-            if (o + 1 == members) {
+            if ((uint32_t)(o & kArriveCount) + 1 == members) {
                 // last of this XCD: reset its counter, write back its L2
-                // and arrive for the XCD
-                __hip_atomic_store(&cx->xcd_arrive[x].count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t o2 = __hip_atomic_fetch_add(&c->arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-                last = (o2 + 1 == groups) ? 1u : 0u;
+                // and arrive for the XCD with the XCD's sums
+                __hip_atomic_store(&cx->xcd_arrive[x].count, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t xs = (o + 1ull + payload) & ~kArriveCount;
+                const uint64_t o2 = __hip_atomic_fetch_add(&c->arrive, 1ull + xs, __ATOMIC_ACQ_REL,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+                last = ((uint32_t)(o2 & kArriveCount) + 1 == groups) ? 1u : 0u;
+                b.sums = (o2 + 1ull + xs) >> kArriveCountBits;
             }
         } else {
-            const uint32_t old = __hip_atomic_fetch_add(&c->arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            last = (old + 1 == m.M) ? 1u : 0u;
+            const uint64_t old = __hip_atomic_fetch_add(&c->arrive, 1ull + payload, __ATOMIC_ACQ_REL,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+            last = ((uint32_t)(old & kArriveCount) + 1 == m.M) ? 1u : 0u;
+            b.sums = (old + 1ull + payload) >> kArriveCountBits;
         }
         b.is_master = last;
-        if (b.is_master) __hip_atomic_store(&c->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (b.is_master) __hip_atomic_store(&c->arrive, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
     if (b.is_master) {
@@ -1026,14 +1049,18 @@ __device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, Ma
 // L1 lines (other waves' atomics were performed in L2), and the workgroup
 // runs the master step itself.
 template <class MasterFn>
-__device__ inline void team_barrier(CtxCore* c, const Cfg cfg, Member& m, BarrierLds& b, MasterFn&& master_fn) {
+__device__ inline void team_barrier(CtxCore* c, const Cfg cfg, Member& m, BarrierLds& b, MasterFn&& master_fn,
+                                    uint64_t payload = 0) {
     if (m.M > 1) {
-        barrier<false>(c, cfg, m, b, master_fn);
+        barrier<false>(c, cfg, m, b, master_fn, true, payload);
         return;
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        b.sums = payload >> kArriveCountBits;
+    }
     __syncthreads();
     uint32_t flags = master_fn(1u, m.epoch + 1);
     __builtin_amdgcn_s_waitcnt(0);
@@ -1168,10 +1195,13 @@ __device__ __forceinline__ bool coop_joined(const Group& g) { return g.bar.membe
 // Returns false if this workgroup was killed or the kernel is over: the
 // caller leaves (or re-queues with coop_rejoin). All global memory accesses
 // issued before the barrier are complete and visible after it.
+// `payload` (thread 0's value counts; arrive_payload) is this workgroup's
+// share of two sums the master step finds in g.bar.sums: what every member
+// brought to this barrier, added up by the arrival atomics themselves.
 template <bool Coop, class Single>
-__device__ inline bool coop_resizing_global_barrier(Group& g, Single&& single) {
+__device__ inline bool coop_resizing_global_barrier(Group& g, Single&& single, uint64_t payload = 0) {
     Member m = g.bar.member;
-    barrier<Coop>(g.ctx, g.cfg, m, g.bar, single, true);
+    barrier<Coop>(g.ctx, g.cfg, m, g.bar, single, true, payload);
     return m.alive != 0;
 }
 template <bool Coop>

@@ -36,6 +36,7 @@ COOP_F_TOP_DOWN_ONLY = 8
 COOP_F_REGULAR_BARRIER = 16
 COOP_F_LEVEL_BARRIERS = 32
 COOP_F_TEST_LOSE_ONE = 64
+COOP_F_SLOT_SUMS = 128
 COOP_KERNEL_OCTREE = 8
 COOP_KERNEL_CC = 9
 

@@ -133,6 +133,9 @@ struct BfsArgs {
     uint32_t* flist;           // N x (1 + kFlWgHost) words: per workgroup the count and first 64 vertices it
                                // found in the last phase; null: no lists
     uint32_t inline_on;        // 1: the master step runs small levels itself (top-down)
+    uint32_t arrive_sums;      // 1: a level's found and mf come with the barrier arrivals (the
+                               // graph keeps them in range: n < 2^24, arcs < 2^28); 0: the master
+                               // step sums the statistics slots
 };
 
 struct SsspArgs {

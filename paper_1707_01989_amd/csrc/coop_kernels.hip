@@ -76,11 +76,11 @@ __device__ __forceinline__ void bfs_body(const BfsArgs& p, bool joiner_grid) {
         const uint32_t id = coop_get_group_id(g), M = coop_get_num_groups(g);
         fresh = false;
         wg_trace(t.cfg, g.bar.member.epoch, id, kTrStart);
-        bfs_phase<Small>(p, sh, ph, cur_flags, level, root, id, M, p.level_out);
+        const uint64_t pay = bfs_phase<Small>(p, sh, ph, cur_flags, level, root, id, M, p.level_out);
         wg_trace(t.cfg, g.bar.member.epoch, id, kTrWorkDone);
         coop_resizing_global_barrier<Coop>(g, [&](uint32_t M_now, uint32_t) -> uint32_t {
             return bfs_master<Small>(p, sh, c, ph, cur_flags, t.roots, p.level_out, M_now);
-        });
+        }, pay);
         bfs_follow(ph, coop_flags(g), level, root, wk);
     }
 }

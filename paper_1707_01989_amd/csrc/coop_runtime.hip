@@ -679,6 +679,14 @@ int coop_graph_release(coop_graph* g) {
     return COOP_OK;
 }
 
+// A BFS level's found vertices and their degree sum can ride on the barrier
+// arrivals (24 and 28 bits of the arrival counter) when no level can exceed
+// them: found <= n, mf <= arcs.
+static uint32_t arrive_sums_ok(const coop_graph* g, const coop_launch_opts* opts) {
+    if (opts && (opts->flags & COOP_F_SLOT_SUMS)) return 0u;
+    return (g->n < (1u << 24) && g->arcs < (1ull << 28)) ? 1u : 0u;
+}
+
 int coop_bfs(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_t nroots, uint32_t* d_level,
              uint64_t out_stride, const coop_launch_opts* opts, coop_stream_t stream, coop_handle** out) {
     int rc = check_traversal_args(rt, g, d_roots, nroots, d_level, out_stride);
@@ -713,6 +721,7 @@ int coop_bfs(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_t
     a.col_bu = g->col_bu;
     a.first2 = g->first2;
     a.inline_on = (opts && (opts->flags & COOP_F_LEVEL_BARRIERS)) ? 0u : 1u;
+    a.arrive_sums = arrive_sums_ok(g, opts);
     a.flist = a.inline_on ? static_cast<uint32_t*>(scratch_buf(h, (size_t)sz.grid * (coop::kFlWgHost + 1) * 4))
                           : nullptr;
     if (!a.vis || !a.fb[0] || !a.fb[1] || !a.fb[2] || (a.inline_on && !a.flist)) {
@@ -785,6 +794,7 @@ int coop_bfs_noalloc(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, 
     a.col_bu = g->col_bu;
     a.first2 = g->first2;
     a.inline_on = inline_on ? 1u : 0u;
+    a.arrive_sums = arrive_sums_ok(g, opts);
     a.flist = inline_on ? reinterpret_cast<uint32_t*>(base + o_flist) : nullptr;
     // the array keeps the previous call's contents: the context and the
     // slots are cleared here, the bitmaps by the kernel's per-source init

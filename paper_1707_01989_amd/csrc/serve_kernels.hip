@@ -56,9 +56,9 @@ __device__ void serve_barrier(const ServeArgs& a, CtxCore* c, const Cfg tcfg, Me
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint32_t old = __hip_atomic_fetch_add(&c->arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        b.is_master = (old + 1 == m.M) ? 1u : 0u;
-        if (b.is_master) __hip_atomic_store(&c->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t old = __hip_atomic_fetch_add(&c->arrive, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        b.is_master = ((uint32_t)(old & kArriveCount) + 1 == m.M) ? 1u : 0u;
+        if (b.is_master) __hip_atomic_store(&c->arrive, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
     if (b.is_master) {

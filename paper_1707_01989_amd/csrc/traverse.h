@@ -149,8 +149,9 @@ __device__ void stats_to_lds(BlockLds& sh, const Stats& s) {
 // Add the workgroup's phase statistics to its slot (after a __syncthreads);
 // fire-and-forget atomics, so nobody waits for the round trip. Every field
 // only grows: fields 0 and 1 (found, mf) are kept only when the master step
-// reads them (BFS), which takes a level's values as the difference from
-// the sums it saw at the previous level.
+// reads them (BFS whose level counts do not come with the barrier
+// arrivals), which takes a level's values as the difference from the sums
+// it saw at the previous level.
 __device__ void acc_to_slot(BlockLds& sh, uint32_t* slots, uint32_t id, bool per_level = true) {
     if (threadIdx.x < 5) {
         uint64_t* s = reinterpret_cast<uint64_t*>(slots + (size_t)id * kSlotWords);
@@ -859,10 +860,12 @@ __device__ __forceinline__ void clear_share(uint32_t* bm, uint32_t words, uint32
 // One BFS phase for member `id` of `M` (the interval's membership):
 // INIT clears the per-source state, TD/HEAVY expand the frontier, BU probes
 // the unvisited vertices. Statistics go to the member's slot.
+// Returns (thread 0) the workgroup's share of the level's found and mf for
+// the barrier arrival when the launch takes them that way, else 0.
 template <bool Small = false>
-__device__ __forceinline__ void bfs_phase(const BfsArgs& p, BlockLds& sh, uint32_t ph, uint32_t flags,
-                                          uint32_t level, uint32_t root, uint32_t id, uint32_t M,
-                                          uint32_t* lvl_base) {
+__device__ __forceinline__ uint64_t bfs_phase(const BfsArgs& p, BlockLds& sh, uint32_t ph, uint32_t flags,
+                                              uint32_t level, uint32_t root, uint32_t id, uint32_t M,
+                                              uint32_t* lvl_base) {
     const TraversalArgs& t = p.t;
     Work* wk = t.work;
     const uint32_t nw = num_waves();
@@ -907,10 +910,13 @@ __device__ __forceinline__ void bfs_phase(const BfsArgs& p, BlockLds& sh, uint32
         if (p.bu_prefetch) bfs_bottom_up_rp(p, sh.wave[wave_id()], cur, nxt, lvl, level + 1, gw, W, st, fn, sh.fl);
         else bfs_bottom_up(p, sh.wave[wave_id()], cur, nxt, lvl, level + 1, gw, W, st, fn, sh.fl);
     }
+    uint64_t pay = 0;
     if (ph != kPhStart && ph != kPhInit) {
         stats_to_lds(sh, st);
         __syncthreads();
-        acc_to_slot(sh, t.slots, id);
+        // read before acc_to_slot clears the accumulators (the same wave)
+        if (p.arrive_sums && threadIdx.x == 0) pay = arrive_payload(sh.acc[0], sh.acc[1]);
+        acc_to_slot(sh, t.slots, id, !p.arrive_sums);
         if (Small && p.flist && (flags & kFlagRecord) && threadIdx.x < kWave) {
             // the phase's found list, for a master step that may run the
             // next levels itself: count, then up to kFlWg vertices (wave 0
@@ -924,6 +930,7 @@ __device__ __forceinline__ void bfs_phase(const BfsArgs& p, BlockLds& sh, uint32
             }
         }
     }
+    return pay;
 }
 
 // ------------------------------------------- small levels in the master step
@@ -1407,8 +1414,10 @@ __device__ __forceinline__ uint32_t bfs_master(const BfsArgs& p, BlockLds& sh, C
         x = wk->load_x();
         hs = ld_relaxed(&wk->heavy_tail);
     }
-    uint64_t tot[2];
-    master_sum_slots(sh, t.slots, t.N, tot);
+    // the phase's found and mf: from the barrier arrivals, or as the growth
+    // of the slot sums
+    uint64_t tot[2] = {0, 0};
+    if (!p.arrive_sums) master_sum_slots(sh, t.slots, t.N, tot);
     if (ph == kPhInit) {
         const uint32_t res = bfs_master_source<Small>(p, sh, c, x, roots, lvl_base);
         if (threadIdx.x == 0) {
@@ -1428,10 +1437,16 @@ __device__ __forceinline__ uint32_t bfs_master(const BfsArgs& p, BlockLds& sh, C
             // this phase's finds: the growth of the slot sums (modulo 2^32:
             // a level finds fewer vertices and arcs than that); level
             // partials (a TD level may be followed by a HEAVY phase)
-            const uint32_t d_found = (uint32_t)tot[0] - x.sum_found();
-            const uint32_t d_mf = (uint32_t)tot[1] - x.sum_mf();
-            x.sum_found() = (uint32_t)tot[0];
-            x.sum_mf() = (uint32_t)tot[1];
+            uint32_t d_found, d_mf;
+            if (p.arrive_sums) {
+                d_found = sums_a(sh.bar.sums);
+                d_mf = sums_b(sh.bar.sums);
+            } else {
+                d_found = (uint32_t)tot[0] - x.sum_found();
+                d_mf = (uint32_t)tot[1] - x.sum_mf();
+                x.sum_found() = (uint32_t)tot[0];
+                x.sum_mf() = (uint32_t)tot[1];
+            }
             const uint64_t mf_lvl = join64(x.lvl_mf_lo(), x.lvl_mf_hi()) + d_mf;
             const uint32_t nf_lvl = x.lvl_found() + d_found;
             if (ph == kPhTD && hs > 0) {

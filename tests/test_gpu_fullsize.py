@@ -55,12 +55,16 @@ def rmat22(rt, gg):
     dg.release()
 
 
-@pytest.mark.parametrize("mode", ["coop_host", "plain"])
+# "slot_sums": the level counts summed from the statistics slots instead of
+# coming with the barrier arrivals (the default at this size)
+@pytest.mark.parametrize("mode", ["coop_host", "plain", "coop_host_slot_sums"])
 def test_bfs_rmat22_bench_launch(rt, coop_mod, rmat22, mode):
     c = coop_mod
     g, dg, roots, exp = rmat22
-    o = (c.make_opts(c.COOP_MODE_COOP, flags=c.COOP_F_HOST_SCHEDULE) if mode == "coop_host"
-         else c.make_opts(c.COOP_MODE_PLAIN))
+    o = {"coop_host": lambda: c.make_opts(c.COOP_MODE_COOP, flags=c.COOP_F_HOST_SCHEDULE),
+         "plain": lambda: c.make_opts(c.COOP_MODE_PLAIN),
+         "coop_host_slot_sums": lambda: c.make_opts(c.COOP_MODE_COOP,
+                                                    flags=c.COOP_F_HOST_SCHEDULE | c.COOP_F_SLOT_SUMS)}[mode]()
     say(f"bfs rmat22 {mode}: 8 sources in one launch")
     rc, out, st = rt.bfs(dg, roots, o)
     assert rc == 0, c.coop_strerror(rc)

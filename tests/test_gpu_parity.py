@@ -62,6 +62,9 @@ def modes(coop):
         "coop_host": coop.make_opts(coop.COOP_MODE_COOP, flags=coop.COOP_F_HOST_SCHEDULE),
         "coop_topdown": coop.make_opts(coop.COOP_MODE_COOP, flags=coop.COOP_F_TOP_DOWN_ONLY),
         "coop_levels": coop.make_opts(coop.COOP_MODE_COOP, flags=coop.COOP_F_LEVEL_BARRIERS),
+        # BFS level counts from the statistics slots, not the barrier arrivals
+        "coop_slot_sums": coop.make_opts(coop.COOP_MODE_COOP, flags=coop.COOP_F_SLOT_SUMS),
+        "plain_slot_sums": coop.make_opts(coop.COOP_MODE_PLAIN, flags=coop.COOP_F_SLOT_SUMS),
     }
 
 
@@ -152,7 +155,7 @@ def test_bfs_multi_root(rt, coop_mod, gg):
     roots = gg.sources(g, 2, 6)
     say(f"bfs multi-root rmat13 roots={roots.tolist()}")
     dg = rt.graph(g)
-    for mode in ("plain", "coop", "coop_topdown"):
+    for mode in ("plain", "coop", "coop_topdown", "coop_slot_sums"):
         rc, lv, st = rt.bfs(dg, roots, modes(coop_mod)[mode])
         assert rc == 0
         got = lv.cpu().numpy().view(np.uint32)
