@@ -12,7 +12,10 @@ published by the master with the release word and cached by every
 workgroup, which reloads them only after a release that recounted them. An
 interval right after joiners were admitted (whose XCDs are not recorded
 yet) and the first interval arrive per workgroup on the top counter alone
-(the flat interval).
+(the flat interval). The same atomic adds that count also carry sums (a
+BFS level's found count and degree sum): the XCD's last arriver passes the
+sum its add returned up with its top-level add, and the master takes the
+total from the value its own add returned.
 
 This model restates that protocol one shared-memory step at a time (each
 atomic add, store and load is its own transition) and ``explore`` runs every
@@ -25,6 +28,8 @@ in every reachable state:
     release is published;
   * the per-XCD counts a workgroup uses equal the true member counts of its
     interval (a stale cache would make a counter wait forever or overshoot);
+  * the sums the master receives are exactly the contributions of the
+    interval's members (each contributes a bit of its own);
   * no deadlock: a state where some workgroup is not finished has an enabled
     step;
   * the final state: every barrier of the schedule was passed (the planned
@@ -62,6 +67,7 @@ class WG:
     xm: int = 0                  # cached: members of this XCD
     xg: int = 0                  # cached: XCDs with members (0 = reload)
     last: bool = False           # this arrival made it the master
+    carry: int = 0               # sums its arrival returned: its XCD's (by XCD), then the grand total
 
 
 @dataclass(frozen=True)
@@ -77,6 +83,8 @@ class State:
     admitted: Tuple[Tuple[int, int, int], ...]   # (physical, logical id, epoch)
     masters: Tuple[int, ...]     # epochs that have had a master (checked: no two)
     arrived: Tuple[int, ...]     # per physical workgroup: last epoch it arrived at (-1 none)
+    xsum: Tuple[int, ...] = ()   # the sums riding on each XCD counter (same atomic as the count)
+    topsum: int = 0              # ... and on the top counter
     hist: Tuple[int, ...] = ()   # M published at each epoch 1, 2, ...
 
 
@@ -92,7 +100,9 @@ class ArrivalModel:
     Planted mistakes (each must be caught by ``explore``): "no_reset" (the
     XCD's last arriver does not reset its counter), "keep_cache" (counts are
     never reloaded after a recount), "no_flat" (the interval after an
-    admission arrives by XCD although the joiners' XCDs are not recorded)."""
+    admission arrives by XCD although the joiners' XCDs are not recorded),
+    "keep_sums" (the XCD's last arriver resets its count but not the sums
+    riding on it)."""
 
     def __init__(self, xcd_of: Sequence[int], barriers: int, *, coop: bool = False,
                  joiner_xcds: Sequence[int] = (), choices: Optional[Sequence[Sequence[Tuple[int, int]]]] = None,
@@ -123,7 +133,8 @@ class ArrivalModel:
                 wgs[p] = replace(wgs[p], pc=ENGINE, id=p, epoch=0, M=len(self.grid))
             joinq = ()
             M0 = len(self.grid)
-        return State(wgs=tuple(wgs), xcnt=(0,) * self.nx, top=0, rel=(0, M0, 0), members=(0,) * self.nx,
+        return State(wgs=tuple(wgs), xcnt=(0,) * self.nx, top=0, xsum=(0,) * self.nx, rel=(0, M0, 0),
+                     members=(0,) * self.nx,
                      groups=0, engine_of=(-1,) * self.N, joinq=joinq, admitted=(), masters=(),
                      arrived=(-1,) * self.P)
 
@@ -161,32 +172,45 @@ class ArrivalModel:
         elif w.pc == LOADCNT:
             yield ("loadcnt", replace(s, wgs=self._set(s, p, pc=XADD, xm=s.members[w.xcd], xg=s.groups)))
         elif w.pc == XADD:
+            # one atomic: the count and this workgroup's contribution (the
+            # bit 1 << p, so a sum names exactly who is in it)
             o = s.xcnt[w.xcd]
+            osum = s.xsum[w.xcd]
             xc = list(s.xcnt)
             xc[w.xcd] = o + 1
+            xs = list(s.xsum)
+            xs[w.xcd] = osum + (1 << p)
             if o + 1 > w.xm:
                 raise ModelError(f"XCD {w.xcd} counter passed its {w.xm} members (epoch {w.epoch})")
             nxt = XRESET if o + 1 == w.xm else WAIT
-            yield ("xadd", replace(s, xcnt=tuple(xc), wgs=self._set(s, p, pc=nxt)))
+            yield ("xadd", replace(s, xcnt=tuple(xc), xsum=tuple(xs),
+                                   wgs=self._set(s, p, pc=nxt, carry=osum + (1 << p))))
         elif w.pc == XRESET:
             xc = list(s.xcnt)
+            xs = list(s.xsum)
             if self.mistake != "no_reset":
                 xc[w.xcd] = 0
-            yield ("xreset", replace(s, xcnt=tuple(xc), wgs=self._set(s, p, pc=XTOP)))
+                if self.mistake != "keep_sums":
+                    xs[w.xcd] = 0
+            yield ("xreset", replace(s, xcnt=tuple(xc), xsum=tuple(xs), wgs=self._set(s, p, pc=XTOP)))
         elif w.pc == XTOP:
             o2 = s.top
             last = o2 + 1 == w.xg
             if o2 + 1 > w.xg:
                 raise ModelError(f"top counter passed its {w.xg} XCD groups (epoch {w.epoch})")
-            yield ("xtop", replace(s, top=o2 + 1, wgs=self._set(s, p, pc=MASTER_RESET if last else WAIT)))
+            yield ("xtop", replace(s, top=o2 + 1, topsum=s.topsum + w.carry,
+                                   wgs=self._set(s, p, pc=MASTER_RESET if last else WAIT,
+                                                 carry=s.topsum + w.carry)))
         elif w.pc == FLATADD:
             old = s.top
             if old + 1 > w.M:
                 raise ModelError(f"flat counter passed its {w.M} members (epoch {w.epoch})")
             last = old + 1 == w.M
-            yield ("flatadd", replace(s, top=old + 1, wgs=self._set(s, p, pc=MASTER_RESET if last else WAIT)))
+            yield ("flatadd", replace(s, top=old + 1, topsum=s.topsum + (1 << p),
+                                      wgs=self._set(s, p, pc=MASTER_RESET if last else WAIT,
+                                                    carry=s.topsum + (1 << p))))
         elif w.pc == MASTER_RESET:
-            yield ("mreset", replace(s, top=0, wgs=self._set(s, p, pc=MASTER)))
+            yield ("mreset", replace(s, top=0, topsum=0, wgs=self._set(s, p, pc=MASTER)))
         elif w.pc == MASTER:
             yield from self._master(s, p, w)
         elif w.pc == WAIT:
@@ -223,6 +247,10 @@ class ArrivalModel:
         for q in members:
             if s.arrived[q] != ep:
                 raise ModelError(f"master at epoch {ep} before workgroup {q} arrived")
+        # the sums the master's arrival returned are exactly the members' contributions
+        if w.carry != sum(1 << q for q in members):
+            raise ModelError(f"master at epoch {ep} got sums {w.carry:#x}, members "
+                             f"{sum(1 << q for q in members):#x}")
         if any(c != 0 for c in s.xcnt) and self.mistake != "no_reset":
             raise ModelError(f"an XCD counter is not back at 0 at the master step of epoch {ep}: {s.xcnt}")
         ne = ep + 1
@@ -274,8 +302,8 @@ class ArrivalModel:
         if self._counts_changed(w, ne, Mn, flags):
             xm, xg = 0, 0
         if not alive:
-            return replace(w, pc=EXITED, epoch=ne, M=Mn, flags=flags)
-        return replace(w, pc=CHOOSE, epoch=ne, M=Mn, flags=flags, xm=xm, xg=xg)
+            return replace(w, pc=EXITED, epoch=ne, M=Mn, flags=flags, carry=0)
+        return replace(w, pc=CHOOSE, epoch=ne, M=Mn, flags=flags, xm=xm, xg=xg, carry=0)
 
     def _after_release(self, s: State, p: int, w: WG) -> State:
         ep, M, fl = s.rel
@@ -285,7 +313,7 @@ class ArrivalModel:
             killed_M = s.hist[w.epoch]          # M published at epoch w.epoch + 1
             if w.id < killed_M:
                 raise ModelError(f"workgroup {p} (id {w.id}) missed epoch {w.epoch + 1} while alive")
-            return replace(s, wgs=self._set(s, p, pc=EXITED, epoch=ep))
+            return replace(s, wgs=self._set(s, p, pc=EXITED, epoch=ep, carry=0))
         return replace(s, wgs=self._set(s, p, **self._member_after(w, ep, M, fl).__dict__))
 
     # ------------------------------------------------------------ check

@@ -30,7 +30,7 @@ def test_coop_arrival_with_admissions_and_kills(grid, joiners, choices):
     assert r["finals"] > 1
 
 
-@pytest.mark.parametrize("mistake", ["no_reset", "keep_cache", "no_flat"])
+@pytest.mark.parametrize("mistake", ["no_reset", "keep_cache", "no_flat", "keep_sums"])
 def test_planted_mistakes_are_caught(mistake):
     caught = False
     for grid, joiners, coop in (([0, 1, 0], [], False), ([0, 1], [1], True), ([0, 0], [1, 1], True)):
