@@ -61,6 +61,7 @@ constexpr uint32_t kModeRandomSched = 4u;   // device-side seeded kill/fork sche
 constexpr uint32_t kModeRegular = 8u;       // regular resizing barrier: at most one kill per barrier
 constexpr uint32_t kModeRelayTarget = 16u;  // the host target is relayed into Ctx::T_seen by the kernel itself
 constexpr uint32_t kModeLoseOne = 32u;      // test: the barrier benchmark's last workgroup goes missing
+constexpr uint32_t kModeArriveSums = 64u;   // the arrivals carry sums (64-bit counters; else 32-bit adds)
 
 // error codes written to ctx->error (match COOP_E_* of coop.h)
 constexpr int32_t kErrInvalid = -1;
@@ -192,6 +193,7 @@ __device__ __forceinline__ uint64_t arrive_payload(uint64_t a24, uint64_t b28) {
     return (a24 << kArriveCountBits) | (b28 << (kArriveCountBits + 24));
 }
 __device__ __forceinline__ uint32_t sums_a(uint64_t sums) { return (uint32_t)(sums & 0xFFFFFFu); }
+__device__ __forceinline__ uint32_t* arrive_lo(uint64_t* counter) { return reinterpret_cast<uint32_t*>(counter); }
 __device__ __forceinline__ uint32_t sums_b(uint64_t sums) { return (uint32_t)(sums >> 24); }
 struct alignas(256) XcdCounts {
     uint32_t members[kMaxXcds];   // members of this interval per XCD
@@ -949,6 +951,10 @@ __device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, Ma
     // by XCD: every wave's memory operations must have reached the L2 that
     // its XCD's last arriver writes back
     const bool by_xcd = kGroupedArrival<C> && m.epoch != 0 && !(m.flags & kFlagFlat);
+    // the counters are 64-bit only in a launch whose arrivals carry sums
+    // (a 64-bit add costs the contended counters more); otherwise every
+    // add is 32-bit on the low word, whose high word stays 0
+    const bool wide = (cfg.mode & kModeArriveSums) != 0;
     if (by_xcd) __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     wg_trace(cfg, m.epoch, m.id, kTrArrive);
@@ -971,26 +977,47 @@ __device__ inline void barrier(C* c, const Cfg cfg, Member& m, BarrierLds& b, Ma
             }
             const uint32_t members = m.xm, groups = m.xg;
             __builtin_amdgcn_s_waitcnt(0);       // our T_seen store is in the L2 too
-            const uint64_t o = __hip_atomic_fetch_add(&cx->xcd_arrive[x].count, 1ull + payload, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-            if ((uint32_t)(o & kArriveCount) + 1 == members) {
-                // last of this XCD: reset its counter, write back its L2
-                // and arrive for the XCD with the XCD's sums
-                __hip_atomic_store(&cx->xcd_arrive[x].count, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const uint64_t xs = (o + 1ull + payload) & ~kArriveCount;
-                const uint64_t o2 = __hip_atomic_fetch_add(&c->arrive, 1ull + xs, __ATOMIC_ACQ_REL,
-                                                           __HIP_MEMORY_SCOPE_AGENT);
-                last = ((uint32_t)(o2 & kArriveCount) + 1 == groups) ? 1u : 0u;
-                b.sums = (o2 + 1ull + xs) >> kArriveCountBits;
+            if (wide) {
+                const uint64_t o = __hip_atomic_fetch_add(&cx->xcd_arrive[x].count, 1ull + payload,
+                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((uint32_t)(o & kArriveCount) + 1 == members) {
+                    // last of this XCD: reset its counter, write back its L2
+                    // and arrive for the XCD with the XCD's sums
+                    __hip_atomic_store(&cx->xcd_arrive[x].count, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const uint64_t xs = (o + 1ull + payload) & ~kArriveCount;
+                    const uint64_t o2 = __hip_atomic_fetch_add(&c->arrive, 1ull + xs, __ATOMIC_ACQ_REL,
+                                                               __HIP_MEMORY_SCOPE_AGENT);
+                    last = ((uint32_t)(o2 & kArriveCount) + 1 == groups) ? 1u : 0u;
+                    b.sums = (o2 + 1ull + xs) >> kArriveCountBits;
+                }
+            } else {
+                const uint32_t o = __hip_atomic_fetch_add(arrive_lo(&cx->xcd_arrive[x].count), 1u, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                if (o + 1 == members) {
+                    // last of this XCD: reset its counter, write back its L2
+                    // and arrive for the XCD
+                    __hip_atomic_store(arrive_lo(&cx->xcd_arrive[x].count), 0u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    const uint32_t o2 = __hip_atomic_fetch_add(arrive_lo(&c->arrive), 1u, __ATOMIC_ACQ_REL,
+                                                               __HIP_MEMORY_SCOPE_AGENT);
+                    last = (o2 + 1 == groups) ? 1u : 0u;
+                }
             }
-        } else {
+        } else if (wide) {
             const uint64_t old = __hip_atomic_fetch_add(&c->arrive, 1ull + payload, __ATOMIC_ACQ_REL,
                                                         __HIP_MEMORY_SCOPE_AGENT);
             last = ((uint32_t)(old & kArriveCount) + 1 == m.M) ? 1u : 0u;
             b.sums = (old + 1ull + payload) >> kArriveCountBits;
+        } else {
+            const uint32_t old = __hip_atomic_fetch_add(arrive_lo(&c->arrive), 1u, __ATOMIC_ACQ_REL,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+            last = (old + 1 == m.M) ? 1u : 0u;
         }
         b.is_master = last;
-        if (b.is_master) __hip_atomic_store(&c->arrive, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (b.is_master) {
+            if (wide) __hip_atomic_store(&c->arrive, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else __hip_atomic_store(arrive_lo(&c->arrive), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
     __syncthreads();
     if (b.is_master) {

@@ -722,6 +722,7 @@ int coop_bfs(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_t
     a.first2 = g->first2;
     a.inline_on = (opts && (opts->flags & COOP_F_LEVEL_BARRIERS)) ? 0u : 1u;
     a.arrive_sums = arrive_sums_ok(g, opts);
+    if (a.arrive_sums) a.t.cfg.mode |= coop::kModeArriveSums;
     a.flist = a.inline_on ? static_cast<uint32_t*>(scratch_buf(h, (size_t)sz.grid * (coop::kFlWgHost + 1) * 4))
                           : nullptr;
     if (!a.vis || !a.fb[0] || !a.fb[1] || !a.fb[2] || (a.inline_on && !a.flist)) {
@@ -795,6 +796,7 @@ int coop_bfs_noalloc(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, 
     a.first2 = g->first2;
     a.inline_on = inline_on ? 1u : 0u;
     a.arrive_sums = arrive_sums_ok(g, opts);
+    if (a.arrive_sums) a.t.cfg.mode |= coop::kModeArriveSums;
     a.flist = inline_on ? reinterpret_cast<uint32_t*>(base + o_flist) : nullptr;
     // the array keeps the previous call's contents: the context and the
     // slots are cleared here, the bitmaps by the kernel's per-source init
