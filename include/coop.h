@@ -118,7 +118,9 @@ enum {
     COOP_F_SLOT_SUMS = 128u       /* BFS: the master step sums every workgroup's statistics slot
                                      for a level's counts; by default (graphs with n < 2^24 and
                                      fewer than 2^28 arcs) the counts come with the barrier
-                                     arrivals; the same result either way */
+                                     arrivals. SSSP: the master step reads per-XCD flags to learn
+                                     whether a round lowered a distance instead of a count on the
+                                     arrivals. The same result either way */
 };
 
 typedef struct coop_launch_opts {

@@ -144,6 +144,8 @@ struct SsspArgs {
     uint32_t words;            // bitmap words, multiple of 64
     int32_t* dist_out;         // nroots * out_stride (or n) distances, also the working state
     uint32_t* lowered;         // kMaxXcds flags 64 words apart: a workgroup on that XCD lowered a distance
+    uint32_t arrive_sums;      // 1: whether a round lowered anything comes with the barrier arrivals
+                               // (then the flags are not used)
 };
 
 struct ColorArgs {

@@ -120,11 +120,11 @@ __device__ __forceinline__ void sssp_body(const SsspArgs& p, bool joiner_grid) {
         const uint32_t id = coop_get_group_id(g), M = coop_get_num_groups(g);
         fresh = false;
         wg_trace(t.cfg, g.bar.member.epoch, id, kTrStart);
-        sssp_phase(p, sh, ph, cur_flags, p.dist_out + (size_t)root * t.out_stride, id, M);
+        const uint64_t pay = sssp_phase(p, sh, ph, cur_flags, p.dist_out + (size_t)root * t.out_stride, id, M);
         wg_trace(t.cfg, g.bar.member.epoch, id, kTrWorkDone);
         coop_resizing_global_barrier<Coop>(g, [&](uint32_t, uint32_t) -> uint32_t {
             return sssp_master(p, sh, c, ph, cur_flags, t.roots, p.dist_out);
-        });
+        }, pay);
         sssp_follow(ph, coop_flags(g), root);
     }
 }

@@ -829,6 +829,10 @@ int coop_sssp(coop_rt* rt, const coop_graph* g, const uint32_t* d_roots, uint32_
     for (int i = 0; i < 3; ++i) a.fb[i] = static_cast<uint32_t*>(scratch_buf(h, (size_t)a.words * 4));
     a.lowered = static_cast<uint32_t*>(scratch_buf(h, (size_t)coop::kMaxXcds * 256));
     a.dist_out = d_dist;
+    // whether a round lowered anything rides on the barrier arrivals (a count
+    // of workgroups: it cannot overflow)
+    a.arrive_sums = (opts && (opts->flags & COOP_F_SLOT_SUMS)) ? 0u : 1u;
+    if (a.arrive_sums) a.t.cfg.mode |= coop::kModeArriveSums;
     if (!a.fb[0] || !a.fb[1] || !a.fb[2] || !a.lowered) { handle_free(h); return COOP_E_OOM; }
     (void)hipEventRecord(h->ev_init, s);
     (void)hipEventRecord(h->ev_start, s);

@@ -1604,8 +1604,10 @@ struct SsspVisit {
 // in the current bitmap (one-word units) and clears the bitmap two rounds
 // ahead, HEAVY walks strips of heavy vertices. A workgroup that lowered any
 // distance raises the round's "next bitmap not empty" word.
-__device__ __forceinline__ void sssp_phase(const SsspArgs& p, BlockLds& sh, uint32_t ph, uint32_t flags,
-                                           int32_t* dist_i, uint32_t id, uint32_t M) {
+// Returns (thread 0) the workgroup's arrival payload when the launch takes
+// the round's outcome that way: 1 in the first sum if it lowered a distance.
+__device__ __forceinline__ uint64_t sssp_phase(const SsspArgs& p, BlockLds& sh, uint32_t ph, uint32_t flags,
+                                               int32_t* dist_i, uint32_t id, uint32_t M) {
     const TraversalArgs& t = p.t;
     Work* wk = t.work;
     const uint32_t nw = num_waves();
@@ -1617,6 +1619,7 @@ __device__ __forceinline__ void sssp_phase(const SsspArgs& p, BlockLds& sh, uint
     const uint32_t gw = wave_slot(id, M, nw);
     const uint32_t W = M * nw;
     Stats st;
+    uint64_t pay = 0;
     if (ph == kPhInit) {
         const uint32_t tid = id * blockDim.x + threadIdx.x, stride = M * blockDim.x;
         for (uint32_t i = tid; i < t.n; i += stride) dist[i] = 0x7FFFFFFFu;
@@ -1637,11 +1640,14 @@ __device__ __forceinline__ void sssp_phase(const SsspArgs& p, BlockLds& sh, uint
         stats_to_lds(sh, st);
         __syncthreads();
         // one flag per XCD: a single shared word took every workgroup's
-        // store in turn at the end of the round
-        if (threadIdx.x == 0 && sh.acc[0])
-            __hip_atomic_store(&p.lowered[xcc_id() * 64u], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // store in turn at the end of the round (or a count on the arrivals)
+        if (threadIdx.x == 0 && sh.acc[0]) {
+            if (p.arrive_sums) pay = arrive_payload(1u, 0u);
+            else __hip_atomic_store(&p.lowered[xcc_id() * 64u], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         acc_to_slot(sh, t.slots, id, false);
     }
+    return pay;
 }
 
 // SSSP master step: place the next source, switch a round to its HEAVY
@@ -1657,11 +1663,20 @@ __device__ __forceinline__ uint32_t sssp_master(const SsspArgs& p, BlockLds& sh,
         XferR x = wk->load_x();                 // one batch of loads
         const uint32_t hs = ld_relaxed(&wk->heavy_tail);
         uint32_t lw[kMaxXcds];
-#pragma unroll
-        for (uint32_t i = 0; i < kMaxXcds; ++i) lw[i] = ld_relaxed(&p.lowered[i * 64u]);
         uint32_t lowered = 0;
+        if (p.arrive_sums) {
+            // workgroups that lowered a distance in this phase, counted by
+            // the arrivals (a TD phase's count waits in lvl_found while its
+            // HEAVY phase runs)
 #pragma unroll
-        for (uint32_t i = 0; i < kMaxXcds; ++i) lowered |= lw[i];
+            for (uint32_t i = 0; i < kMaxXcds; ++i) lw[i] = 0;
+            lowered = sums_a(sh.bar.sums);
+        } else {
+#pragma unroll
+            for (uint32_t i = 0; i < kMaxXcds; ++i) lw[i] = ld_relaxed(&p.lowered[i * 64u]);
+#pragma unroll
+            for (uint32_t i = 0; i < kMaxXcds; ++i) lowered |= lw[i];
+        }
         const uint32_t r = (cur_flags & kRotMask) >> kRotShift;
         uint32_t res;
         if (ph == kPhStart) {
@@ -1686,6 +1701,7 @@ __device__ __forceinline__ uint32_t sssp_master(const SsspArgs& p, BlockLds& sh,
             x.in_size() = hs;
             wk->heavy_tail = 0;
             x.heavy_phases() += 1;
+            if (p.arrive_sums) x.lvl_found() = lowered;   // the HEAVY phase's master adds it
             res = (cur_flags & kRotMask) | kPhHeavy;
             if (hs > t.heavy_cap) {                     // the strip list overflowed
                 raise_error(c, kErrInternal);
@@ -1693,6 +1709,10 @@ __device__ __forceinline__ uint32_t sssp_master(const SsspArgs& p, BlockLds& sh,
             }
         } else {
             if (hs) wk->heavy_tail = 0;
+            if (p.arrive_sums) {
+                lowered += x.lvl_found();
+                x.lvl_found() = 0;
+            }
 #pragma unroll
             for (uint32_t i = 0; i < kMaxXcds; ++i)
                 if (lw[i]) p.lowered[i * 64u] = 0;
